@@ -1,0 +1,146 @@
+"""CPU oracle for the HPL hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may import
+this package.  The GPU library never imports, links or calls it, and this package
+never imports the GPU library.
+
+Thin ctypes wrappers over oracle/liboracle.so (plain C, fp64, see oracle.c for
+the passages of the paper each function follows).  Matrices are numpy float64
+arrays in Fortran (column-major) order; lda is taken from the array's strides.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        i64, u64, dbl = ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+        P = ctypes.c_void_p
+        L.oracle_splitmix64_at.restype = u64
+        L.oracle_splitmix64_at.argtypes = [u64, u64]
+        L.oracle_stream_key.restype = u64
+        L.oracle_stream_key.argtypes = [u64, u64]
+        L.oracle_uniform.restype = dbl
+        L.oracle_uniform.argtypes = [u64, u64]
+        L.oracle_gen.restype = None
+        L.oracle_gen.argtypes = [u64, u64, P, i64, i64, i64]
+        L.oracle_lu.restype = None
+        L.oracle_lu.argtypes = [P, i64, i64, P, P]
+        L.oracle_solve.restype = None
+        L.oracle_solve.argtypes = [P, P, P, i64, i64, i64, i64, ctypes.c_int]
+        L.oracle_residual.restype = None
+        L.oracle_residual.argtypes = [P, i64, i64, P, i64, P, i64, i64, P]
+        L.oracle_residual_gen.restype = None
+        L.oracle_residual_gen.argtypes = [u64, i64, P, i64, P, i64, i64, P]
+        L.oracle_det.restype = None
+        L.oracle_det.argtypes = [P, P, i64, i64, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _ld(a):
+    """Leading dimension of a Fortran-ordered 2-D float64 array (or 1-D vector)."""
+    if a.ndim == 1 or a.size == 0:
+        return max(1, a.shape[0])
+    assert a.strides[0] == a.itemsize, "matrix must be column-major (Fortran order)"
+    return max(1, a.strides[1] // a.itemsize, a.shape[0])
+
+
+def _check(a, dtype=np.float64):
+    assert isinstance(a, np.ndarray) and a.dtype == dtype
+    if a.ndim == 2 and a.size > 0:
+        assert a.strides[0] == a.itemsize, "matrix must be column-major (Fortran order)"
+    return a
+
+
+def splitmix64_at(s0: int, idx: int) -> int:
+    return int(lib().oracle_splitmix64_at(s0 & (2**64 - 1), idx & (2**64 - 1)))
+
+
+def stream_key(seed: int, stream: int) -> int:
+    return int(lib().oracle_stream_key(seed & (2**64 - 1), stream & (2**64 - 1)))
+
+
+def gen(seed: int, stream: int, rows: int, cols: int, ld: int = None) -> np.ndarray:
+    """rows x cols Fortran-ordered matrix (leading dimension ld >= rows) of the stream."""
+    ld = rows if ld is None else ld
+    buf = np.zeros((ld, cols), dtype=np.float64, order="F")
+    lib().oracle_gen(seed, stream, _ptr(buf), rows, cols, max(ld, 1))
+    return buf[:rows, :]
+
+
+def lu(A: np.ndarray):
+    """In-place LU with partial pivoting of a square column-major A; returns (ipiv, info)."""
+    _check(A)
+    n = A.shape[0]
+    assert A.shape[1] == n
+    ipiv = np.zeros(max(n, 1), dtype=np.int32)
+    info = ctypes.c_int64(0)
+    lib().oracle_lu(_ptr(A), n, _ld(A), _ptr(ipiv), ctypes.byref(info))
+    return ipiv[:n], int(info.value)
+
+
+def solve(LU: np.ndarray, ipiv: np.ndarray, B: np.ndarray, trans: int = 0):
+    """In-place solve A X = B (trans=0) or A^T X = B (trans=1) with the factors of A."""
+    _check(LU)
+    n = LU.shape[0]
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
+    if B.ndim == 1:
+        assert B.flags.c_contiguous and B.dtype == np.float64
+        nrhs, ldb = 1, max(n, 1)
+    else:
+        _check(B)
+        nrhs, ldb = B.shape[1], _ld(B)
+    lib().oracle_solve(_ptr(LU), _ptr(ipiv), _ptr(B), n, _ld(LU), nrhs, ldb, int(trans))
+    return B
+
+
+def residual(A, X, B):
+    """[scaled, ||r||inf, ||A||inf, ||x||inf, ||b||inf] for A X = B (A given)."""
+    _check(A)
+    n = A.shape[0]
+    X2 = X.reshape(n, -1, order="F") if X.ndim == 1 else X
+    B2 = B.reshape(n, -1, order="F") if B.ndim == 1 else B
+    out = np.zeros(5)
+    lib().oracle_residual(_ptr(A), n, _ld(A), _ptr(X2), _ld(X2), _ptr(B2), _ld(B2),
+                          X2.shape[1], _ptr(out))
+    return out
+
+
+def residual_gen(seed, n, X, B):
+    """Same as residual() with A regenerated from (seed, stream 0)."""
+    X2 = X.reshape(n, -1, order="F") if X.ndim == 1 else X
+    B2 = B.reshape(n, -1, order="F") if B.ndim == 1 else B
+    out = np.zeros(5)
+    lib().oracle_residual_gen(seed, n, _ptr(X2), _ld(X2), _ptr(B2), _ld(B2), X2.shape[1],
+                              _ptr(out))
+    return out
+
+
+def det(LU, ipiv):
+    """(sign, log2|det|, plain product) from the factors."""
+    n = LU.shape[0]
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
+    s, l2, ex = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().oracle_det(_ptr(LU), _ptr(ipiv), n, _ld(LU), ctypes.byref(s), ctypes.byref(l2),
+                     ctypes.byref(ex))
+    return s.value, l2.value, ex.value
+
+
+def uniform(s0: int, idx: int) -> float:
+    """Value of linear index idx of the stream whose SplitMix64 state is s0."""
+    return float(lib().oracle_uniform(s0 & (2**64 - 1), idx & (2**64 - 1)))

@@ -1,0 +1,264 @@
+/*
+ * oracle.c -- the CPU oracle for the HPL hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or constant generator with the GPU library
+ * (paper_2304_10397_amd/csrc), and the GPU library never calls it.
+ *
+ * What it computes (Chalmers, Kurzak, McDougall, Bauman, "Optimizing
+ * High-Performance Linpack for Exascale Accelerated Architectures"):
+ *   - Sec. II: a random N x N double-precision system A x = b is solved by
+ *     Gaussian elimination with partial pivoting, A = P L U, the system is
+ *     reduced to U x = L^{-1} P^{-1} b and x is found by applying U^{-1}.
+ *   - Sec. I (FACT, RS, UPDATE bullets) and Sec. II (phase descriptions): the
+ *     blocked method is a reordering of the same eliminations; the oracle is
+ *     the unblocked elimination, one column at a time, in the paper's order
+ *     (find pivot, interchange rows, scale, update the trailing matrix).
+ *   - The HPL acceptance test (scaled residual < 16) is not printed in the
+ *     paper; its formula is the standard HPL one, written out in
+ *     oracle_residual below.
+ *
+ * Precision: IEEE fp64 throughout (the paper's double precision), compiled
+ * with -ffp-contract=off so every a*b+c is two correctly rounded operations.
+ *
+ * Parity pins (what ties this file to something other than itself) live in
+ * tests/test_oracle_*.py: Leibniz and Bareiss determinants, exact dyadic
+ * factorizations, integer systems with known solutions, special matrices,
+ * LAPACK (scipy) as an independent opinion, and the published SplitMix64
+ * output sequence for the generator.
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <math.h>
+#include <string.h>
+
+#define IDX(i, j, ld) ((size_t)(i) + (size_t)(j) * (size_t)(ld))
+
+/* ------------------------------------------------------------------------ */
+/* Input generator.                                                          */
+/*                                                                           */
+/* The paper only says the matrix is random (Sec. I, Sec. II).  The reading  */
+/* used here: entries i.i.d. uniform on [-0.5, 0.5), drawn from SplitMix64   */
+/* (Steele, Lea, Flood, "Fast splittable pseudorandom number generators",    */
+/* OOPSLA 2014) used as a counter-based generator: the value at linear       */
+/* index idx of a stream is the idx-th output of a SplitMix64 sequence,      */
+/* i.e. mix64(s0 + (idx + 1) * GAMMA), so any element can be produced on its */
+/* own.  s0 for (seed, stream) is the first SplitMix64 output of the state   */
+/* seed + stream * STREAM_STRIDE.                                            */
+/* ------------------------------------------------------------------------ */
+static const uint64_t GAMMA = 0x9E3779B97F4A7C15ull;         /* SplitMix64 increment */
+static const uint64_t STREAM_STRIDE = 0xD1B54A32D192ED03ull; /* odd, separates streams */
+
+static uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* idx-th output (idx = 0, 1, ...) of the SplitMix64 sequence with state s0. */
+uint64_t oracle_splitmix64_at(uint64_t s0, uint64_t idx)
+{
+    return mix64(s0 + (idx + 1ull) * GAMMA);
+}
+
+uint64_t oracle_stream_key(uint64_t seed, uint64_t stream)
+{
+    return oracle_splitmix64_at(seed + stream * STREAM_STRIDE, 0);
+}
+
+/* 53 high bits -> [0,1) -> shift to [-0.5, 0.5); every step is exact. */
+double oracle_uniform(uint64_t s0, uint64_t idx)
+{
+    uint64_t h = oracle_splitmix64_at(s0, idx);
+    double u = (double)(h >> 11) * (1.0 / 9007199254740992.0); /* 2^-53 */
+    return u - 0.5;
+}
+
+/* M[i + j*ld] = value of linear index i + j*rows of stream (seed, stream). */
+void oracle_gen(uint64_t seed, uint64_t stream, double *M, int64_t rows, int64_t cols, int64_t ld)
+{
+    uint64_t s0 = oracle_stream_key(seed, stream);
+    for (int64_t j = 0; j < cols; ++j)
+        for (int64_t i = 0; i < rows; ++i)
+            M[IDX(i, j, ld)] = oracle_uniform(s0, (uint64_t)i + (uint64_t)j * (uint64_t)rows);
+}
+
+/* ------------------------------------------------------------------------ */
+/* LU factorization with partial pivoting, unblocked, right-looking.         */
+/*                                                                           */
+/* Column k: (1) the pivot is the row of largest |a_ik|, i >= k, the first   */
+/* such row on ties; (2) rows k and p are interchanged across all n columns  */
+/* (so L ends up with every later interchange applied: P A = L U with        */
+/* P = S_{n-1} ... S_0, S_k swapping rows k and ipiv[k]); (3) the entries    */
+/* below the diagonal are divided by the pivot; (4) the trailing matrix gets */
+/* the rank-1 update a_ij -= l_ik * u_kj.  A zero pivot column leaves the     */
+/* column untouched and records info = k + 1 for the first such k.           */
+/* ipiv is 0-based.                                                          */
+/* ------------------------------------------------------------------------ */
+void oracle_lu(double *A, int64_t n, int64_t lda, int32_t *ipiv, int64_t *info)
+{
+    *info = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t p = k;
+        double amax = fabs(A[IDX(k, k, lda)]);
+        for (int64_t i = k + 1; i < n; ++i) {
+            double v = fabs(A[IDX(i, k, lda)]);
+            if (v > amax) { amax = v; p = i; }
+        }
+        ipiv[k] = (int32_t)p;
+        if (amax == 0.0) {
+            if (*info == 0) *info = k + 1;
+            continue;
+        }
+        if (p != k) {
+            for (int64_t j = 0; j < n; ++j) {
+                double t = A[IDX(k, j, lda)];
+                A[IDX(k, j, lda)] = A[IDX(p, j, lda)];
+                A[IDX(p, j, lda)] = t;
+            }
+        }
+        double piv = A[IDX(k, k, lda)];
+        for (int64_t i = k + 1; i < n; ++i)
+            A[IDX(i, k, lda)] = A[IDX(i, k, lda)] / piv;
+        for (int64_t j = k + 1; j < n; ++j) {
+            double ukj = A[IDX(k, j, lda)];
+            for (int64_t i = k + 1; i < n; ++i)
+                A[IDX(i, j, lda)] = A[IDX(i, j, lda)] - A[IDX(i, k, lda)] * ukj;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Solve with the factors (Sec. II: U x = L^{-1} P b, then x = U^{-1} ...).  */
+/* trans = 0: A X = B.  Interchanges applied in order k = 0..n-1, forward    */
+/*            substitution with unit L, back substitution with U.            */
+/* trans = 1: A^T X = B.  Since A = P^T L U, A^T = U^T L^T P: forward with   */
+/*            U^T, backward with unit L^T, interchanges in reverse order.    */
+/* ------------------------------------------------------------------------ */
+void oracle_solve(const double *LU, const int32_t *ipiv, double *B, int64_t n, int64_t lda,
+                  int64_t nrhs, int64_t ldb, int trans)
+{
+    for (int64_t c = 0; c < nrhs; ++c) {
+        double *b = B + (size_t)c * (size_t)ldb;
+        if (trans == 0) {
+            for (int64_t k = 0; k < n; ++k) {
+                int64_t p = ipiv[k];
+                if (p != k) { double t = b[k]; b[k] = b[p]; b[p] = t; }
+            }
+            for (int64_t i = 0; i < n; ++i) {
+                double s = b[i];
+                for (int64_t j = 0; j < i; ++j) s = s - LU[IDX(i, j, lda)] * b[j];
+                b[i] = s;
+            }
+            for (int64_t i = n - 1; i >= 0; --i) {
+                double s = b[i];
+                for (int64_t j = i + 1; j < n; ++j) s = s - LU[IDX(i, j, lda)] * b[j];
+                b[i] = s / LU[IDX(i, i, lda)];
+            }
+        } else {
+            /* U^T z = b: (U^T)_{ij} = u_ji, lower triangular with diagonal u_ii */
+            for (int64_t i = 0; i < n; ++i) {
+                double s = b[i];
+                for (int64_t j = 0; j < i; ++j) s = s - LU[IDX(j, i, lda)] * b[j];
+                b[i] = s / LU[IDX(i, i, lda)];
+            }
+            /* L^T w = z: (L^T)_{ij} = l_ji, unit upper triangular */
+            for (int64_t i = n - 1; i >= 0; --i) {
+                double s = b[i];
+                for (int64_t j = i + 1; j < n; ++j) s = s - LU[IDX(j, i, lda)] * b[j];
+                b[i] = s;
+            }
+            for (int64_t k = n - 1; k >= 0; --k) {
+                int64_t p = ipiv[k];
+                if (p != k) { double t = b[k]; b[k] = b[p]; b[p] = t; }
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* HPL scaled residual: ||A x - b||_inf / (eps * (||A||_inf ||x||_inf +      */
+/* ||b||_inf) * n), eps = 2^-53 (unit roundoff of fp64).  out[5] =           */
+/* {scaled, ||r||_inf, ||A||_inf, ||x||_inf, ||b||_inf}; with several right- */
+/* hand sides out[0] is the largest per-column scaled residual and out[1],   */
+/* out[3], out[4] the largest per-column norms.                              */
+/* The matrix is either given (A != NULL) or regenerated from (seed, 0).     */
+/* ------------------------------------------------------------------------ */
+static void residual_impl(const double *A, int64_t lda, int gen, uint64_t seed, int64_t n,
+                          const double *X, int64_t ldx, const double *B, int64_t ldb,
+                          int64_t nrhs, double *out)
+{
+    const double eps = 1.0 / 9007199254740992.0;
+    uint64_t s0 = gen ? oracle_stream_key(seed, 0) : 0;
+    double anorm = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double rs = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double a = gen ? oracle_uniform(s0, (uint64_t)i + (uint64_t)j * (uint64_t)n)
+                           : A[IDX(i, j, lda)];
+            rs = rs + fabs(a);
+        }
+        if (!(rs <= anorm)) anorm = rs; /* NaN propagates */
+    }
+    double worst = 0.0, rmax = 0.0, xmax = 0.0, bmax = 0.0;
+    for (int64_t c = 0; c < nrhs; ++c) {
+        const double *x = X + (size_t)c * (size_t)ldx;
+        const double *b = B + (size_t)c * (size_t)ldb;
+        double rn = 0.0, xn = 0.0, bn = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                double a = gen ? oracle_uniform(s0, (uint64_t)i + (uint64_t)j * (uint64_t)n)
+                               : A[IDX(i, j, lda)];
+                s = s + a * x[j];
+            }
+            double r = fabs(s - b[i]);
+            if (!(r <= rn)) rn = r;
+            if (!(fabs(x[i]) <= xn)) xn = fabs(x[i]);
+            if (!(fabs(b[i]) <= bn)) bn = fabs(b[i]);
+        }
+        double scaled = rn / (eps * (anorm * xn + bn) * (double)n);
+        if (!(scaled <= worst)) worst = scaled;
+        if (!(rn <= rmax)) rmax = rn;
+        if (!(xn <= xmax)) xmax = xn;
+        if (!(bn <= bmax)) bmax = bn;
+    }
+    out[0] = worst; out[1] = rmax; out[2] = anorm; out[3] = xmax; out[4] = bmax;
+}
+
+void oracle_residual(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx,
+                     const double *B, int64_t ldb, int64_t nrhs, double *out)
+{
+    residual_impl(A, lda, 0, 0, n, X, ldx, B, ldb, nrhs, out);
+}
+
+void oracle_residual_gen(uint64_t seed, int64_t n, const double *X, int64_t ldx,
+                         const double *B, int64_t ldb, int64_t nrhs, double *out)
+{
+    residual_impl(NULL, 0, 1, seed, n, X, ldx, B, ldb, nrhs, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Determinant from the factors: det A = (-1)^s * prod u_kk, s = number of   */
+/* k with ipiv[k] != k (each is one interchange).  Returned as sign, and the */
+/* sum of log2 |u_kk| so that large n does not overflow; *exact holds the    */
+/* plain product when it is finite.                                          */
+/* ------------------------------------------------------------------------ */
+void oracle_det(const double *LU, const int32_t *ipiv, int64_t n, int64_t lda,
+                double *sign, double *log2abs, double *exact)
+{
+    double s = 1.0, l2 = 0.0, prod = 1.0;
+    for (int64_t k = 0; k < n; ++k) {
+        double u = LU[IDX(k, k, lda)];
+        if (ipiv[k] != k) s = -s;      /* one interchange */
+        if (u < 0) s = -s;
+        l2 += log2(fabs(u));
+        prod = prod * u;
+    }
+    *sign = s;
+    *log2abs = l2;
+    *exact = s * fabs(prod);
+}
