@@ -1,0 +1,177 @@
+/*
+ * hpl.h -- C ABI of libhplx: the High-Performance Linpack hot path on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method (Chalmers, Kurzak, McDougall, Bauman, "Optimizing
+ * High-Performance Linpack for Exascale Accelerated Architectures"):
+ * a random dense N x N double-precision system A x = b is solved by blocked
+ * Gaussian elimination with partial pivoting (Sec. I, Sec. II).  Each
+ * iteration along the diagonal factors an NB-column panel with pivoting
+ * inside the panel (FACT), applies the panel's NB interchanges to the rest of
+ * the matrix (RS), solves for the U block row with the unit-lower diagonal
+ * block (DTRSM) and applies the rank-NB update to the trailing matrix (DGEMM)
+ * (Sec. I bullets, Sec. II).  A look-ahead updates the next panel's columns
+ * first so that the next FACT overlaps the rest of the update (Sec. III).
+ * With A = P L U, A x = b becomes U x = L^{-1} P^{-1} b, solved by applying
+ * U^{-1} (Sec. II).
+ *
+ * Conventions shared by every entry point
+ *   - All matrices are FP64, column-major: element (i, j) of a matrix with
+ *     leading dimension ld is at ptr[i + j*ld].  Sizes and leading dimensions
+ *     are int64_t; offsets are computed in 64 bits (N^2 exceeds 2^31).
+ *   - Matrix and pivot pointers are DEVICE pointers, allocated and owned by
+ *     the caller.  Output arrays documented as host arrays (info, out) are
+ *     host pointers.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  Work is ordered
+ *     on that stream; the library may use internal streams for the
+ *     look-ahead and joins them back before returning.  Every entry point
+ *     returns after its work on the device has completed.
+ *   - Return value: 0 on success; -k if argument k (1-based) is invalid,
+ *     detected on the host before any HIP call; a positive HPL_ERR_* code on a
+ *     runtime failure (hpl_strerror gives text, hpl_last_error_detail the
+ *     failing call).  Nothing is modified when -k is returned.
+ *   - The library allocates only workspace (never O(n^2)), once per device,
+ *     lazily on first use; hpl_release frees it.  Calls on one device must not
+ *     overlap in time (the workspace is shared); the library is not
+ *     re-entrant per device.
+ *   - The library loads on a machine without a GPU; argument validation and
+ *     hpl_strerror / hpl_set_option / hpl_get_option work there.
+ */
+#ifndef HPLX_HPL_H
+#define HPLX_HPL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum hpl_status {
+    HPL_OK = 0,
+    HPL_ERR_HIP = 1,      /* a HIP runtime call failed (see hpl_last_error_detail) */
+    HPL_ERR_NOMEM = 2,    /* workspace allocation failed */
+    HPL_ERR_DEVICE = 3,   /* no device, or the current device is not gfx950 */
+    HPL_ERR_INTERNAL = 4  /* a kernel reported failure (e.g. panel barrier time-out) */
+};
+
+/*
+ * hpl_factor -- LU factorization with partial pivoting, P A = L U
+ * (Sec. I FACT/RS/UPDATE, Sec. II, Sec. III look-ahead).
+ *   1 A     device, n x n at leading dimension lda; overwritten by L (unit
+ *           diagonal not stored) below the diagonal and U on and above it.
+ *   2 n     order, 0 <= n <= 2^31 - 1 (n = 0 returns at once).
+ *   3 lda   leading dimension, lda >= max(1, n).
+ *   4 nb    block size (panel width), 1 <= nb <= 1024.
+ *   5 ipiv  device int32[n]: 0-based, row k was interchanged with row
+ *           ipiv[k] >= k, interchanges applied in the order k = 0..n-1 and
+ *           across all n columns (LAPACK getrf form: P = S_{n-1}...S_0).
+ *   6 info  host int64*: 0, or k + 1 for the first k with U(k,k) exactly 0 (the
+ *           pivot column was all zero); the factorization still completes and
+ *           that column is left unscaled.
+ *   7 hip_stream
+ * The pivot is the row of largest |a| in the column, the lowest row index on
+ * ties, so results do not depend on the reduction order.  Look-ahead on or
+ * off (hpl_set_option) gives bit-identical results.
+ */
+int hpl_factor(double *A, int64_t n, int64_t lda, int64_t nb, int32_t *ipiv, int64_t *info,
+               void *hip_stream);
+
+/*
+ * hpl_solve -- solve with the factors of hpl_factor (Sec. II: apply P, then
+ * L^{-1}, then U^{-1}).
+ *   1 LU    device, n x n at lda, as returned by hpl_factor (not modified).
+ *   2 ipiv  device int32[n] from hpl_factor.
+ *   3 B     device, n x nrhs at ldb; overwritten by the solution X.
+ *   4 nrhs  number of right-hand sides, >= 0.
+ *   5 n     order, >= 0.
+ *   6 lda   >= max(1, n).
+ *   7 ldb   >= max(1, n).
+ *   8 trans 0: A X = B.  1: A^T X = B (U^T forward, L^T backward, then the
+ *           interchanges in reverse order).
+ *   9 hip_stream
+ * LU and B must not overlap.  A zero diagonal of U yields inf/NaN in X (no
+ * check), as the factorization's info reported.
+ */
+int hpl_solve(const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, int64_t n,
+              int64_t lda, int64_t ldb, int trans, void *hip_stream);
+
+/*
+ * hpl_residual -- HPL acceptance test for A X = B with an explicit A.
+ *   1 A0 device n x n at lda (the original matrix); 2 n; 3 lda >= max(1,n);
+ *   4 X device n x nrhs at ldx; 5 ldx >= max(1,n); 6 B device n x nrhs at ldb;
+ *   7 ldb >= max(1,n); 8 nrhs >= 1;
+ *   9 out host double[5] = {scaled, ||A X - B||inf, ||A||inf, ||X||inf, ||B||inf},
+ *     scaled = ||r||inf / (eps (||A||inf ||x||inf + ||b||inf) n), eps = 2^-53,
+ *     computed per column; out[0] is the largest per-column scaled residual
+ *     and out[1], out[3], out[4] the largest per-column norms.  The run
+ *     passes when out[0] < 16.  NaN anywhere propagates to out[0].
+ *  10 hip_stream
+ */
+int hpl_residual(const double *A0, int64_t n, int64_t lda, const double *X, int64_t ldx,
+                 const double *B, int64_t ldb, int64_t nrhs, double *out, void *hip_stream);
+
+/*
+ * hpl_residual_gen -- as hpl_residual, with A regenerated on the fly from
+ * (seed, stream 0) of hpl_generate instead of being read (at N = 163840 the
+ * original A cannot be kept next to its factors).
+ *   1 seed; 2 n >= 0; 3 X device; 4 ldx; 5 B device; 6 ldb; 7 nrhs >= 1;
+ *   8 out host double[5]; 9 hip_stream.
+ */
+int hpl_residual_gen(uint64_t seed, int64_t n, const double *X, int64_t ldx, const double *B,
+                     int64_t ldb, int64_t nrhs, double *out, void *hip_stream);
+
+/*
+ * hpl_generate -- the random system (Sec. II: the benchmark generates a random
+ * N x N matrix and right-hand side).  Entries are i.i.d. uniform on
+ * [-0.5, 0.5): the value at linear index idx = i + j*rows is the idx-th
+ * output of a SplitMix64 sequence (Steele, Lea, Flood, OOPSLA 2014) whose
+ * state is the first SplitMix64 output of seed + stream_id * 0xD1B54A32D192ED03,
+ * mapped as (h >> 11) * 2^-53 - 0.5 (exact).  Stream 0 is A, stream 1 is b.
+ *   1 seed; 2 stream_id; 3 M device rows x cols at ld (written);
+ *   4 rows >= 0; 5 cols >= 0; 6 ld >= max(1, rows); 7 hip_stream.
+ */
+int hpl_generate(uint64_t seed, uint64_t stream_id, double *M, int64_t rows, int64_t cols,
+                 int64_t ld, void *hip_stream);
+
+/* Options (process-wide, read at the start of each call). */
+enum hpl_option {
+    HPL_OPT_LOOKAHEAD = 1,   /* 0 or 1 (default 1): depth of the panel look-ahead */
+    HPL_OPT_PANEL_BASE = 2,  /* leaf width of the recursive panel: 8, 16, 32 or 64 (default 32) */
+    HPL_OPT_PANEL_WGS = 3,   /* max workgroups of the panel leaf kernel, 1..256 (default 64) */
+    HPL_OPT_TIMING = 4,      /* 1: time every kernel with HIP events (see hpl_get_stats) */
+    HPL_OPT_PROGRESS = 5,    /* k > 0: print a progress line to stderr every k panels */
+    HPL_OPT_SERIALIZE = 6,   /* 1: run every step on one stream (debug; bit-identical) */
+    HPL_OPT_GEMM_TILE = 7    /* trailing-update GEMM tile variant id (default 0 = auto) */
+};
+/* Returns 0, or -1 (bad key) / -2 (bad value); the option is unchanged on error. */
+int hpl_set_option(int key, int64_t value);
+/* Current value of an option, or INT64_MIN for an unknown key. */
+int64_t hpl_get_option(int key);
+
+/*
+ * Per-kernel-class statistics of the calls made since the last
+ * hpl_reset_stats, collected while HPL_OPT_TIMING is 1.  Entry k of the
+ * arrays describes class k: 0 trailing GEMM, 1 panel (recursive FACT, all of
+ * its kernels), 2 laswp, 3 trsm, 4 solve, 5 panel-internal GEMM.  For each
+ * class: launches[k], total device milliseconds ms[k] (sum of HIP-event
+ * intervals around each launch on the stream it ran on) and algorithmic
+ * flops[k] and bytes[k] (the method's own operation and HBM byte counts).
+ * Arrays are host arrays of length cap; returns the number of classes.
+ */
+int hpl_get_stats(int64_t *launches, double *ms, double *flops, double *bytes, int cap);
+void hpl_reset_stats(void);
+
+/* Frees the per-device workspace, streams and events.  Returns 0 or HPL_ERR_HIP. */
+int hpl_release(void);
+
+/* Static text for a return code (negative codes name the argument position). */
+const char *hpl_strerror(int code);
+
+/* Text describing the last runtime failure in this process (HIP call, file, line). */
+const char *hpl_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPLX_HPL_H */

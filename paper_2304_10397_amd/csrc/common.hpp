@@ -1,0 +1,141 @@
+// common.hpp -- internal declarations shared by the libhplx translation units.
+//
+// Every kernel here is written for gfx950 (CDNA4): 64-wide wavefronts, FP64
+// MFMA (v_mfma_f64_16x16x4_f64), 160 KB of LDS per CU.  Matrices are FP64,
+// column-major, 64-bit offsets.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "hpl.h"
+
+namespace hplx {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// 64-bit element offset of (i, j) in a column-major matrix.
+__host__ __device__ __forceinline__ size_t off(int64_t i, int64_t j, int64_t ld)
+{
+    return (size_t)i + (size_t)j * (size_t)ld;
+}
+
+// ---------------------------------------------------------------------------
+// Error plumbing (host).
+// ---------------------------------------------------------------------------
+void note_hip_error(hipError_t e, const char *what, const char *file, int line);
+void note_error(const char *what, const char *file, int line);
+
+#define HPLX_TRY(call)                                                         \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess) {                                                \
+            ::hplx::note_hip_error(e_, #call, __FILE__, __LINE__);             \
+            return HPL_ERR_HIP;                                                \
+        }                                                                      \
+    } while (0)
+
+#define HPLX_TRY_LAUNCH()  HPLX_TRY(hipGetLastError())
+
+#define HPLX_PROPAGATE(expr)                                                   \
+    do {                                                                       \
+        int rc_ = (expr);                                                      \
+        if (rc_ != HPL_OK) return rc_;                                         \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Random input generator: counter-based SplitMix64 (Steele, Lea, Flood 2014).
+// ---------------------------------------------------------------------------
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kStreamStride = 0xD1B54A32D192ED03ull;
+
+__host__ __device__ __forceinline__ uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// SplitMix64 state of (seed, stream): first output of state seed + stream*stride.
+__host__ __device__ __forceinline__ uint64_t stream_state(uint64_t seed, uint64_t stream)
+{
+    return sm64_mix(seed + stream * kStreamStride + kGamma);
+}
+
+// Value at linear index idx: idx-th SplitMix64 output, top 53 bits -> [-0.5, 0.5).
+__host__ __device__ __forceinline__ double gen_value(uint64_t s0, uint64_t idx)
+{
+    uint64_t h = sm64_mix(s0 + (idx + 1ull) * kGamma);
+    return (double)(h >> 11) * 0x1.0p-53 - 0.5;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (each returns HPL_OK or an HPL_ERR_* after noting the cause).
+// ---------------------------------------------------------------------------
+
+// gen.hip
+int launch_generate(uint64_t s0, double *M, int64_t rows, int64_t cols, int64_t ld,
+                    hipStream_t st);
+// Residual partials: result slots (uint64 bit patterns of non-negative doubles,
+// combined with atomicMax): red[0] = ||A||inf, then per rhs c: red[1+3c+0] =
+// ||r_c||inf, red[1+3c+1] = ||x_c||inf, red[1+3c+2] = ||b_c||inf.  red must be
+// zeroed first.
+int launch_residual(const double *A, int64_t lda, bool gen, uint64_t s0, int64_t n,
+                    const double *X, int64_t ldx, const double *B, int64_t ldb, int64_t nrhs,
+                    unsigned long long *red, hipStream_t st);
+int launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v, hipStream_t st);
+
+// gemm.hip: C(m x n) -= A(m x k) * B(k x n).
+int launch_gemm_sub(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda,
+                    const double *B, int64_t ldb, double *C, int64_t ldc, int variant,
+                    hipStream_t st);
+
+// trsm.hip: B(nbk x ncols) <- L^{-1} B, L unit lower nbk x nbk (nbk <= 512).
+int launch_trsm_llnu(const double *L, int64_t ldl, double *B, int64_t ldb, int64_t nbk,
+                     int64_t ncols, hipStream_t st);
+
+// laswp.hip
+// Interchanges k = 0..cnt-1: row r0+k <-> ipiv[k] (global rows, ipiv[k] >= r0+k),
+// cnt <= kMaxSwaps, composed into a permutation of the touched rows.  Output
+// "slot list": nslots, rows[s] (global rows), srcslot[s]: after the
+// interchanges, row rows[s] holds what row rows[srcslot[s]] held before.
+constexpr int kMaxSwaps = 512;
+struct SwapPlan {
+    int32_t *rows;     // [2*kMaxSwaps]
+    int32_t *srcslot;  // [2*kMaxSwaps]
+    int32_t *nslots;   // [1]
+    int *err;          // set to 1 (never cleared by the kernel) if a pivot lies outside [r0+k, nrows)
+};
+int launch_swap_plan(const int32_t *ipiv, int cnt, int64_t r0, int64_t nrows, bool reverse, SwapPlan plan,
+                     hipStream_t st);
+// Applies a plan to columns [col0, col0+ncols) of A.
+int launch_laswp(double *A, int64_t lda, int64_t col0, int64_t ncols, SwapPlan plan,
+                 hipStream_t st);
+
+// panel.hip: leaf of the recursive panel factorization.
+struct LeafSync {
+    unsigned long long *counter;  // monotonic barrier counter
+    int *abort_flag;              // set on barrier time-out
+    double *slots;                // [2][kLeafMaxWGs][kLeafSlot]
+    double *top;                  // [2][kLeafMaxW]
+    unsigned long long *info;     // min over singular columns of (global col + 1)
+};
+constexpr int kLeafMaxW = 64;
+constexpr int kLeafMaxWGs = 256;
+constexpr int kLeafSlot = kLeafMaxW + 2;
+int launch_panel_leaf(double *A, int64_t lda, int64_t c, int64_t m, int w, int32_t *ipiv,
+                      LeafSync sync, unsigned long long bar_base, int G, hipStream_t st);
+// Number of workgroups the leaf kernel uses for m rows, width w, limit gmax.
+int leaf_groups(int64_t m, int w, int gmax);
+
+// solve.hip
+int launch_trsv_block(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs,
+                      int64_t r0, int64_t bs, int mode, hipStream_t st);
+int launch_gemv_update(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs,
+                       int64_t r0, int64_t bs, int64_t row_begin, int64_t row_end, int mode,
+                       hipStream_t st);
+// mode: 0 = L unit lower (forward), 1 = U upper (backward), 2 = U^T (forward),
+//       3 = L^T unit (backward)
+
+}  // namespace hplx

@@ -1,0 +1,754 @@
+// driver.hip -- host side of libhplx: argument checks, per-device workspace,
+// the blocked right-looking factorization with look-ahead, the solves, the
+// residual and the generator entry points of hpl.h.
+//
+// Factorization loop (Sec. I / Sec. II: FACT -> RS -> UPDATE per NB-column
+// panel along the diagonal; Sec. III: look-ahead).  With look-ahead on, panel
+// j+1 is factored on the panel stream while the update of panel j on the
+// caller's stream finishes the columns to the right of it:
+//
+//   update stream U                          panel stream P
+//   wait panel j done
+//   RS + TRSM + GEMM on panel j+1's columns  .
+//   record "look-ahead done"  -------------> wait, FACT panel j+1, its plan
+//   RS + TRSM + GEMM on the remaining cols   (runs concurrently)
+//   RS on the columns left of panel j        record "panel j+1 done"
+//
+// One GPU holds the whole matrix, so the paper's LBCAST and the MPI parts of
+// RS disappear: the panel's L stays in place and RS is an in-place row
+// interchange.  Every element sees the same operations in the same order with
+// and without look-ahead, so both give identical bits.
+#include "common.hpp"
+
+#include <atomic>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+namespace hplx {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static std::mutex g_err_mu;
+static char g_err_detail[512] = "no error";
+
+void note_hip_error(hipError_t e, const char *what, const char *file, int line)
+{
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    snprintf(g_err_detail, sizeof g_err_detail, "%s failed: %s (%d) at %s:%d", what, hipGetErrorString(e), (int)e,
+             file, line);
+}
+
+void note_error(const char *what, const char *file, int line)
+{
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    snprintf(g_err_detail, sizeof g_err_detail, "%s at %s:%d", what, file, line);
+}
+
+#define HPLX_FAIL(code, what)                                                                                    \
+    do {                                                                                                          \
+        note_error(what, __FILE__, __LINE__);                                                                     \
+        return (code);                                                                                            \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// options
+// ---------------------------------------------------------------------------
+static std::atomic<int64_t> opt_lookahead{1};
+static std::atomic<int64_t> opt_panel_base{32};
+static std::atomic<int64_t> opt_panel_wgs{128};
+static std::atomic<int64_t> opt_timing{0};
+static std::atomic<int64_t> opt_progress{0};
+static std::atomic<int64_t> opt_serialize{0};
+static std::atomic<int64_t> opt_gemm_tile{0};
+
+// ---------------------------------------------------------------------------
+// statistics (HPL_OPT_TIMING)
+// ---------------------------------------------------------------------------
+enum { ST_GEMM = 0, ST_PANEL = 1, ST_LASWP = 2, ST_TRSM = 3, ST_SOLVE = 4, ST_PLAN = 5, ST_N = 6 };
+static std::mutex g_st_mu;
+static int64_t g_st_launch[ST_N];
+static double g_st_ms[ST_N], g_st_flops[ST_N], g_st_bytes[ST_N];
+
+struct TimedRec {
+    int cls;
+    hipEvent_t e0, e1;
+    double flops, bytes;
+};
+
+struct Device;
+
+// A per-call list of event pairs, resolved after the call's final synchronize.
+class Timer {
+  public:
+    explicit Timer(Device *d, bool on) : d_(d), on_(on) {}
+    bool on() const { return on_; }
+    int begin(int cls, hipStream_t st);
+    int end(int id, hipStream_t st, double flops, double bytes);
+    int collect();
+    ~Timer();
+
+  private:
+    Device *d_;
+    bool on_;
+    std::vector<TimedRec> recs_;
+};
+
+// ---------------------------------------------------------------------------
+// per-device state
+// ---------------------------------------------------------------------------
+constexpr int kRing = 4;        // panels in flight (plans and events are reused modulo kRing)
+constexpr int kMaxChunks = 2;   // nb <= 1024 = 2 x kMaxSwaps
+constexpr int kMaxDevices = 64;
+
+struct Device {
+    bool ready = false;
+    int id = -1;
+    hipStream_t sp = nullptr;  // panel stream (non-blocking)
+    hipEvent_t ev_start = nullptr, ev_end = nullptr;
+    hipEvent_t ev_panel[kRing] = {}, ev_la[kRing] = {}, ev_iter[kRing] = {};
+    void *ws = nullptr;
+    LeafSync sync{};
+    unsigned long long bar_epoch = 0;
+    SwapPlan ring[kRing][kMaxChunks]{};
+    SwapPlan pint{};  // plans inside the recursive panel
+    SwapPlan psolve{};
+    unsigned long long *red = nullptr;
+    int64_t red_cap = 0;
+    unsigned long long *hbuf = nullptr;  // pinned host staging
+    int *pivot_err = nullptr;            // raised by the plan kernel on an out-of-range pivot
+    std::vector<hipEvent_t> ev_pool;      // timing events
+};
+
+static std::mutex g_dev_mu;
+static Device g_dev[kMaxDevices];
+
+int Timer::begin(int cls, hipStream_t st)
+{
+    if (!on_) return -1;
+    TimedRec r{cls, nullptr, nullptr, 0, 0};
+    for (hipEvent_t *e : {&r.e0, &r.e1}) {
+        if (!d_->ev_pool.empty()) {
+            *e = d_->ev_pool.back();
+            d_->ev_pool.pop_back();
+        } else if (hipEventCreate(e) != hipSuccess) {
+            return -1;
+        }
+    }
+    if (hipEventRecord(r.e0, st) != hipSuccess) return -1;
+    recs_.push_back(r);
+    return (int)recs_.size() - 1;
+}
+
+int Timer::end(int id, hipStream_t st, double flops, double bytes)
+{
+    if (!on_ || id < 0) return HPL_OK;
+    recs_[id].flops = flops;
+    recs_[id].bytes = bytes;
+    HPLX_TRY(hipEventRecord(recs_[id].e1, st));
+    return HPL_OK;
+}
+
+int Timer::collect()
+{
+    if (!on_) return HPL_OK;
+    std::lock_guard<std::mutex> lk(g_st_mu);
+    for (auto &r : recs_) {
+        float ms = 0.f;
+        HPLX_TRY(hipEventElapsedTime(&ms, r.e0, r.e1));
+        g_st_launch[r.cls] += 1;
+        g_st_ms[r.cls] += ms;
+        g_st_flops[r.cls] += r.flops;
+        g_st_bytes[r.cls] += r.bytes;
+    }
+    return HPL_OK;
+}
+
+Timer::~Timer()
+{
+    for (auto &r : recs_) {
+        d_->ev_pool.push_back(r.e0);
+        d_->ev_pool.push_back(r.e1);
+    }
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static int init_device(Device &d, int id)
+{
+    hipDeviceProp_t prop;
+    HPLX_TRY(hipGetDeviceProperties(&prop, id));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) HPLX_FAIL(HPL_ERR_DEVICE, "device is not gfx950");
+    HPLX_TRY(hipStreamCreateWithFlags(&d.sp, hipStreamNonBlocking));
+    HPLX_TRY(hipEventCreateWithFlags(&d.ev_start, hipEventDisableTiming));
+    HPLX_TRY(hipEventCreateWithFlags(&d.ev_end, hipEventDisableTiming));
+    for (int i = 0; i < kRing; ++i) {
+        HPLX_TRY(hipEventCreateWithFlags(&d.ev_panel[i], hipEventDisableTiming));
+        HPLX_TRY(hipEventCreateWithFlags(&d.ev_la[i], hipEventDisableTiming));
+        HPLX_TRY(hipEventCreateWithFlags(&d.ev_iter[i], hipEventDisableTiming));
+    }
+    // one workspace block: sync words, leaf slots, interchange plans
+    const size_t plan_bytes = align_up(2 * kMaxSwaps * sizeof(int32_t), 256) * 2 + 256;
+    size_t o = 0;
+    const size_t o_ctr = o; o += 256;
+    const size_t o_abort = o; o += 256;
+    const size_t o_info = o; o += 256;
+    const size_t o_perr = o; o += 256;
+    const size_t o_slots = o; o = align_up(o + sizeof(double) * 2 * kLeafMaxWGs * kLeafSlot, 256);
+    const size_t o_top = o; o = align_up(o + sizeof(double) * 2 * kLeafMaxW, 256);
+    const size_t o_plans = o; o += plan_bytes * (kRing * kMaxChunks + 2);
+    void *ws = nullptr;
+    if (hipMalloc(&ws, o) != hipSuccess) HPLX_FAIL(HPL_ERR_NOMEM, "workspace allocation failed");
+    d.ws = ws;
+    char *b = (char *)ws;
+    d.sync.counter = (unsigned long long *)(b + o_ctr);
+    d.sync.abort_flag = (int *)(b + o_abort);
+    d.sync.info = (unsigned long long *)(b + o_info);
+    d.pivot_err = (int *)(b + o_perr);
+    d.sync.slots = (double *)(b + o_slots);
+    d.sync.top = (double *)(b + o_top);
+    auto plan_at = [&](int k) {
+        char *p = b + o_plans + (size_t)k * plan_bytes;
+        SwapPlan s;
+        s.rows = (int32_t *)p;
+        s.srcslot = (int32_t *)(p + align_up(2 * kMaxSwaps * sizeof(int32_t), 256));
+        s.nslots = (int32_t *)(p + 2 * align_up(2 * kMaxSwaps * sizeof(int32_t), 256));
+        s.err = (int *)(b + o_perr);
+        return s;
+    };
+    for (int r = 0; r < kRing; ++r)
+        for (int q = 0; q < kMaxChunks; ++q) d.ring[r][q] = plan_at(r * kMaxChunks + q);
+    d.pint = plan_at(kRing * kMaxChunks);
+    d.psolve = plan_at(kRing * kMaxChunks + 1);
+    HPLX_TRY(hipMemset(ws, 0, o));
+    HPLX_TRY(hipHostMalloc((void **)&d.hbuf, 4096, hipHostMallocDefault));
+    HPLX_TRY(hipDeviceSynchronize());
+    d.bar_epoch = 0;
+    d.id = id;
+    d.ready = true;
+    return HPL_OK;
+}
+
+static int get_device(Device **out)
+{
+    int id = 0;
+    HPLX_TRY(hipGetDevice(&id));
+    if (id < 0 || id >= kMaxDevices) HPLX_FAIL(HPL_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    Device &d = g_dev[id];
+    if (!d.ready) {
+        int rc = init_device(d, id);
+        if (rc != HPL_OK) return rc;
+    }
+    *out = &d;
+    return HPL_OK;
+}
+
+static int ensure_red(Device *d, int64_t count)
+{
+    if (d->red_cap >= count) return HPL_OK;
+    if (d->red) HPLX_TRY(hipFree(d->red));
+    d->red = nullptr;
+    d->red_cap = 0;
+    if (hipMalloc((void **)&d->red, sizeof(unsigned long long) * count) != hipSuccess)
+        HPLX_FAIL(HPL_ERR_NOMEM, "residual buffer allocation failed");
+    d->red_cap = count;
+    return HPL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// building blocks
+// ---------------------------------------------------------------------------
+struct Ctx {
+    Device *d;
+    double *A;
+    int64_t n, lda;
+    int32_t *ipiv;
+    int base, gmax, gemm_tile;
+    Timer *tm;
+};
+
+// Interchange plans of ipiv[k0 .. k0+cnt) (cnt <= kMaxChunks*kMaxSwaps) into plans[].
+static int make_plans(const int32_t *ipiv_k0, int64_t k0, int64_t cnt, int64_t nrows, SwapPlan *plans,
+                      bool reverse, hipStream_t st, Timer *tm)
+{
+    int id = tm->begin(ST_PLAN, st);
+    for (int64_t q = 0; q * kMaxSwaps < cnt; ++q) {
+        const int64_t off0 = q * kMaxSwaps;
+        const int64_t c = (cnt - off0) < kMaxSwaps ? (cnt - off0) : kMaxSwaps;
+        HPLX_PROPAGATE(launch_swap_plan(ipiv_k0 + off0, (int)c, k0 + off0, nrows, reverse, plans[q], st));
+    }
+    return tm->end(id, st, 0, 0);
+}
+
+static int apply_plans(double *A, int64_t lda, int64_t col0, int64_t ncols, int64_t cnt, SwapPlan *plans,
+                       hipStream_t st, Timer *tm)
+{
+    if (ncols <= 0 || cnt <= 0) return HPL_OK;
+    int id = tm->begin(ST_LASWP, st);
+    for (int64_t q = 0; q * kMaxSwaps < cnt; ++q) HPLX_PROPAGATE(launch_laswp(A, lda, col0, ncols, plans[q], st));
+    return tm->end(id, st, 0, 32.0 * (double)cnt * (double)ncols);
+}
+
+// B(nbk x ncols) <- L^{-1} B for nbk <= 1024 (row chunks of 512 joined by a GEMM).
+static int trsm_any(const double *L, int64_t ldl, double *B, int64_t ldb, int64_t nbk, int64_t ncols, int tile,
+                    hipStream_t st)
+{
+    if (nbk <= 512) return launch_trsm_llnu(L, ldl, B, ldb, nbk, ncols, st);
+    HPLX_PROPAGATE(launch_trsm_llnu(L, ldl, B, ldb, 512, ncols, st));
+    HPLX_PROPAGATE(launch_gemm_sub(nbk - 512, ncols, 512, L + 512, ldl, B, ldb, B + 512, ldb, tile, st));
+    return launch_trsm_llnu(L + off(512, 512, ldl), ldl, B + 512, ldb, nbk - 512, ncols, st);
+}
+
+// Recursive panel factorization of columns [c, c+w), rows [c, n) (Sec. III-A:
+// recursive right-looking, two halves per level, small leaves factored
+// right-looking).
+static int panel_rec(Ctx &x, int64_t c, int64_t w, hipStream_t st)
+{
+    Device *d = x.d;
+    if (w <= x.base) {
+        const int64_t m = x.n - c;
+        const int G = leaf_groups(m, (int)w, x.gmax);
+        const unsigned long long base_ctr = d->bar_epoch;
+        if (G > 1) d->bar_epoch += (unsigned long long)G * (unsigned long long)w;
+        return launch_panel_leaf(x.A, x.lda, c, m, (int)w, x.ipiv, d->sync, base_ctr, G, st);
+    }
+    int64_t w1 = ((w / 2 + x.base - 1) / x.base) * x.base;
+    if (w1 >= w) w1 = w - 1;
+    const int64_t w2 = w - w1;
+    HPLX_PROPAGATE(panel_rec(x, c, w1, st));
+    HPLX_PROPAGATE(launch_swap_plan(x.ipiv + c, (int)w1, c, x.n, false, d->pint, st));
+    HPLX_PROPAGATE(launch_laswp(x.A, x.lda, c + w1, w2, d->pint, st));
+    HPLX_PROPAGATE(launch_trsm_llnu(x.A + off(c, c, x.lda), x.lda, x.A + off(c, c + w1, x.lda), x.lda, w1, w2, st));
+    HPLX_PROPAGATE(launch_gemm_sub(x.n - c - w1, w2, w1, x.A + off(c + w1, c, x.lda), x.lda,
+                                   x.A + off(c, c + w1, x.lda), x.lda, x.A + off(c + w1, c + w1, x.lda), x.lda, 0,
+                                   st));
+    HPLX_PROPAGATE(panel_rec(x, c + w1, w2, st));
+    HPLX_PROPAGATE(launch_swap_plan(x.ipiv + c + w1, (int)w2, c + w1, x.n, false, d->pint, st));
+    return launch_laswp(x.A, x.lda, c, w1, d->pint, st);
+}
+
+static int panel_full(Ctx &x, int64_t c0, int64_t jb, SwapPlan *plans, hipStream_t st)
+{
+    const double m = (double)(x.n - c0);
+    const double w = (double)jb;
+    int id = x.tm->begin(ST_PANEL, st);
+    HPLX_PROPAGATE(panel_rec(x, c0, jb, st));
+    // flops of LU of an m x w panel: m w^2 - w^3/3 (plus lower-order terms)
+    HPLX_PROPAGATE(x.tm->end(id, st, m * w * w - w * w * w / 3.0, 16.0 * m * w));
+    return make_plans(x.ipiv + c0, c0, jb, x.n, plans, false, st, x.tm);
+}
+
+// RS + TRSM + GEMM of panel (c0, jb) applied to columns [col, col+ncols).
+static int update_cols(Ctx &x, int64_t c0, int64_t jb, int64_t col, int64_t ncols, SwapPlan *plans, hipStream_t st)
+{
+    if (ncols <= 0) return HPL_OK;
+    HPLX_PROPAGATE(apply_plans(x.A, x.lda, col, ncols, jb, plans, st, x.tm));
+    int id = x.tm->begin(ST_TRSM, st);
+    HPLX_PROPAGATE(trsm_any(x.A + off(c0, c0, x.lda), x.lda, x.A + off(c0, col, x.lda), x.lda, jb, ncols,
+                            x.gemm_tile, st));
+    HPLX_PROPAGATE(x.tm->end(id, st, (double)jb * (double)jb * (double)ncols, 16.0 * (double)jb * (double)ncols));
+    const int64_t c1 = c0 + jb;
+    const int64_t m = x.n - c1;
+    if (m > 0) {
+        id = x.tm->begin(ST_GEMM, st);
+        HPLX_PROPAGATE(launch_gemm_sub(m, ncols, jb, x.A + off(c1, c0, x.lda), x.lda, x.A + off(c0, col, x.lda),
+                                       x.lda, x.A + off(c1, col, x.lda), x.lda, x.gemm_tile, st));
+        HPLX_PROPAGATE(x.tm->end(id, st, 2.0 * (double)m * (double)ncols * (double)jb,
+                                 16.0 * (double)m * (double)ncols + 8.0 * (double)jb * ((double)m + (double)ncols)));
+    }
+    return HPL_OK;
+}
+
+// Reports (and clears) an out-of-range pivot seen by the plan kernel; hbuf[2] holds the flag.
+static int check_pivot_error(Device *d, hipStream_t st)
+{
+    if (*(int *)(d->hbuf + 2) == 0) return HPL_OK;
+    HPLX_TRY(hipMemsetAsync(d->pivot_err, 0, sizeof(int), st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    HPLX_FAIL(HPL_ERR_INTERNAL, "pivot index outside [k, n) in ipiv");
+}
+
+static double now_s()
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return ts.tv_sec + 1e-9 * ts.tv_nsec;
+}
+
+static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb, int32_t *ipiv, int64_t *info,
+                       hipStream_t su)
+{
+    Timer tm(d, opt_timing.load() != 0);
+    Ctx x{d, A, n, lda, ipiv, (int)opt_panel_base.load(), (int)opt_panel_wgs.load(), (int)opt_gemm_tile.load(), &tm};
+    const int64_t progress = opt_progress.load();
+    const bool la = opt_lookahead.load() != 0 && opt_serialize.load() == 0 && n > nb;
+    hipStream_t sp = la ? d->sp : su;
+    const int64_t np = (n + nb - 1) / nb;
+    const double t0 = now_s();
+
+    HPLX_PROPAGATE(launch_fill_u64(d->sync.info, 1, ULLONG_MAX, su));
+    if (la) {
+        HPLX_TRY(hipEventRecord(d->ev_start, su));
+        HPLX_TRY(hipStreamWaitEvent(sp, d->ev_start, 0));
+    }
+    HPLX_PROPAGATE(panel_full(x, 0, nb < n ? nb : n, d->ring[0], sp));
+    if (la) HPLX_TRY(hipEventRecord(d->ev_panel[0], sp));
+
+    for (int64_t j = 0; j < np; ++j) {
+        const int64_t c0 = j * nb;
+        const int64_t jb = (n - c0) < nb ? (n - c0) : nb;
+        const int64_t c1 = c0 + jb;
+        SwapPlan *plans = d->ring[j % kRing];
+        if (la) HPLX_TRY(hipStreamWaitEvent(su, d->ev_panel[j % kRing], 0));
+        if (c1 < n) {
+            const int64_t jb2 = (n - c1) < nb ? (n - c1) : nb;
+            SwapPlan *next_plans = d->ring[(j + 1) % kRing];
+            if (la) {
+                HPLX_PROPAGATE(update_cols(x, c0, jb, c1, jb2, plans, su));
+                HPLX_TRY(hipEventRecord(d->ev_la[j % kRing], su));
+                HPLX_TRY(hipStreamWaitEvent(sp, d->ev_la[j % kRing], 0));
+                HPLX_PROPAGATE(panel_full(x, c1, jb2, next_plans, sp));
+                HPLX_TRY(hipEventRecord(d->ev_panel[(j + 1) % kRing], sp));
+                HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, n - c1 - jb2, plans, su));
+            } else {
+                HPLX_PROPAGATE(update_cols(x, c0, jb, c1, n - c1, plans, su));
+                HPLX_PROPAGATE(panel_full(x, c1, jb2, next_plans, su));
+            }
+        }
+        // interchanges of panel j on the columns to its left (L in LAPACK form)
+        HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
+        HPLX_TRY(hipEventRecord(d->ev_iter[j % kRing], su));
+        // keep at most two iterations queued ahead of the device
+        if (j >= 2) HPLX_TRY(hipEventSynchronize(d->ev_iter[(j - 2) % kRing]));
+        if (progress > 0 && ((j + 1) % progress == 0 || j + 1 == np)) {
+            fprintf(stderr, "[hplx] panel %lld/%lld queued, %.2f s\n", (long long)(j + 1), (long long)np,
+                    now_s() - t0);
+            fflush(stderr);
+        }
+    }
+    HPLX_TRY(hipMemcpyAsync(d->hbuf, d->sync.info, sizeof(unsigned long long), hipMemcpyDeviceToHost, su));
+    HPLX_TRY(hipMemcpyAsync(d->hbuf + 1, d->sync.abort_flag, sizeof(int), hipMemcpyDeviceToHost, su));
+    HPLX_TRY(hipMemcpyAsync(d->hbuf + 2, d->pivot_err, sizeof(int), hipMemcpyDeviceToHost, su));
+    HPLX_TRY(hipStreamSynchronize(su));
+    if (la) HPLX_TRY(hipStreamSynchronize(sp));
+    HPLX_PROPAGATE(tm.collect());
+    HPLX_PROPAGATE(check_pivot_error(d, su));
+    const int aborted = *(int *)(d->hbuf + 1);
+    if (aborted) {
+        HPLX_PROPAGATE(launch_fill_u64(d->sync.counter, 1, 0ull, su));
+        HPLX_TRY(hipMemsetAsync(d->sync.abort_flag, 0, sizeof(int), su));
+        HPLX_TRY(hipStreamSynchronize(su));
+        d->bar_epoch = 0;
+        HPLX_FAIL(HPL_ERR_INTERNAL, "panel barrier timed out");
+    }
+    const unsigned long long iv = d->hbuf[0];
+    *info = (iv == ULLONG_MAX) ? 0 : (int64_t)iv;
+    return HPL_OK;
+}
+
+static int solve_impl(Device *d, const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, int64_t n,
+                      int64_t lda, int64_t ldb, int trans, hipStream_t st)
+{
+    Timer tm(d, opt_timing.load() != 0);
+    const int64_t bs = 64;
+    int id = tm.begin(ST_SOLVE, st);
+    auto swaps = [&](bool reverse) -> int {
+        const int64_t nchunk = (n + kMaxSwaps - 1) / kMaxSwaps;
+        for (int64_t qq = 0; qq < nchunk; ++qq) {
+            const int64_t q = reverse ? nchunk - 1 - qq : qq;
+            const int64_t k0 = q * kMaxSwaps;
+            const int64_t cnt = (n - k0) < kMaxSwaps ? (n - k0) : kMaxSwaps;
+            HPLX_PROPAGATE(launch_swap_plan(ipiv + k0, (int)cnt, k0, n, reverse, d->psolve, st));
+            HPLX_PROPAGATE(launch_laswp(B, ldb, 0, nrhs, d->psolve, st));
+        }
+        return HPL_OK;
+    };
+    auto forward = [&](int mode) -> int {
+        for (int64_t r0 = 0; r0 < n; r0 += bs) {
+            const int64_t b = (n - r0) < bs ? (n - r0) : bs;
+            HPLX_PROPAGATE(launch_trsv_block(LU, lda, B, ldb, nrhs, r0, b, mode, st));
+            HPLX_PROPAGATE(launch_gemv_update(LU, lda, B, ldb, nrhs, r0, b, r0 + b, n, mode, st));
+        }
+        return HPL_OK;
+    };
+    auto backward = [&](int mode) -> int {
+        for (int64_t r0 = ((n - 1) / bs) * bs; r0 >= 0; r0 -= bs) {
+            const int64_t b = (n - r0) < bs ? (n - r0) : bs;
+            HPLX_PROPAGATE(launch_trsv_block(LU, lda, B, ldb, nrhs, r0, b, mode, st));
+            HPLX_PROPAGATE(launch_gemv_update(LU, lda, B, ldb, nrhs, r0, b, 0, r0, mode, st));
+        }
+        return HPL_OK;
+    };
+    if (trans == 0) {
+        HPLX_PROPAGATE(swaps(false));
+        HPLX_PROPAGATE(forward(0));
+        HPLX_PROPAGATE(backward(1));
+    } else {
+        HPLX_PROPAGATE(forward(2));
+        HPLX_PROPAGATE(backward(3));
+        HPLX_PROPAGATE(swaps(true));
+    }
+    HPLX_PROPAGATE(tm.end(id, st, 2.0 * (double)n * (double)n * (double)nrhs, 8.0 * (double)n * (double)n));
+    HPLX_TRY(hipMemcpyAsync(d->hbuf + 2, d->pivot_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    HPLX_PROPAGATE(tm.collect());
+    return check_pivot_error(d, st);
+}
+
+static int residual_impl(const double *A, int64_t lda, bool gen, uint64_t seed, int64_t n, const double *X,
+                         int64_t ldx, const double *B, int64_t ldb, int64_t nrhs, double *out, hipStream_t st)
+{
+    for (int i = 0; i < 5; ++i) out[i] = 0.0;
+    if (n == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    const int64_t cnt = 1 + 3 * nrhs;
+    HPLX_PROPAGATE(ensure_red(d, cnt));
+    HPLX_PROPAGATE(launch_fill_u64(d->red, cnt, 0ull, st));
+    HPLX_PROPAGATE(launch_residual(A, lda, gen, gen ? stream_state(seed, 0) : 0, n, X, ldx, B, ldb, nrhs, d->red, st));
+    std::vector<unsigned long long> h(cnt);
+    HPLX_TRY(hipMemcpyAsync(h.data(), d->red, sizeof(unsigned long long) * cnt, hipMemcpyDeviceToHost, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    auto asd = [](unsigned long long u) {
+        double v;
+        memcpy(&v, &u, sizeof v);
+        return v;
+    };
+    const double eps = 0x1.0p-53;
+    const double anorm = asd(h[0]);
+    double worst = 0.0, rmax = 0.0, xmax = 0.0, bmax = 0.0;
+    auto upd = [](double &acc, double v) {
+        if (!(v <= acc)) acc = v;  // NaN wins
+    };
+    for (int64_t c = 0; c < nrhs; ++c) {
+        const double rn = asd(h[1 + 3 * c]), xn = asd(h[2 + 3 * c]), bn = asd(h[3 + 3 * c]);
+        upd(worst, rn / (eps * (anorm * xn + bn) * (double)n));
+        upd(rmax, rn);
+        upd(xmax, xn);
+        upd(bmax, bn);
+    }
+    out[0] = worst;
+    out[1] = rmax;
+    out[2] = anorm;
+    out[3] = xmax;
+    out[4] = bmax;
+    return HPL_OK;
+}
+
+}  // namespace hplx
+
+using namespace hplx;
+
+extern "C" {
+
+int hpl_factor(double *A, int64_t n, int64_t lda, int64_t nb, int32_t *ipiv, int64_t *info, void *hip_stream)
+{
+    if (n > 0 && A == nullptr) return -1;
+    if (n < 0 || n > INT32_MAX) return -2;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (nb < 1 || nb > (int64_t)kMaxChunks * kMaxSwaps) return -4;
+    if (n > 0 && ipiv == nullptr) return -5;
+    if (info == nullptr) return -6;
+    *info = 0;
+    if (n == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    return factor_impl(d, A, n, lda, nb, ipiv, info, (hipStream_t)hip_stream);
+}
+
+int hpl_solve(const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, int64_t n, int64_t lda, int64_t ldb,
+              int trans, void *hip_stream)
+{
+    if (n > 0 && LU == nullptr) return -1;
+    if (n > 0 && ipiv == nullptr) return -2;
+    if (n > 0 && nrhs > 0 && B == nullptr) return -3;
+    if (nrhs < 0) return -4;
+    if (n < 0 || n > INT32_MAX) return -5;
+    if (lda < (n > 1 ? n : 1)) return -6;
+    if (ldb < (n > 1 ? n : 1)) return -7;
+    if (trans != 0 && trans != 1) return -8;
+    if (n == 0 || nrhs == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    return solve_impl(d, LU, ipiv, B, nrhs, n, lda, ldb, trans, (hipStream_t)hip_stream);
+}
+
+int hpl_residual(const double *A0, int64_t n, int64_t lda, const double *X, int64_t ldx, const double *B, int64_t ldb,
+                 int64_t nrhs, double *out, void *hip_stream)
+{
+    if (n > 0 && A0 == nullptr) return -1;
+    if (n < 0) return -2;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (n > 0 && X == nullptr) return -4;
+    if (ldx < (n > 1 ? n : 1)) return -5;
+    if (n > 0 && B == nullptr) return -6;
+    if (ldb < (n > 1 ? n : 1)) return -7;
+    if (nrhs < 1) return -8;
+    if (out == nullptr) return -9;
+    return residual_impl(A0, lda, false, 0, n, X, ldx, B, ldb, nrhs, out, (hipStream_t)hip_stream);
+}
+
+int hpl_residual_gen(uint64_t seed, int64_t n, const double *X, int64_t ldx, const double *B, int64_t ldb,
+                     int64_t nrhs, double *out, void *hip_stream)
+{
+    if (n < 0) return -2;
+    if (n > 0 && X == nullptr) return -3;
+    if (ldx < (n > 1 ? n : 1)) return -4;
+    if (n > 0 && B == nullptr) return -5;
+    if (ldb < (n > 1 ? n : 1)) return -6;
+    if (nrhs < 1) return -7;
+    if (out == nullptr) return -8;
+    return residual_impl(nullptr, 1, true, seed, n, X, ldx, B, ldb, nrhs, out, (hipStream_t)hip_stream);
+}
+
+int hpl_generate(uint64_t seed, uint64_t stream_id, double *M, int64_t rows, int64_t cols, int64_t ld,
+                 void *hip_stream)
+{
+    if (rows > 0 && cols > 0 && M == nullptr) return -3;
+    if (rows < 0) return -4;
+    if (cols < 0) return -5;
+    if (ld < (rows > 1 ? rows : 1)) return -6;
+    if (rows == 0 || cols == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HPLX_PROPAGATE(launch_generate(stream_state(seed, stream_id), M, rows, cols, ld, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    return HPL_OK;
+}
+
+int hpl_set_option(int key, int64_t value)
+{
+    switch (key) {
+    case HPL_OPT_LOOKAHEAD:
+        if (value != 0 && value != 1) return -2;
+        opt_lookahead = value;
+        return 0;
+    case HPL_OPT_PANEL_BASE:
+        if (value != 8 && value != 16 && value != 32 && value != 64) return -2;
+        opt_panel_base = value;
+        return 0;
+    case HPL_OPT_PANEL_WGS:
+        if (value < 1 || value > kLeafMaxWGs) return -2;
+        opt_panel_wgs = value;
+        return 0;
+    case HPL_OPT_TIMING:
+        if (value != 0 && value != 1) return -2;
+        opt_timing = value;
+        return 0;
+    case HPL_OPT_PROGRESS:
+        if (value < 0) return -2;
+        opt_progress = value;
+        return 0;
+    case HPL_OPT_SERIALIZE:
+        if (value != 0 && value != 1) return -2;
+        opt_serialize = value;
+        return 0;
+    case HPL_OPT_GEMM_TILE:
+        if (value < 0 || value > 4) return -2;
+        opt_gemm_tile = value;
+        return 0;
+    default: return -1;
+    }
+}
+
+int64_t hpl_get_option(int key)
+{
+    switch (key) {
+    case HPL_OPT_LOOKAHEAD: return opt_lookahead;
+    case HPL_OPT_PANEL_BASE: return opt_panel_base;
+    case HPL_OPT_PANEL_WGS: return opt_panel_wgs;
+    case HPL_OPT_TIMING: return opt_timing;
+    case HPL_OPT_PROGRESS: return opt_progress;
+    case HPL_OPT_SERIALIZE: return opt_serialize;
+    case HPL_OPT_GEMM_TILE: return opt_gemm_tile;
+    default: return INT64_MIN;
+    }
+}
+
+int hpl_get_stats(int64_t *launches, double *ms, double *flops, double *bytes, int cap)
+{
+    std::lock_guard<std::mutex> lk(g_st_mu);
+    for (int k = 0; k < ST_N && k < cap; ++k) {
+        if (launches) launches[k] = g_st_launch[k];
+        if (ms) ms[k] = g_st_ms[k];
+        if (flops) flops[k] = g_st_flops[k];
+        if (bytes) bytes[k] = g_st_bytes[k];
+    }
+    return ST_N;
+}
+
+void hpl_reset_stats(void)
+{
+    std::lock_guard<std::mutex> lk(g_st_mu);
+    for (int k = 0; k < ST_N; ++k) {
+        g_st_launch[k] = 0;
+        g_st_ms[k] = g_st_flops[k] = g_st_bytes[k] = 0.0;
+    }
+}
+
+int hpl_release(void)
+{
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return HPL_OK;
+    for (int i = 0; i < kMaxDevices; ++i) {
+        Device &d = g_dev[i];
+        if (!d.ready) continue;
+        HPLX_TRY(hipSetDevice(i));
+        HPLX_TRY(hipDeviceSynchronize());
+        for (hipEvent_t e : d.ev_pool) (void)hipEventDestroy(e);
+        d.ev_pool.clear();
+        for (int r = 0; r < kRing; ++r) {
+            (void)hipEventDestroy(d.ev_panel[r]);
+            (void)hipEventDestroy(d.ev_la[r]);
+            (void)hipEventDestroy(d.ev_iter[r]);
+        }
+        (void)hipEventDestroy(d.ev_start);
+        (void)hipEventDestroy(d.ev_end);
+        (void)hipStreamDestroy(d.sp);
+        if (d.red) (void)hipFree(d.red);
+        if (d.hbuf) (void)hipHostFree(d.hbuf);
+        (void)hipFree(d.ws);
+        d = Device();
+    }
+    HPLX_TRY(hipSetDevice(cur));
+    return HPL_OK;
+}
+
+const char *hpl_strerror(int code)
+{
+    static const char *neg[] = {"",
+                                "invalid argument 1",
+                                "invalid argument 2",
+                                "invalid argument 3",
+                                "invalid argument 4",
+                                "invalid argument 5",
+                                "invalid argument 6",
+                                "invalid argument 7",
+                                "invalid argument 8",
+                                "invalid argument 9",
+                                "invalid argument 10"};
+    switch (code) {
+    case HPL_OK: return "success";
+    case HPL_ERR_HIP: return "HIP runtime error";
+    case HPL_ERR_NOMEM: return "workspace allocation failed";
+    case HPL_ERR_DEVICE: return "no gfx950 device";
+    case HPL_ERR_INTERNAL: return "internal error (kernel-reported failure)";
+    default:
+        if (code < 0 && code >= -10) return neg[-code];
+        return "unknown error code";
+    }
+}
+
+const char *hpl_last_error_detail(void)
+{
+    return g_err_detail;
+}
+
+}  // extern "C"

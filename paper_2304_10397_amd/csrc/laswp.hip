@@ -1,0 +1,158 @@
+// laswp.hip -- applying a panel's row interchanges to other columns (the RS
+// phase, Sec. I / Sec. II: all NB pivots found by FACT are applied to the
+// rest of the matrix).
+//
+// The interchanges k = 0..cnt-1 (row r0+k <-> ipiv[k], in order) touch at most
+// 2*cnt distinct rows S.  Their composition is a permutation of S, computed
+// once per panel by swap_plan_kernel ("slot list": slot s names row rows[s];
+// after the interchanges row rows[s] holds the old contents of row
+// rows[srcslot[s]]).  Slots 0..cnt-1 are the contiguous rows r0..r0+cnt-1 in
+// order, so the reads and writes of that block are coalesced; the other rows
+// are scattered (one 8-byte element per column per row: column-major storage
+// makes a row interchange a strided access whatever the kernel does).
+//
+// laswp_kernel then works on a few columns per workgroup: it gathers every
+// slot's element into LDS, synchronizes, and writes the permuted values back,
+// which is the in-place gather/scatter of the RS phase on one GPU.
+#include "common.hpp"
+
+namespace hplx {
+
+namespace {
+
+constexpr int kPlanThreads = kMaxSwaps;  // one thread per interchange
+constexpr int kLwCols = 8;               // columns per laswp workgroup
+constexpr int kLwThreads = 256;
+
+__global__ __launch_bounds__(kPlanThreads) void swap_plan_kernel(const int32_t *__restrict__ ipiv, int cnt,
+                                                                 int64_t r0, int64_t nrows, int reverse,
+                                                                 int32_t *__restrict__ rows_out,
+                                                                 int32_t *__restrict__ src_out,
+                                                                 int32_t *__restrict__ nslots_out,
+                                                                 int *__restrict__ err)
+{
+    __shared__ int piv[kMaxSwaps];        // target row relative to r0 (>= k)
+    __shared__ int bslot[kMaxSwaps];      // slot of the target row
+    __shared__ int cur[2 * kMaxSwaps];    // content (slot id) currently in slot s
+    __shared__ int used[2 * kMaxSwaps];
+    __shared__ int pos[2 * kMaxSwaps];    // compacted position of slot s
+    __shared__ int scan[kPlanThreads];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    if (t == 0) bad = 0;
+    __syncthreads();
+    if (t < cnt) {
+        const int64_t p = ipiv[t];
+        // an interchange partner must lie in [r0 + k, nrows): anything else would
+        // address rows outside the matrix, so the plan is dropped and reported
+        if (p < r0 + t || p >= nrows) atomicOr(&bad, 1);
+        piv[t] = (int)(p - r0);
+    }
+    __syncthreads();
+    if (bad) {
+        if (t == 0) {
+            *nslots_out = 0;
+            atomicOr(err, 1);
+        }
+        return;
+    }
+    if (t < cnt) {
+        const int p = piv[t];
+        int b = p;
+        if (p >= cnt) {  // outside the contiguous block: slot cnt + first k' with the same row
+            int f = t;
+            for (int k2 = 0; k2 < t; ++k2)
+                if (piv[k2] == p) { f = k2; break; }
+            b = cnt + f;
+        }
+        bslot[t] = b;
+    }
+    for (int s = t; s < 2 * cnt; s += kPlanThreads) cur[s] = s;
+    __syncthreads();
+    for (int s = t; s < 2 * cnt; s += kPlanThreads)
+        used[s] = (s < cnt) ? 1 : (bslot[s - cnt] == s ? 1 : 0);
+    if (t == 0) {
+        for (int kk = 0; kk < cnt; ++kk) {
+            const int k = reverse ? cnt - 1 - kk : kk;
+            const int b = bslot[k];
+            const int ca = cur[k], cb = cur[b];
+            cur[k] = cb;
+            cur[b] = ca;
+        }
+    }
+    __syncthreads();
+    // exclusive scan of used[] over 2*cnt slots: thread t owns slots 2t, 2t+1
+    const int s0 = 2 * t, s1 = 2 * t + 1;
+    const int u0 = (s0 < 2 * cnt) ? used[s0] : 0, u1 = (s1 < 2 * cnt) ? used[s1] : 0;
+    scan[t] = u0 + u1;
+    __syncthreads();
+    for (int o = 1; o < kPlanThreads; o <<= 1) {
+        const int v = (t >= o) ? scan[t - o] : 0;
+        __syncthreads();
+        scan[t] += v;
+        __syncthreads();
+    }
+    const int base = scan[t] - (u0 + u1);
+    if (s0 < 2 * cnt) pos[s0] = base;
+    if (s1 < 2 * cnt) pos[s1] = base + u0;
+    __syncthreads();
+    for (int s = t; s < 2 * cnt; s += kPlanThreads) {
+        if (!used[s]) continue;
+        const int rel = (s < cnt) ? s : piv[s - cnt];
+        rows_out[pos[s]] = (int32_t)(r0 + rel);
+        src_out[pos[s]] = pos[cur[s]];
+    }
+    if (t == kPlanThreads - 1) *nslots_out = scan[t];
+}
+
+__global__ __launch_bounds__(kLwThreads) void laswp_kernel(double *__restrict__ A, int64_t lda, int64_t col0,
+                                                           int64_t ncols, const int32_t *__restrict__ rows,
+                                                           const int32_t *__restrict__ srcslot,
+                                                           const int32_t *__restrict__ nslots_p)
+{
+    __shared__ double vals[2 * kMaxSwaps][kLwCols];
+    const int ns = *nslots_p;
+    const int64_t cb = col0 + (int64_t)blockIdx.x * kLwCols;
+    const int64_t left = col0 + ncols - cb;
+    const int nc = left < kLwCols ? (int)left : kLwCols;
+    for (int s = threadIdx.x; s < ns; s += kLwThreads) {
+        const int64_t r = rows[s];
+#pragma unroll
+        for (int c = 0; c < kLwCols; ++c)
+            if (c < nc) vals[s][c] = A[off(r, cb + c, lda)];
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < ns; s += kLwThreads) {
+        const int ss = srcslot[s];
+        if (ss == s) continue;
+        const int64_t r = rows[s];
+#pragma unroll
+        for (int c = 0; c < kLwCols; ++c)
+            if (c < nc) A[off(r, cb + c, lda)] = vals[ss][c];
+    }
+}
+
+}  // namespace
+
+int launch_swap_plan(const int32_t *ipiv, int cnt, int64_t r0, int64_t nrows, bool reverse, SwapPlan plan,
+                     hipStream_t st)
+{
+    if (cnt <= 0 || cnt > kMaxSwaps) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(swap_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, ipiv, cnt, r0, nrows, reverse ? 1 : 0,
+                       plan.rows, plan.srcslot, plan.nslots, plan.err);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_laswp(double *A, int64_t lda, int64_t col0, int64_t ncols, SwapPlan plan, hipStream_t st)
+{
+    if (ncols <= 0) return HPL_OK;
+    const int64_t g = (ncols + kLwCols - 1) / kLwCols;
+    if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)g), dim3(kLwThreads), 0, st, A, lda, col0, ncols, plan.rows,
+                       plan.srcslot, plan.nslots);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+}  // namespace hplx

@@ -1,0 +1,132 @@
+// trsm.hip -- U12 <- L11^{-1} A12 (the DTRSM of the UPDATE phase, Sec. I /
+// Sec. II: the pivoted rows of the block row are solved with the unit-lower
+// triangle of the factored diagonal block).
+//
+// B is nbk x ncols (nbk <= 512), L is nbk x nbk unit lower.  One workgroup of
+// 8 waves owns 64 columns of B for the whole solve; the 64 columns live in
+// MFMA accumulators (32 row blocks of 16 rows x 4 column blocks of 16, row
+// block rb owned by wave rb % 8).  Step i:
+//   1. the owner of row block i hands its 16 x 64 block to LDS,
+//   2. all 512 threads finish it by substitution with the 16 x 16 diagonal
+//      block of L (so exactly representable data stay exact): each column's 16
+//      rows sit in 16 lanes of one wave and x_k travels by lane shuffle; the
+//      solved rows go to global memory,
+//   3. every wave subtracts L[rb, i] * X_i from its row blocks rb > i with
+//      v_mfma_f64_16x16x4_f64 (A operand = -L fragment from L2, B operand = X_i
+//      from LDS).
+// Each column's arithmetic is independent of which workgroup holds it, so a
+// split of the columns (look-ahead) gives identical bits.
+#include "common.hpp"
+
+namespace hplx {
+
+namespace {
+
+constexpr int kTrWB = 64;      // columns per workgroup
+constexpr int kTrCB = kTrWB / 16;  // column blocks
+constexpr int kTrWaves = 8;    // waves per workgroup
+constexpr int kTrMaxRB = 32;   // row blocks (nbk <= 512)
+constexpr int kTrQ = kTrMaxRB / kTrWaves;  // row blocks per wave
+
+__global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const double *__restrict__ L, int64_t ldl,
+                                                                    double *__restrict__ B, int64_t ldb, int nbk,
+                                                                    int64_t ncols)
+{
+    __shared__ double Xs[2][16][kTrWB + 1];
+    __shared__ double Ls[2][16][17];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t c0 = (int64_t)blockIdx.x * kTrWB;
+    const int64_t crem = ncols - c0;
+    const int nrb = (nbk + 15) >> 4;
+
+    dbl4 acc[kTrQ][kTrCB];
+#pragma unroll
+    for (int q = 0; q < kTrQ; ++q) {
+        const int rb = wave + kTrWaves * q;
+#pragma unroll
+        for (int cb = 0; cb < kTrCB; ++cb) {
+            const int cc = 16 * cb + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = 16 * rb + 4 * (lane >> 4) + r;
+                acc[q][cb][r] = (rb < nrb && rr < nbk && cc < crem) ? B[off(rr, c0 + cc, ldb)] : 0.0;
+            }
+        }
+    }
+
+    for (int i = 0; i < nrb; ++i) {
+        const int par = i & 1;
+        // 1. owner publishes row block i; others stage the diagonal block of L
+        if (wave == (i % kTrWaves)) {
+            const int q = i / kTrWaves;
+#pragma unroll
+            for (int qq = 0; qq < kTrQ; ++qq) {
+                if (qq != q) continue;
+#pragma unroll
+                for (int cb = 0; cb < kTrCB; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Xs[par][4 * (lane >> 4) + r][16 * cb + (lane & 15)] = acc[qq][cb][r];
+            }
+        }
+        if (t >= 256) {
+            const int e = t - 256, r = e & 15, c = e >> 4;
+            const int gr = 16 * i + r, gc = 16 * i + c;
+            Ls[par][r][c] = (gr < nbk && gc < nbk) ? L[off(gr, gc, ldl)] : 0.0;
+        }
+        __syncthreads();
+        // 2. substitution of the 16 x kTrWB block: thread -> (row r, columns c, c + 32);
+        //    a column's 16 rows sit in 16 consecutive lanes, so x_k is a lane shuffle
+        {
+            const int r = t & 15, c = t >> 4;
+#pragma unroll
+            for (int h = 0; h < kTrWB / 32; ++h) {
+                const int cc = c + 32 * h;
+                double x = Xs[par][r][cc];
+#pragma unroll
+                for (int kk = 0; kk < 15; ++kk) {
+                    const double xk = __shfl(x, (lane & ~15) | kk, 64);
+                    if (r > kk) x = x - Ls[par][r][kk] * xk;
+                }
+                Xs[par][r][cc] = x;
+                const int gr = 16 * i + r;
+                if (gr < nbk && cc < crem) B[off(gr, c0 + cc, ldb)] = x;
+            }
+        }
+        __syncthreads();
+        // 3. trailing row blocks
+#pragma unroll
+        for (int q = 0; q < kTrQ; ++q) {
+            const int rb = wave + kTrWaves * q;
+            if (rb > i && rb < nrb) {
+                const int lr = 16 * rb + (lane & 15);
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    const int kc = 4 * k4 + (lane >> 4);
+                    const double a = (lr < nbk) ? -L[off(lr, 16 * i + kc, ldl)] : 0.0;
+#pragma unroll
+                    for (int cb = 0; cb < kTrCB; ++cb) {
+                        const double b = Xs[par][kc][16 * cb + (lane & 15)];
+                        acc[q][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q][cb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int launch_trsm_llnu(const double *L, int64_t ldl, double *B, int64_t ldb, int64_t nbk, int64_t ncols,
+                     hipStream_t st)
+{
+    if (nbk <= 0 || ncols <= 0) return HPL_OK;
+    if (nbk > 16 * kTrMaxRB) return HPL_ERR_INTERNAL;
+    const int64_t g = (ncols + kTrWB - 1) / kTrWB;
+    if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(trsm_llnu_kernel, dim3((unsigned)g), dim3(kTrWaves * 64), 0, st, L, ldl, B, ldb, (int)nbk,
+                       ncols);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+}  // namespace hplx

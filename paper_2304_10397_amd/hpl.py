@@ -1,0 +1,230 @@
+"""Python binding of libhplx (include/hpl.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Device memory and
+streams come from PyTorch (HIP build): matrices are float64 CUDA tensors in
+column-major layout, i.e. ``A.stride(0) == 1`` and ``A.stride(1) == lda``
+(``colmajor(n, m)`` makes one).  All arithmetic runs in the HIP kernels of
+libhplx.so; there is no fallback: if the library is missing the import of this
+module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhplx.so")
+
+HPL_OK = 0
+HPL_ERR_HIP = 1
+HPL_ERR_NOMEM = 2
+HPL_ERR_DEVICE = 3
+HPL_ERR_INTERNAL = 4
+
+HPL_OPT_LOOKAHEAD = 1
+HPL_OPT_PANEL_BASE = 2
+HPL_OPT_PANEL_WGS = 3
+HPL_OPT_TIMING = 4
+HPL_OPT_PROGRESS = 5
+HPL_OPT_SERIALIZE = 6
+HPL_OPT_GEMM_TILE = 7
+
+STAT_CLASSES = ("gemm", "panel", "laswp", "trsm", "solve", "plan")
+
+
+class HplError(RuntimeError):
+    def __init__(self, fn, code, detail=""):
+        self.code = code
+        msg = f"{fn}: {strerror(code)} (code {code})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libhplx.so not found at {LIB_PATH}; build it with "
+            "`python -m paper_2304_10397_amd.build` (there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, u64, i32, dbl, P = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    sig = {
+        "hpl_factor": (i32, [P, i64, i64, i64, P, P, P]),
+        "hpl_solve": (i32, [P, P, P, i64, i64, i64, i64, i32, P]),
+        "hpl_residual": (i32, [P, i64, i64, P, i64, P, i64, i64, P, P]),
+        "hpl_residual_gen": (i32, [u64, i64, P, i64, P, i64, i64, P, P]),
+        "hpl_generate": (i32, [u64, u64, P, i64, i64, i64, P]),
+        "hpl_set_option": (i32, [i32, i64]),
+        "hpl_get_option": (i64, [i32]),
+        "hpl_get_stats": (i32, [P, P, P, P, i32]),
+        "hpl_reset_stats": (None, []),
+        "hpl_release": (i32, []),
+        "hpl_strerror": (ctypes.c_char_p, [i32]),
+        "hpl_last_error_detail": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+_lib = _load()
+EXPORTED = ("hpl_factor", "hpl_solve", "hpl_residual", "hpl_residual_gen", "hpl_generate",
+            "hpl_set_option", "hpl_get_option", "hpl_get_stats", "hpl_reset_stats",
+            "hpl_release", "hpl_strerror", "hpl_last_error_detail")
+
+
+def lib():
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return _lib.hpl_strerror(int(code)).decode()
+
+
+def _check(fn, rc):
+    if rc != 0:
+        detail = _lib.hpl_last_error_detail().decode() if rc > 0 else ""
+        if rc < 0:
+            raise ValueError(f"{fn}: {strerror(rc)}")
+        raise HplError(fn, rc, detail)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _matrix(name, M, rows=None):
+    """(pointer, rows, cols, ld) of a column-major float64 CUDA tensor (1-D = one column)."""
+    torch = _torch()
+    if not isinstance(M, torch.Tensor) or M.dtype != torch.float64 or not M.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if M.dim() == 1:
+        if M.stride(0) != 1 and M.numel() > 1:
+            raise ValueError(f"{name} must be contiguous")
+        r = M.shape[0]
+        return ctypes.c_void_p(M.data_ptr()), r, 1, max(1, r)
+    if M.dim() != 2:
+        raise ValueError(f"{name} must be 1-D or 2-D")
+    r, c = M.shape
+    if r > 1 and M.stride(0) != 1:
+        raise ValueError(f"{name} must be column-major (stride(0) == 1)")
+    ld = M.stride(1) if c > 1 else max(1, r)
+    return ctypes.c_void_p(M.data_ptr()), r, c, max(ld, 1)
+
+
+def colmajor(rows, cols, ld=None, device="cuda", fill=None):
+    """Empty (or filled) column-major float64 tensor of shape (rows, cols), leading dimension ld."""
+    torch = _torch()
+    ld = rows if ld is None else ld
+    buf = torch.empty((max(cols, 1), max(ld, 1)), dtype=torch.float64, device=device)
+    if fill is not None:
+        buf.fill_(fill)
+    return buf.t()[:rows, :cols]
+
+
+def hpl_factor(A, nb, ipiv=None, stream=None):
+    """LU with partial pivoting in place; returns (ipiv int32 CUDA tensor, info)."""
+    torch = _torch()
+    pA, n, m, lda = _matrix("A", A)
+    if n != m:
+        raise ValueError("A must be square")
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    if ipiv.dtype != torch.int32 or not ipiv.is_cuda or ipiv.numel() < n:
+        raise TypeError("ipiv must be an int32 CUDA tensor with n entries")
+    info = ctypes.c_int64(0)
+    rc = _lib.hpl_factor(pA, n, lda, int(nb), ctypes.c_void_p(ipiv.data_ptr()), ctypes.byref(info),
+                         _stream(stream))
+    _check("hpl_factor", rc)
+    return ipiv[:n], int(info.value)
+
+
+def hpl_solve(LU, ipiv, B, trans=0, stream=None):
+    """Overwrite B (n or n x nrhs, column-major) with the solution of A X = B (or A^T X = B)."""
+    pLU, n, m, lda = _matrix("LU", LU)
+    pB, nb_, nrhs, ldb = _matrix("B", B)
+    if nb_ != n:
+        raise ValueError("B must have n rows")
+    rc = _lib.hpl_solve(pLU, ctypes.c_void_p(ipiv.data_ptr()), pB, nrhs, n, lda, ldb, int(trans),
+                        _stream(stream))
+    _check("hpl_solve", rc)
+    return B
+
+
+def hpl_residual(A0, X, B, stream=None):
+    """numpy [scaled, ||r||inf, ||A||inf, ||x||inf, ||b||inf] (HPL passes when scaled < 16)."""
+    pA, n, m, lda = _matrix("A0", A0)
+    pX, _, nrhs, ldx = _matrix("X", X)
+    pB, _, _, ldb = _matrix("B", B)
+    out = np.zeros(5)
+    rc = _lib.hpl_residual(pA, n, lda, pX, ldx, pB, ldb, nrhs, out.ctypes.data_as(ctypes.c_void_p),
+                           _stream(stream))
+    _check("hpl_residual", rc)
+    return out
+
+
+def hpl_residual_gen(seed, n, X, B, stream=None):
+    """As hpl_residual with A regenerated from (seed, stream 0)."""
+    pX, _, nrhs, ldx = _matrix("X", X)
+    pB, _, _, ldb = _matrix("B", B)
+    out = np.zeros(5)
+    rc = _lib.hpl_residual_gen(int(seed) % 2**64, int(n), pX, ldx, pB, ldb, nrhs,
+                               out.ctypes.data_as(ctypes.c_void_p), _stream(stream))
+    _check("hpl_residual_gen", rc)
+    return out
+
+
+def hpl_generate(seed, stream_id, M, stream=None):
+    """Fill the column-major tensor M with the random stream (seed, stream_id); returns M."""
+    pM, r, c, ld = _matrix("M", M)
+    rc = _lib.hpl_generate(int(seed) % 2**64, int(stream_id) % 2**64, pM, r, c, ld, _stream(stream))
+    _check("hpl_generate", rc)
+    return M
+
+
+def hpl_set_option(key, value):
+    rc = _lib.hpl_set_option(int(key), int(value))
+    if rc != 0:
+        raise ValueError(f"hpl_set_option({key}, {value}) -> {rc}")
+
+
+def hpl_get_option(key):
+    return int(_lib.hpl_get_option(int(key)))
+
+
+def hpl_get_stats():
+    """{class: {"launches", "ms", "flops", "bytes"}} accumulated while HPL_OPT_TIMING is 1."""
+    cap = 16
+    la = (ctypes.c_int64 * cap)()
+    ms = (ctypes.c_double * cap)()
+    fl = (ctypes.c_double * cap)()
+    by = (ctypes.c_double * cap)()
+    k = _lib.hpl_get_stats(la, ms, fl, by, cap)
+    return {STAT_CLASSES[i] if i < len(STAT_CLASSES) else str(i):
+            {"launches": int(la[i]), "ms": ms[i], "flops": fl[i], "bytes": by[i]} for i in range(k)}
+
+
+def hpl_reset_stats():
+    _lib.hpl_reset_stats()
+
+
+def hpl_release():
+    _check("hpl_release", _lib.hpl_release())
+
+
+def hpl_strerror(code):
+    return strerror(code)
+
+
+def hpl_last_error_detail():
+    return _lib.hpl_last_error_detail().decode()

@@ -1,0 +1,107 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function that
+include/hpl.h declares, and rejects invalid arguments on the host (-k) before
+any HIP call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hpl.h")
+
+h = pytest.importorskip("paper_2304_10397_amd.hpl", reason="libhplx.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hpl_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", h.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (hpl_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(h.lib(), n)
+
+
+P = ctypes.c_void_p
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def test_factor_argument_errors():
+    L = h.lib()
+    info = ctypes.c_int64(7)
+    assert L.hpl_factor(None, 10, 10, 64, FAKE, ctypes.byref(info), None) == -1
+    assert L.hpl_factor(FAKE, -1, 10, 64, FAKE, ctypes.byref(info), None) == -2
+    assert L.hpl_factor(FAKE, 2**31, 2**31, 64, FAKE, ctypes.byref(info), None) == -2
+    assert L.hpl_factor(FAKE, 10, 9, 64, FAKE, ctypes.byref(info), None) == -3
+    assert L.hpl_factor(FAKE, 10, 10, 0, FAKE, ctypes.byref(info), None) == -4
+    assert L.hpl_factor(FAKE, 10, 10, 1025, FAKE, ctypes.byref(info), None) == -4
+    assert L.hpl_factor(FAKE, 10, 10, 64, None, ctypes.byref(info), None) == -5
+    assert L.hpl_factor(FAKE, 10, 10, 64, FAKE, None, None) == -6
+    assert info.value == 7  # untouched on argument errors
+    assert L.hpl_factor(None, 0, 1, 64, None, ctypes.byref(info), None) == 0 and info.value == 0
+
+
+def test_solve_argument_errors():
+    L = h.lib()
+    assert L.hpl_solve(None, FAKE, FAKE, 1, 10, 10, 10, 0, None) == -1
+    assert L.hpl_solve(FAKE, None, FAKE, 1, 10, 10, 10, 0, None) == -2
+    assert L.hpl_solve(FAKE, FAKE, None, 1, 10, 10, 10, 0, None) == -3
+    assert L.hpl_solve(FAKE, FAKE, FAKE, -1, 10, 10, 10, 0, None) == -4
+    assert L.hpl_solve(FAKE, FAKE, FAKE, 1, -1, 10, 10, 0, None) == -5
+    assert L.hpl_solve(FAKE, FAKE, FAKE, 1, 10, 9, 10, 0, None) == -6
+    assert L.hpl_solve(FAKE, FAKE, FAKE, 1, 10, 10, 9, 0, None) == -7
+    assert L.hpl_solve(FAKE, FAKE, FAKE, 1, 10, 10, 10, 2, None) == -8
+    assert L.hpl_solve(FAKE, FAKE, FAKE, 0, 10, 10, 10, 0, None) == 0  # nothing to do
+
+
+def test_residual_generate_argument_errors():
+    L = h.lib()
+    out = (ctypes.c_double * 5)()
+    assert L.hpl_residual(None, 4, 4, FAKE, 4, FAKE, 4, 1, out, None) == -1
+    assert L.hpl_residual(FAKE, 4, 3, FAKE, 4, FAKE, 4, 1, out, None) == -3
+    assert L.hpl_residual(FAKE, 4, 4, FAKE, 4, FAKE, 4, 0, out, None) == -8
+    assert L.hpl_residual(FAKE, 4, 4, FAKE, 4, FAKE, 4, 1, None, None) == -9
+    assert L.hpl_residual_gen(1, -1, FAKE, 4, FAKE, 4, 1, out, None) == -2
+    assert L.hpl_residual_gen(1, 4, None, 4, FAKE, 4, 1, out, None) == -3
+    assert L.hpl_residual_gen(1, 4, FAKE, 4, FAKE, 4, 1, None, None) == -8
+    assert L.hpl_generate(1, 0, None, 4, 4, 4, None) == -3
+    assert L.hpl_generate(1, 0, FAKE, -1, 4, 4, None) == -4
+    assert L.hpl_generate(1, 0, FAKE, 4, -1, 4, None) == -5
+    assert L.hpl_generate(1, 0, FAKE, 4, 4, 3, None) == -6
+    assert L.hpl_generate(1, 0, FAKE, 0, 4, 1, None) == 0
+
+
+def test_options_roundtrip_and_rejects():
+    old = h.hpl_get_option(h.HPL_OPT_LOOKAHEAD)
+    h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 0)
+    assert h.hpl_get_option(h.HPL_OPT_LOOKAHEAD) == 0
+    h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, old)
+    with pytest.raises(ValueError):
+        h.hpl_set_option(h.HPL_OPT_PANEL_BASE, 12)
+    with pytest.raises(ValueError):
+        h.hpl_set_option(999, 1)
+    assert h.hpl_get_option(999) == -(2**63)
+
+
+def test_strerror():
+    assert h.hpl_strerror(0) == "success"
+    assert h.hpl_strerror(-4) == "invalid argument 4"
+    assert "HIP" in h.hpl_strerror(1)
+    assert h.hpl_strerror(12345) == "unknown error code"
+
+
+def test_stats_interface():
+    h.hpl_reset_stats()
+    st = h.hpl_get_stats()
+    assert set(st) >= {"gemm", "panel", "laswp", "trsm", "solve"}
+    assert all(v["launches"] == 0 for v in st.values())

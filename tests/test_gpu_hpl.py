@@ -1,0 +1,279 @@
+"""GPU parity tests: the HIP path through the C ABI against the CPU oracle."""
+import functools
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from gpu_util import hpl, padding_of, to_gpu, to_host, torch
+
+pytestmark = pytest.mark.gpu
+
+SEED = 2304
+XTOL = 1e-10  # ||x_gpu - x_oracle||inf / ||x_oracle||inf
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _defaults():
+    h = hpl()
+    keys = (h.HPL_OPT_LOOKAHEAD, h.HPL_OPT_PANEL_BASE, h.HPL_OPT_PANEL_WGS, h.HPL_OPT_SERIALIZE)
+    saved = {k: h.hpl_get_option(k) for k in keys}
+    yield
+    for k, v in saved.items():
+        h.hpl_set_option(k, v)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_solution(n, seed=SEED):
+    A = oracle.gen(seed, 0, n, n).copy(order="F")
+    b = oracle.gen(seed, 1, n, 1)[:, 0].copy()
+    LU = A.copy(order="F")
+    ipiv, info = oracle.lu(LU)
+    x = b.copy()
+    oracle.solve(LU, ipiv, x)
+    return A, b, LU, ipiv, info, x
+
+
+def gpu_system(n, ld=None, seed=SEED):
+    h = hpl()
+    A = h.colmajor(n, n, ld=ld, fill=float("nan"))
+    h.hpl_generate(seed, 0, A)
+    b = h.colmajor(n, 1)
+    h.hpl_generate(seed, 1, b)
+    return A, b
+
+
+# ---------------------------------------------------------------- generator
+@pytest.mark.parametrize("rows,cols,ld", [(1, 1, 1), (1024, 1024, 1024), (1031, 77, 1040), (5, 3000, 9)])
+@pytest.mark.parametrize("stream", [0, 1])
+def test_generate_bitwise(rows, cols, ld, stream):
+    h = hpl()
+    M = h.colmajor(rows, cols, ld=ld, fill=7.0)
+    h.hpl_generate(SEED, stream, M)
+    want = oracle.gen(SEED, stream, rows, cols)
+    got = to_host(M)
+    assert np.array_equal(got.view(np.int64), np.asfortranarray(want).view(np.int64))
+    pad = padding_of(M)
+    if pad is not None:
+        assert np.all(pad == 7.0)
+
+
+def test_generate_large_sampled():
+    # more than 2^31 elements: exercises the 64-bit linear index
+    h = hpl()
+    t = torch()
+    rows, cols = 65536, 33000
+    M = h.colmajor(rows, cols)
+    h.hpl_generate(99, 0, M)
+    rng = np.random.default_rng(1)
+    ii = rng.integers(0, rows, 2048)
+    jj = rng.integers(0, cols, 2048)
+    ii[-1], jj[-1] = rows - 1, cols - 1
+    got = M[t.from_numpy(ii).cuda(), t.from_numpy(jj).cuda()].cpu().numpy()
+    s0 = oracle.stream_key(99, 0)
+    want = np.array([oracle.uniform(s0, int(i) + int(j) * rows) for i, j in zip(ii, jj)])
+    assert np.array_equal(got, want)
+    del M
+    t.cuda.empty_cache()
+
+
+# ------------------------------------------------------- factor + solve
+SIZES = [1, 2, 63, 64, 65, 127, 1000, 1024, 1031]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("nb", [16, 32, 64, 128])
+@pytest.mark.parametrize("pad", [0, 7])
+def test_factor_solve_vs_oracle(n, nb, pad):
+    h = hpl()
+    A0, b0, LU_o, ipiv_o, info_o, x_o = oracle_solution(n)
+    A, b = gpu_system(n, ld=n + pad)
+    ipiv, info = h.hpl_factor(A, nb)
+    assert info == info_o == 0
+    piv = ipiv.cpu().numpy()
+    agree = float(np.mean(piv == ipiv_o))
+    print(f"n={n} nb={nb} pad={pad} pivot agreement {agree:.4f}")
+    assert agree == 1.0
+    LU = to_host(A)
+    assert np.max(np.abs(LU - LU_o)) <= 1e-11 * max(1.0, np.max(np.abs(LU_o)))
+    h.hpl_solve(A, ipiv, b)
+    x = b.cpu().numpy()[:, 0]
+    assert np.max(np.abs(x - x_o)) <= XTOL * np.max(np.abs(x_o))
+    A0g = to_gpu(A0)
+    bg = to_gpu(b0)
+    res = h.hpl_residual(A0g, b, bg)
+    assert res[0] < 16.0
+    if pad:
+        assert np.all(np.isnan(padding_of(A)))
+
+
+@pytest.mark.parametrize("n,nb,base", [(64, 16, 32), (200, 32, 16), (1000, 64, 32), (1031, 128, 64),
+                                       (777, 512, 32), (2100, 1024, 32), (3000, 256, 8)])
+def test_dyadic_bit_exact(n, nb, base):
+    h = hpl()
+    h.hpl_set_option(h.HPL_OPT_PANEL_BASE, base)
+    try:
+        A, L, U, perm = inputs.dyadic_factors(n, seed=n + nb)
+        Ag = to_gpu(A, ld=n + 3)
+        ipiv, info = h.hpl_factor(Ag, nb)
+    finally:
+        h.hpl_set_option(h.HPL_OPT_PANEL_BASE, 32)
+    assert info == 0
+    LU = to_host(Ag)
+    assert np.array_equal(np.tril(LU, -1) + np.eye(n), L)
+    assert np.array_equal(np.triu(LU), U)
+    order = np.arange(n)
+    for k, p in enumerate(ipiv.cpu().numpy()):
+        order[[k, p]] = order[[p, k]]
+    assert np.array_equal(order, perm)
+    rng = np.random.default_rng(n)
+    x = rng.integers(-9, 10, size=(n, 3)).astype(np.float64)
+    B = to_gpu(A @ x)
+    h.hpl_solve(Ag, ipiv, B)
+    assert np.array_equal(to_host(B), x)
+    Bt = to_gpu(A.T @ x)
+    h.hpl_solve(Ag, ipiv, Bt, trans=1)
+    assert np.array_equal(to_host(Bt), x)
+
+
+@pytest.mark.parametrize("n,nb", [(1031, 64), (2500, 128), (1500, 512)])
+def test_lookahead_and_serialize_bitwise(n, nb):
+    h = hpl()
+    results = []
+    for la, ser, wgs in [(1, 0, 128), (0, 0, 128), (1, 1, 128), (1, 0, 5), (1, 0, 1)]:
+        h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, la)
+        h.hpl_set_option(h.HPL_OPT_SERIALIZE, ser)
+        h.hpl_set_option(h.HPL_OPT_PANEL_WGS, wgs)
+        A, _ = gpu_system(n, seed=7)
+        ipiv, _ = h.hpl_factor(A, nb)
+        results.append((to_host(A), ipiv.cpu().numpy()))
+    h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 1)
+    h.hpl_set_option(h.HPL_OPT_SERIALIZE, 0)
+    h.hpl_set_option(h.HPL_OPT_PANEL_WGS, 128)
+    ref = results[0]
+    for LU, piv in results[1:]:
+        assert np.array_equal(piv, ref[1])
+        assert np.array_equal(LU.view(np.int64), ref[0].view(np.int64))
+
+
+@pytest.mark.parametrize("base", [8, 16, 64])
+def test_panel_base_variants_vs_oracle(base):
+    h = hpl()
+    n = 1000
+    _, _, LU_o, ipiv_o, _, x_o = oracle_solution(n)
+    h.hpl_set_option(h.HPL_OPT_PANEL_BASE, base)
+    try:
+        A, b = gpu_system(n)
+        ipiv, info = h.hpl_factor(A, 128)
+        h.hpl_solve(A, ipiv, b)
+    finally:
+        h.hpl_set_option(h.HPL_OPT_PANEL_BASE, 32)
+    assert np.array_equal(ipiv.cpu().numpy(), ipiv_o)
+    x = b.cpu().numpy()[:, 0]
+    assert np.max(np.abs(x - x_o)) <= XTOL * np.max(np.abs(x_o))
+
+
+@pytest.mark.parametrize("n,nrhs", [(300, 16), (1031, 4)])
+def test_multi_rhs_and_transposed_vs_oracle(n, nrhs):
+    h = hpl()
+    A0, _, LU_o, ipiv_o, _, _ = oracle_solution(n)
+    Bh = inputs.uniform_matrix(n, nrhs, n)
+    X_o = inputs.fortran(Bh)
+    oracle.solve(LU_o.copy(order="F"), ipiv_o, X_o)
+    XT_o = inputs.fortran(Bh)
+    oracle.solve(LU_o.copy(order="F"), ipiv_o, XT_o, trans=1)
+    A, _ = gpu_system(n)
+    ipiv, _ = h.hpl_factor(A, 64)
+    B = to_gpu(Bh, ld=n + 5)
+    h.hpl_solve(A, ipiv, B)
+    assert np.max(np.abs(to_host(B) - X_o)) <= XTOL * np.max(np.abs(X_o))
+    BT = to_gpu(Bh)
+    h.hpl_solve(A, ipiv, BT, trans=1)
+    assert np.max(np.abs(to_host(BT) - XT_o)) <= XTOL * np.max(np.abs(XT_o))
+
+
+# ----------------------------------------------------------- residual
+def test_residual_vs_oracle_and_regenerated():
+    h = hpl()
+    n = 777
+    A0 = oracle.gen(5, 0, n, n)
+    rng = np.random.default_rng(3)
+    X = rng.random((n, 3)) - 0.5
+    B = rng.random((n, 3)) - 0.5
+    want = oracle.residual(np.asfortranarray(A0), np.asfortranarray(X), np.asfortranarray(B))
+    Ag, _ = gpu_system(n, seed=5)
+    Xg, Bg = to_gpu(X, ld=n + 1), to_gpu(B)
+    got = h.hpl_residual(Ag, Xg, Bg)
+    assert got[2] == want[2] and got[3] == want[3] and got[4] == want[4]  # norms: same order, exact
+    assert abs(got[1] - want[1]) <= 4 * n * 2**-53 * want[2] * want[3]
+    assert got[0] == pytest.approx(want[0], rel=1e-9)
+    gen = h.hpl_residual_gen(5, n, Xg, Bg)
+    assert np.array_equal(gen, got)
+
+
+def test_residual_nan_fails():
+    h = hpl()
+    n = 64
+    Ag, bg = gpu_system(n)
+    x = torch().ones(n, dtype=torch().float64, device="cuda")
+    x[5] = float("nan")
+    out = h.hpl_residual(Ag, x, bg)
+    assert np.isnan(out[0])
+
+
+# ----------------------------------------------------- special inputs
+def test_singular_column_info():
+    h = hpl()
+    n = 300
+    A = oracle.gen(11, 0, n, n).copy(order="F")
+    A[:, 57] = 0.0
+    LU_o = A.copy(order="F")
+    ipiv_o, info_o = oracle.lu(LU_o)
+    Ag = to_gpu(A)
+    ipiv, info = h.hpl_factor(Ag, 32)
+    assert info == info_o == 58
+    assert np.array_equal(ipiv.cpu().numpy(), ipiv_o)
+    np.testing.assert_allclose(to_host(Ag), LU_o, atol=1e-11)
+
+
+def test_zero_matrix_and_tiny():
+    h = hpl()
+    Z = to_gpu(np.zeros((40, 40)))
+    ipiv, info = h.hpl_factor(Z, 16)
+    assert info == 1
+    assert np.array_equal(ipiv.cpu().numpy(), np.arange(40))
+    one = to_gpu(np.array([[4.0]]))
+    ipiv, info = h.hpl_factor(one, 64)
+    b = to_gpu(np.array([2.0]))
+    h.hpl_solve(one, ipiv, b)
+    assert info == 0 and b.cpu().item() == 0.5
+
+
+def test_identity_and_permutation_exact():
+    h = hpl()
+    P, perm = inputs.permutation_matrix(500, 2)
+    Pg = to_gpu(P)
+    ipiv, info = h.hpl_factor(Pg, 64)
+    assert info == 0
+    assert np.array_equal(to_host(Pg), np.eye(500))
+    Ig = to_gpu(np.eye(300))
+    ipiv, _ = h.hpl_factor(Ig, 32)
+    assert np.array_equal(ipiv.cpu().numpy(), np.arange(300))
+    assert np.array_equal(to_host(Ig), np.eye(300))
+
+
+def test_column_dominant_no_interchanges():
+    h = hpl()
+    A = inputs.column_dominant(700, 4)
+    Ag = to_gpu(A)
+    ipiv, _ = h.hpl_factor(Ag, 64)
+    assert np.array_equal(ipiv.cpu().numpy(), np.arange(700))
+
+
+def test_n_zero_is_noop():
+    h = hpl()
+    t = torch()
+    A = t.empty((0, 0), dtype=t.float64, device="cuda")
+    ipiv, info = h.hpl_factor(A, 64)
+    assert info == 0 and ipiv.numel() == 0
