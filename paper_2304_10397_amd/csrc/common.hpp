@@ -109,6 +109,12 @@ struct SwapPlan {
 };
 int launch_swap_plan(const int32_t *ipiv, int cnt, int64_t r0, int64_t nrows, bool reverse, SwapPlan plan,
                      hipStream_t st);
+// Plans of all kMaxSwaps-sized chunks of ipiv[0..total) at once (chunk q covers
+// rows r0 + q*kMaxSwaps ...), laid out with stride kPlanStride int32 per chunk:
+// rows at [0, 2*kMaxSwaps), srcslot at [2*kMaxSwaps, 4*kMaxSwaps), nslots at 4*kMaxSwaps.
+constexpr int kPlanStride = 4 * kMaxSwaps + 64;
+int launch_swap_plans_all(const int32_t *ipiv, int64_t total, int64_t r0, int64_t nrows, bool reverse,
+                          int32_t *plans, int *err, hipStream_t st);
 // Applies a plan to columns [col0, col0+ncols) of A.
 int launch_laswp(double *A, int64_t lda, int64_t col0, int64_t ncols, SwapPlan plan,
                  hipStream_t st);
@@ -130,12 +136,14 @@ int launch_panel_leaf(double *A, int64_t lda, int64_t c, int64_t m, int w, int32
 int leaf_groups(int64_t m, int w, int gmax);
 
 // solve.hip
-int launch_trsv_block(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs,
-                      int64_t r0, int64_t bs, int mode, hipStream_t st);
-int launch_gemv_update(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs,
+// One diagonal block [r0, r0+bs) (bs <= 64, nrhs <= 64): finish it, then update
+// rows [row_begin, row_end).  mode: 0 = L unit lower (forward), 1 = U upper
+// (backward), 2 = U^T (forward), 3 = L^T unit (backward).
+int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs,
                        int64_t r0, int64_t bs, int64_t row_begin, int64_t row_end, int mode,
                        hipStream_t st);
-// mode: 0 = L unit lower (forward), 1 = U upper (backward), 2 = U^T (forward),
-//       3 = L^T unit (backward)
+// Applies nchunks plans (kPlanStride layout) to B in order, or in reverse order.
+int launch_apply_plans_seq(double *B, int64_t ldb, int64_t nrhs, const int32_t *plans,
+                           int64_t nchunks, bool reverse, hipStream_t st);
 
 }  // namespace hplx

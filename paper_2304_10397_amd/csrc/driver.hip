@@ -121,6 +121,8 @@ struct Device {
     int64_t red_cap = 0;
     unsigned long long *hbuf = nullptr;  // pinned host staging
     int *pivot_err = nullptr;            // raised by the plan kernel on an out-of-range pivot
+    int32_t *splans = nullptr;           // interchange plans of every chunk of ipiv (solve)
+    int64_t splan_cap = 0;
     std::vector<hipEvent_t> ev_pool;      // timing events
 };
 
@@ -451,48 +453,55 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
     return HPL_OK;
 }
 
+static int ensure_solve_plans(Device *d, int64_t nchunks)
+{
+    if (d->splan_cap >= nchunks) return HPL_OK;
+    if (d->splans) HPLX_TRY(hipFree(d->splans));
+    d->splans = nullptr;
+    d->splan_cap = 0;
+    if (hipMalloc((void **)&d->splans, sizeof(int32_t) * (size_t)kPlanStride * (size_t)nchunks) != hipSuccess)
+        HPLX_FAIL(HPL_ERR_NOMEM, "solve plan buffer allocation failed");
+    d->splan_cap = nchunks;
+    return HPL_OK;
+}
+
 static int solve_impl(Device *d, const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, int64_t n,
                       int64_t lda, int64_t ldb, int trans, hipStream_t st)
 {
     Timer tm(d, opt_timing.load() != 0);
-    const int64_t bs = 64;
+    const int64_t bs = 64;     // diagonal block (one row per lane)
+    const int64_t rhs_chunk = 64;
+    const int64_t nchunks = (n + kMaxSwaps - 1) / kMaxSwaps;
+    HPLX_PROPAGATE(ensure_solve_plans(d, nchunks));
     int id = tm.begin(ST_SOLVE, st);
     auto swaps = [&](bool reverse) -> int {
-        const int64_t nchunk = (n + kMaxSwaps - 1) / kMaxSwaps;
-        for (int64_t qq = 0; qq < nchunk; ++qq) {
-            const int64_t q = reverse ? nchunk - 1 - qq : qq;
-            const int64_t k0 = q * kMaxSwaps;
-            const int64_t cnt = (n - k0) < kMaxSwaps ? (n - k0) : kMaxSwaps;
-            HPLX_PROPAGATE(launch_swap_plan(ipiv + k0, (int)cnt, k0, n, reverse, d->psolve, st));
-            HPLX_PROPAGATE(launch_laswp(B, ldb, 0, nrhs, d->psolve, st));
-        }
-        return HPL_OK;
+        HPLX_PROPAGATE(launch_swap_plans_all(ipiv, n, 0, n, reverse, d->splans, d->pivot_err, st));
+        return launch_apply_plans_seq(B, ldb, nrhs, d->splans, nchunks, reverse, st);
     };
-    auto forward = [&](int mode) -> int {
-        for (int64_t r0 = 0; r0 < n; r0 += bs) {
+    auto sweep = [&](int mode, double *Bc, int64_t nr) -> int {
+        const bool fwd = (mode == 0 || mode == 2);
+        const int64_t nblk = (n + bs - 1) / bs;
+        for (int64_t q = 0; q < nblk; ++q) {
+            const int64_t r0 = (fwd ? q : nblk - 1 - q) * bs;
             const int64_t b = (n - r0) < bs ? (n - r0) : bs;
-            HPLX_PROPAGATE(launch_trsv_block(LU, lda, B, ldb, nrhs, r0, b, mode, st));
-            HPLX_PROPAGATE(launch_gemv_update(LU, lda, B, ldb, nrhs, r0, b, r0 + b, n, mode, st));
+            const int64_t rb = fwd ? r0 + b : 0, re = fwd ? n : r0;
+            HPLX_PROPAGATE(launch_solve_block(LU, lda, Bc, ldb, nr, r0, b, rb, re, mode, st));
         }
         return HPL_OK;
     };
-    auto backward = [&](int mode) -> int {
-        for (int64_t r0 = ((n - 1) / bs) * bs; r0 >= 0; r0 -= bs) {
-            const int64_t b = (n - r0) < bs ? (n - r0) : bs;
-            HPLX_PROPAGATE(launch_trsv_block(LU, lda, B, ldb, nrhs, r0, b, mode, st));
-            HPLX_PROPAGATE(launch_gemv_update(LU, lda, B, ldb, nrhs, r0, b, 0, r0, mode, st));
+    if (trans == 0) HPLX_PROPAGATE(swaps(false));
+    for (int64_t c0 = 0; c0 < nrhs; c0 += rhs_chunk) {
+        const int64_t nr = (nrhs - c0) < rhs_chunk ? (nrhs - c0) : rhs_chunk;
+        double *Bc = B + off(0, c0, ldb);
+        if (trans == 0) {
+            HPLX_PROPAGATE(sweep(0, Bc, nr));
+            HPLX_PROPAGATE(sweep(1, Bc, nr));
+        } else {
+            HPLX_PROPAGATE(sweep(2, Bc, nr));
+            HPLX_PROPAGATE(sweep(3, Bc, nr));
         }
-        return HPL_OK;
-    };
-    if (trans == 0) {
-        HPLX_PROPAGATE(swaps(false));
-        HPLX_PROPAGATE(forward(0));
-        HPLX_PROPAGATE(backward(1));
-    } else {
-        HPLX_PROPAGATE(forward(2));
-        HPLX_PROPAGATE(backward(3));
-        HPLX_PROPAGATE(swaps(true));
     }
+    if (trans == 1) HPLX_PROPAGATE(swaps(true));
     HPLX_PROPAGATE(tm.end(id, st, 2.0 * (double)n * (double)n * (double)nrhs, 8.0 * (double)n * (double)n));
     HPLX_TRY(hipMemcpyAsync(d->hbuf + 2, d->pivot_err, sizeof(int), hipMemcpyDeviceToHost, st));
     HPLX_TRY(hipStreamSynchronize(st));
@@ -713,6 +722,7 @@ int hpl_release(void)
         (void)hipEventDestroy(d.ev_end);
         (void)hipStreamDestroy(d.sp);
         if (d.red) (void)hipFree(d.red);
+        if (d.splans) (void)hipFree(d.splans);
         if (d.hbuf) (void)hipHostFree(d.hbuf);
         (void)hipFree(d.ws);
         d = Device();

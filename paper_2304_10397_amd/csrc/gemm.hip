@@ -9,7 +9,8 @@
 // gfx950 design
 //  * v_mfma_f64_16x16x4_f64: a wave multiplies a 16x4 by a 4x16 block into a
 //    16x16 FP64 accumulator (4 doubles per lane).  Lane l supplies
-//    A[l%16][l/16] and B[l/16][l%16] and holds D[4*(l/16)+r][l%16], r = 0..3.
+//    A[l%16][l/16] and B[l/16][l%16] and holds D[l/16 + 4r][l%16], r = 0..3
+//    (checked on the hardware).
 //  * Block tile BM x BN, K staged BK = 16 at a time through double-buffered
 //    LDS (one barrier per stage); each wave owns a (BM/WM) x (BN/WN) sub-tile
 //    of accumulators that stay in registers for the whole K loop.
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
 
     // Accumulators start from C.
     dbl4 acc[FM][FN];
-    const int crow0 = wm * TM + 4 * (lane >> 4);
+    const int crow0 = wm * TM + (lane >> 4);
     const int ccol0 = wn * TN + (lane & 15);
     double *pc = C + off(m0 + crow0, n0 + ccol0, ldc);
     const int64_t c_step = 16 * ldc;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
         for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                acc[fm][fn][r] = (col_ok && crow0 + 16 * fm + r < mrem) ? pcol[16 * fm + r] : 0.0;
+                acc[fm][fn][r] = (col_ok && crow0 + 16 * fm + 4 * r < mrem) ? pcol[16 * fm + 4 * r] : 0.0;
     }
 
     store_stage(0);
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
         for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (col_ok && crow0 + 16 * fm + r < mrem) pcol[16 * fm + r] = acc[fm][fn][r];
+                if (col_ok && crow0 + 16 * fm + 4 * r < mrem) pcol[16 * fm + 4 * r] = acc[fm][fn][r];
     }
 }
 

@@ -24,13 +24,23 @@ constexpr int kPlanThreads = kMaxSwaps;  // one thread per interchange
 constexpr int kLwCols = 8;               // columns per laswp workgroup
 constexpr int kLwThreads = 256;
 
-__global__ __launch_bounds__(kPlanThreads) void swap_plan_kernel(const int32_t *__restrict__ ipiv, int cnt,
-                                                                 int64_t r0, int64_t nrows, int reverse,
-                                                                 int32_t *__restrict__ rows_out,
-                                                                 int32_t *__restrict__ src_out,
-                                                                 int32_t *__restrict__ nslots_out,
+// Workgroup q builds the plan of chunk q: interchanges ipiv[q*kMaxSwaps ...] of
+// rows r0 + q*kMaxSwaps ..., output at the given pointers + q*stride.
+__global__ __launch_bounds__(kPlanThreads) void swap_plan_kernel(const int32_t *__restrict__ ipiv_all, int64_t total,
+                                                                 int64_t r0_all, int64_t nrows, int reverse,
+                                                                 int32_t *__restrict__ rows_all,
+                                                                 int32_t *__restrict__ src_all,
+                                                                 int32_t *__restrict__ nslots_all, int64_t stride,
                                                                  int *__restrict__ err)
 {
+    const int64_t q = blockIdx.x;
+    const int32_t *ipiv = ipiv_all + q * kMaxSwaps;
+    const int cnt = (int)((total - q * kMaxSwaps) < kMaxSwaps ? (total - q * kMaxSwaps) : kMaxSwaps);
+    const int64_t r0 = r0_all + q * kMaxSwaps;
+    int32_t *rows_out = rows_all + q * stride;
+    int32_t *src_out = src_all + q * stride;
+    int32_t *nslots_out = nslots_all + q * stride;
+
     __shared__ int piv[kMaxSwaps];        // target row relative to r0 (>= k)
     __shared__ int bslot[kMaxSwaps];      // slot of the target row
     __shared__ int cur[2 * kMaxSwaps];    // content (slot id) currently in slot s
@@ -138,8 +148,21 @@ int launch_swap_plan(const int32_t *ipiv, int cnt, int64_t r0, int64_t nrows, bo
                      hipStream_t st)
 {
     if (cnt <= 0 || cnt > kMaxSwaps) return HPL_ERR_INTERNAL;
-    hipLaunchKernelGGL(swap_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, ipiv, cnt, r0, nrows, reverse ? 1 : 0,
-                       plan.rows, plan.srcslot, plan.nslots, plan.err);
+    hipLaunchKernelGGL(swap_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, ipiv, (int64_t)cnt, r0, nrows,
+                       reverse ? 1 : 0, plan.rows, plan.srcslot, plan.nslots, (int64_t)0, plan.err);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_swap_plans_all(const int32_t *ipiv, int64_t total, int64_t r0, int64_t nrows, bool reverse,
+                          int32_t *plans, int *err, hipStream_t st)
+{
+    if (total <= 0) return HPL_OK;
+    const int64_t nchunks = (total + kMaxSwaps - 1) / kMaxSwaps;
+    if (nchunks > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(swap_plan_kernel, dim3((unsigned)nchunks), dim3(kPlanThreads), 0, st, ipiv, total, r0, nrows,
+                       reverse ? 1 : 0, plans, plans + 2 * kMaxSwaps, plans + 4 * kMaxSwaps, (int64_t)kPlanStride,
+                       err);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }

@@ -1,150 +1,160 @@
 // solve.hip -- triangular solves with the factors (Sec. II: after A = P L U,
 // A x = b becomes U x = L^{-1} P^{-1} b and x follows by applying U^{-1}).
 //
-// Blocked column sweep over diagonal blocks of bs rows:
-//   trsv_block_kernel  one workgroup solves the bs x bs diagonal block for all
-//                      right-hand sides (LDS-resident, one barrier per row);
-//   gemv_update_kernel subtracts the block's contribution from the rows not
-//                      yet solved.  Reading the factors once is the whole
-//                      cost, so the kernel is HBM-bound: for L and U the
-//                      column segments are read coalesced one row per lane;
-//                      for the transposed solves a wave reads one column
-//                      segment and reduces it with shuffles.
+// The solve reads the n x n factors once (HBM-bound, 2 n^2 nrhs flops), but its
+// rows depend on each other, so it is organized as a sweep over diagonal blocks
+// of kBs = 64 rows with ONE launch per block:
+//   * every workgroup of the launch first finishes the diagonal block itself:
+//     one wave per right-hand side, lane r holds x_r, and x_k reaches the other
+//     lanes by shuffle -- no barrier, no second launch (workgroup 0 also
+//     stores the finished rows);
+//   * then the workgroup subtracts the block's contribution from its share of
+//     the rows not yet solved (a skinny GEMV: for L and U one row per lane,
+//     columns read coalesced; for the transposed operators one contiguous
+//     column segment per lane).
 // mode 0: L unit lower, forward.  mode 1: U upper, backward.
 // mode 2: U^T (lower, diagonal u_ii), forward.  mode 3: L^T unit upper, backward.
+//
+// Interchanges on B: all chunk plans (see laswp.hip) are computed by one
+// launch in parallel, then one workgroup applies them in order (or in reverse
+// order for A^T X = B).
 #include "common.hpp"
 
 namespace hplx {
 
 namespace {
 
-constexpr int kSvBS = 64;      // diagonal block rows (max)
-constexpr int kSvRhs = 16;     // right-hand sides per pass
-constexpr int kSvThreads = 256;
+constexpr int kBs = 64;          // diagonal block rows (one per lane)
+constexpr int kSvThreads = 256;  // 4 waves
+constexpr int kSvRhs = 8;        // right-hand sides per pass of the GEMV
+constexpr int kRowsPerThread = 4;
 
-// element (r, c) of the operator T_op of the mode, inside the diagonal block
-__device__ __forceinline__ double top_elem(const double *T, int64_t ldt, int64_t r0, int r, int c, int mode)
+// T_op(r, c) of the mode for global indices (r, c)
+__device__ __forceinline__ double top(const double *T, int64_t ldt, int64_t r, int64_t c, int mode)
 {
-    // modes 0,1 use T(r, c); modes 2,3 use T(c, r)
-    return (mode < 2) ? T[off(r0 + r, r0 + c, ldt)] : T[off(r0 + c, r0 + r, ldt)];
+    return (mode < 2) ? T[off(r, c, ldt)] : T[off(c, r, ldt)];
 }
 
-__global__ __launch_bounds__(kSvThreads) void trsv_block_kernel(const double *__restrict__ T, int64_t ldt,
-                                                                double *__restrict__ B, int64_t ldb, int64_t nrhs,
-                                                                int64_t r0, int bs, int mode)
+__global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *__restrict__ T, int64_t ldt,
+                                                                 double *__restrict__ B, int64_t ldb, int64_t nrhs,
+                                                                 int64_t r0, int bs, int64_t row_begin,
+                                                                 int64_t row_end, int mode)
 {
-    __shared__ double Ts[kSvBS][kSvBS + 1];
-    __shared__ double X[kSvBS][kSvRhs];
-    __shared__ double Xo[kSvBS][kSvRhs];
-    const int t = threadIdx.x;
-    for (int e = t; e < bs * bs; e += kSvThreads) {
-        const int r = e % bs, c = e / bs;
-        Ts[r][c] = top_elem(T, ldt, r0, r, c, mode);
-    }
+    extern __shared__ double Y[];  // [nrhs][kBs] solved block
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const bool lower = (mode == 0 || mode == 2);
     const bool unit = (mode == 0 || mode == 3);
-    for (int64_t cr0 = 0; cr0 < nrhs; cr0 += kSvRhs) {
-        const int nr = (int)((nrhs - cr0) < kSvRhs ? (nrhs - cr0) : kSvRhs);
-        __syncthreads();
-        for (int e = t; e < bs * kSvRhs; e += kSvThreads) {
-            const int r = e % bs, c = e / bs;
-            X[r][c] = (c < nr) ? B[off(r0 + r, cr0 + c, ldb)] : 0.0;
-        }
-        __syncthreads();
+
+    // ---- 1. diagonal block, one wave per right-hand side
+    for (int64_t c = wid; c < nrhs; c += kSvThreads / 64) {
+        double x = (lane < bs) ? B[off(r0 + lane, c, ldb)] : 0.0;
         for (int s = 0; s < bs; ++s) {
-            const int kcol = lower ? s : bs - 1 - s;  // row being finished
-            for (int e = t; e < bs * kSvRhs; e += kSvThreads) {
-                const int r = e % bs, c = e / bs;
-                double xk = X[kcol][c];
-                if (!unit) xk = xk / Ts[kcol][kcol];
-                if (r == kcol) Xo[r][c] = xk;
-                const bool below = lower ? (r > kcol) : (r < kcol);
-                if (below) X[r][c] = X[r][c] - Ts[r][kcol] * xk;
-            }
-            __syncthreads();
+            const int k = lower ? s : bs - 1 - s;
+            double xk = __shfl(x, k, 64);
+            if (!unit) xk = xk / top(T, ldt, r0 + k, r0 + k, mode);
+            if (lane == k) x = xk;
+            const bool below = lower ? (lane > k) : (lane < k);
+            if (below && lane < bs) x = x - top(T, ldt, r0 + lane, r0 + k, mode) * xk;
         }
-        for (int e = t; e < bs * kSvRhs; e += kSvThreads) {
-            const int r = e % bs, c = e / bs;
-            if (c < nr) B[off(r0 + r, cr0 + c, ldb)] = Xo[r][c];
+        if (lane < bs) {
+            Y[c * kBs + lane] = x;
+            if (blockIdx.x == 0) B[off(r0 + lane, c, ldb)] = x;
+        }
+    }
+    __syncthreads();
+    if (row_end <= row_begin) return;
+
+    // ---- 2. update of this workgroup's rows
+    const int64_t rows_per_wg = (int64_t)kSvThreads * kRowsPerThread;
+    const int64_t wb = row_begin + (int64_t)blockIdx.x * rows_per_wg;
+    for (int64_t c0 = 0; c0 < nrhs; c0 += kSvRhs) {
+        const int nr = (int)((nrhs - c0) < kSvRhs ? (nrhs - c0) : kSvRhs);
+#pragma unroll
+        for (int q = 0; q < kRowsPerThread; ++q) {
+            const int64_t i = wb + t + (int64_t)q * kSvThreads;
+            if (i >= row_end) break;
+            double acc[kSvRhs];
+#pragma unroll
+            for (int c = 0; c < kSvRhs; ++c) acc[c] = 0.0;
+            if (mode < 2) {
+                const double *col = T + off(i, r0, ldt);
+                for (int k = 0; k < bs; ++k) {
+                    const double a = col[(size_t)k * (size_t)ldt];
+#pragma unroll
+                    for (int c = 0; c < kSvRhs; ++c)
+                        if (c < nr) acc[c] += a * Y[(c0 + c) * kBs + k];
+                }
+            } else {
+                const double *seg = T + off(r0, i, ldt);  // contiguous column segment
+                for (int k = 0; k < bs; ++k) {
+                    const double a = seg[k];
+#pragma unroll
+                    for (int c = 0; c < kSvRhs; ++c)
+                        if (c < nr) acc[c] += a * Y[(c0 + c) * kBs + k];
+                }
+            }
+            for (int c = 0; c < nr; ++c) B[off(i, c0 + c, ldb)] -= acc[c];
         }
     }
 }
 
-// rows [row_begin, row_end) of B -= T_op(rows, block) * X(block) where block = [r0, r0+bs).
-__global__ __launch_bounds__(kSvThreads) void gemv_update_kernel(const double *__restrict__ T, int64_t ldt,
-                                                                 double *__restrict__ B, int64_t ldb,
-                                                                 int64_t nrhs, int64_t r0, int bs,
-                                                                 int64_t row_begin, int64_t row_end, int mode)
+// Applies the chunk plans in order (reverse = 0) or reverse order to B's columns.
+constexpr int kApThreads = 1024;
+constexpr int kApRhs = 16;
+__global__ __launch_bounds__(kApThreads) void apply_plans_seq_kernel(double *__restrict__ B, int64_t ldb,
+                                                                     int64_t nrhs, const int32_t *__restrict__ plans,
+                                                                     int64_t nchunks, int reverse)
 {
-    __shared__ double X[kSvBS][kSvRhs];
-    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    for (int64_t cr0 = 0; cr0 < nrhs; cr0 += kSvRhs) {
-        const int nr = (int)((nrhs - cr0) < kSvRhs ? (nrhs - cr0) : kSvRhs);
-        __syncthreads();
-        for (int e = t; e < bs * kSvRhs; e += kSvThreads) {
-            const int r = e % bs, c = e / bs;
-            X[r][c] = (c < nr) ? B[off(r0 + r, cr0 + c, ldb)] : 0.0;
-        }
-        __syncthreads();
-        if (mode < 2) {
-            // one row per thread; T(i, r0 + q) read coalesced across lanes
-            const int64_t i = row_begin + (int64_t)blockIdx.x * kSvThreads + t;
-            if (i < row_end) {
-                double acc[kSvRhs];
-#pragma unroll
-                for (int c = 0; c < kSvRhs; ++c) acc[c] = 0.0;
-                for (int q = 0; q < bs; ++q) {
-                    const double a = T[off(i, r0 + q, ldt)];
-#pragma unroll
-                    for (int c = 0; c < kSvRhs; ++c) acc[c] += a * X[q][c];
-                }
-                for (int c = 0; c < nr; ++c) B[off(i, cr0 + c, ldb)] -= acc[c];
+    __shared__ double vals[2 * kMaxSwaps * kApRhs];
+    const int t = threadIdx.x;
+    for (int64_t qq = 0; qq < nchunks; ++qq) {
+        const int64_t q = reverse ? nchunks - 1 - qq : qq;
+        const int32_t *rows = plans + (size_t)q * kPlanStride;
+        const int32_t *src = rows + 2 * kMaxSwaps;
+        const int ns = rows[4 * kMaxSwaps];
+        for (int64_t c0 = 0; c0 < nrhs; c0 += kApRhs) {
+            const int nr = (int)((nrhs - c0) < kApRhs ? (nrhs - c0) : kApRhs);
+            for (int e = t; e < ns * nr; e += kApThreads) {
+                const int s = e % ns, c = e / ns;
+                vals[c * 2 * kMaxSwaps + s] = B[off(rows[s], c0 + c, ldb)];
             }
-        } else {
-            // one row per wave; T(r0 + q, i) is a contiguous column segment
-            const int64_t i = row_begin + (int64_t)blockIdx.x * (kSvThreads / 64) + wid;
-            if (i < row_end) {
-                double acc[kSvRhs];
-#pragma unroll
-                for (int c = 0; c < kSvRhs; ++c) acc[c] = 0.0;
-                for (int q = lane; q < bs; q += 64) {
-                    const double a = T[off(r0 + q, i, ldt)];
-#pragma unroll
-                    for (int c = 0; c < kSvRhs; ++c) acc[c] += a * X[q][c];
-                }
-#pragma unroll
-                for (int c = 0; c < kSvRhs; ++c)
-                    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
-                if (lane == 0)
-                    for (int c = 0; c < nr; ++c) B[off(i, cr0 + c, ldb)] -= acc[c];
+            __syncthreads();
+            for (int e = t; e < ns * nr; e += kApThreads) {
+                const int s = e % ns, c = e / ns;
+                const int ss = src[s];
+                if (ss != s) B[off(rows[s], c0 + c, ldb)] = vals[c * 2 * kMaxSwaps + ss];
             }
+            __syncthreads();
         }
     }
 }
 
 }  // namespace
 
-int launch_trsv_block(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs, int64_t r0, int64_t bs,
-                      int mode, hipStream_t st)
+int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs, int64_t r0, int64_t bs,
+                       int64_t row_begin, int64_t row_end, int mode, hipStream_t st)
 {
     if (bs <= 0 || nrhs <= 0) return HPL_OK;
-    if (bs > kSvBS) return HPL_ERR_INTERNAL;
-    hipLaunchKernelGGL(trsv_block_kernel, dim3(1), dim3(kSvThreads), 0, st, T, ldt, B, ldb, nrhs, r0, (int)bs, mode);
+    if (bs > kBs) return HPL_ERR_INTERNAL;
+    const int64_t rows = row_end > row_begin ? row_end - row_begin : 0;
+    const int64_t per = (int64_t)kSvThreads * kRowsPerThread;
+    int64_t g = (rows + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    const size_t lds = sizeof(double) * (size_t)kBs * (size_t)nrhs;
+    if (lds > 64 * 1024) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(solve_block_kernel, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs, r0,
+                       (int)bs, row_begin, row_end, mode);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
 
-int launch_gemv_update(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs, int64_t r0, int64_t bs,
-                       int64_t row_begin, int64_t row_end, int mode, hipStream_t st)
+int launch_apply_plans_seq(double *B, int64_t ldb, int64_t nrhs, const int32_t *plans, int64_t nchunks, bool reverse,
+                           hipStream_t st)
 {
-    if (bs <= 0 || nrhs <= 0 || row_end <= row_begin) return HPL_OK;
-    if (bs > kSvBS) return HPL_ERR_INTERNAL;
-    const int64_t rows = row_end - row_begin;
-    const int64_t per = (mode < 2) ? kSvThreads : kSvThreads / 64;
-    const int64_t g = (rows + per - 1) / per;
-    if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
-    hipLaunchKernelGGL(gemv_update_kernel, dim3((unsigned)g), dim3(kSvThreads), 0, st, T, ldt, B, ldb, nrhs, r0,
-                       (int)bs, row_begin, row_end, mode);
+    if (nchunks <= 0 || nrhs <= 0) return HPL_OK;
+    hipLaunchKernelGGL(apply_plans_seq_kernel, dim3(1), dim3(kApThreads), 0, st, B, ldb, nrhs, plans, nchunks,
+                       reverse ? 1 : 0);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }

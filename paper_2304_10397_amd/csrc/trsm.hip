@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
             const int cc = 16 * cb + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int rr = 16 * rb + 4 * (lane >> 4) + r;
+                const int rr = 16 * rb + (lane >> 4) + 4 * r;  // MFMA result layout: row l/16 + 4r
                 acc[q][cb][r] = (rb < nrb && rr < nbk && cc < crem) ? B[off(rr, c0 + cc, ldb)] : 0.0;
             }
         }
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
 #pragma unroll
                 for (int cb = 0; cb < kTrCB; ++cb)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Xs[par][4 * (lane >> 4) + r][16 * cb + (lane & 15)] = acc[qq][cb][r];
+                    for (int r = 0; r < 4; ++r) Xs[par][(lane >> 4) + 4 * r][16 * cb + (lane & 15)] = acc[qq][cb][r];
             }
         }
         if (t >= 256) {

@@ -42,6 +42,11 @@ class HplError(RuntimeError):
 
 
 def _load():
+    # PyTorch (ROCm build) ships its own HIP runtime.  Load it first so that
+    # libhplx's dependency on libamdhip64.so.7 resolves to that same, already
+    # loaded runtime: two runtimes in one process would not share devices,
+    # streams or allocations.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"libhplx.so not found at {LIB_PATH}; build it with "
