@@ -137,7 +137,7 @@ int hpl_generate(uint64_t seed, uint64_t stream_id, double *M, int64_t rows, int
 enum hpl_option {
     HPL_OPT_LOOKAHEAD = 1,   /* 0 or 1 (default 1): depth of the panel look-ahead */
     HPL_OPT_PANEL_BASE = 2,  /* leaf width of the recursive panel: 8, 16, 32 or 64 (default 32) */
-    HPL_OPT_PANEL_WGS = 3,   /* max workgroups of the panel leaf kernel, 1..256 (default 64) */
+    HPL_OPT_PANEL_WGS = 3,   /* max workgroups of the panel leaf kernel, 1..256 (default 256) */
     HPL_OPT_TIMING = 4,      /* 1: time every kernel with HIP events (see hpl_get_stats) */
     HPL_OPT_PROGRESS = 5,    /* k > 0: print a progress line to stderr every k panels */
     HPL_OPT_SERIALIZE = 6,   /* 1: run every step on one stream (debug; bit-identical) */

@@ -126,14 +126,24 @@ struct LeafSync {
     double *slots;                // [2][kLeafMaxWGs][kLeafSlot]
     double *top;                  // [2][kLeafMaxW]
     unsigned long long *info;     // min over singular columns of (global col + 1)
+    unsigned long long *tslots;   // tagged words of the register leaf: [2][kLeafMaxWGs][kLeafSlotWords]
+    unsigned long long *ttop;     // tagged diagonal row: [2][64]
 };
 constexpr int kLeafMaxW = 64;
 constexpr int kLeafMaxWGs = 256;
 constexpr int kLeafSlot = kLeafMaxW + 2;
+constexpr int kLeafSlotWords = 2 * 32 + 3 + 5;  // tagged words per slot of the register leaf (72)
 int launch_panel_leaf(double *A, int64_t lda, int64_t c, int64_t m, int w, int32_t *ipiv,
                       LeafSync sync, unsigned long long bar_base, int G, hipStream_t st);
 // Number of workgroups the leaf kernel uses for m rows, width w, limit gmax.
 int leaf_groups(int64_t m, int w, int gmax);
+// Register-resident leaf (w <= 32, at most 1024 rows per workgroup): number of
+// workgroups for m rows, or 0 if it does not apply.  The launch also runs the
+// in-leaf interchanges of the finished L columns.  tag0 must differ from every
+// tag used before (tags tag0+1 .. tag0+w are consumed).
+int leaf_reg_groups(int64_t m, int w);
+int launch_leaf_reg(double *A, int64_t lda, int64_t c, int64_t m, int w, int32_t *ipiv, LeafSync sync,
+                    uint32_t tag0, int G, hipStream_t st);
 
 // solve.hip
 // One diagonal block [r0, r0+bs) (bs <= 64, nrhs <= 64): finish it, then update

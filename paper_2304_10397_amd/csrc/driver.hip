@@ -60,7 +60,7 @@ void note_error(const char *what, const char *file, int line)
 // ---------------------------------------------------------------------------
 static std::atomic<int64_t> opt_lookahead{1};
 static std::atomic<int64_t> opt_panel_base{32};
-static std::atomic<int64_t> opt_panel_wgs{128};
+static std::atomic<int64_t> opt_panel_wgs{256};
 static std::atomic<int64_t> opt_timing{0};
 static std::atomic<int64_t> opt_progress{0};
 static std::atomic<int64_t> opt_serialize{0};
@@ -114,6 +114,8 @@ struct Device {
     void *ws = nullptr;
     LeafSync sync{};
     unsigned long long bar_epoch = 0;
+    uint32_t tag_epoch = 0;   // register-leaf tags used so far (tag 0 is never used)
+    size_t tag_area_bytes = 0;
     SwapPlan ring[kRing][kMaxChunks]{};
     SwapPlan pint{};  // plans inside the recursive panel
     SwapPlan psolve{};
@@ -202,6 +204,9 @@ static int init_device(Device &d, int id)
     const size_t o_perr = o; o += 256;
     const size_t o_slots = o; o = align_up(o + sizeof(double) * 2 * kLeafMaxWGs * kLeafSlot, 256);
     const size_t o_top = o; o = align_up(o + sizeof(double) * 2 * kLeafMaxW, 256);
+    const size_t o_tslots = o; o = align_up(o + sizeof(unsigned long long) * 2 * kLeafMaxWGs * kLeafSlotWords, 256);
+    const size_t o_ttop = o; o = align_up(o + sizeof(unsigned long long) * 2 * 64, 256);
+    d.tag_area_bytes = o - o_tslots;
     const size_t o_plans = o; o += plan_bytes * (kRing * kMaxChunks + 2);
     void *ws = nullptr;
     if (hipMalloc(&ws, o) != hipSuccess) HPLX_FAIL(HPL_ERR_NOMEM, "workspace allocation failed");
@@ -213,6 +218,8 @@ static int init_device(Device &d, int id)
     d.pivot_err = (int *)(b + o_perr);
     d.sync.slots = (double *)(b + o_slots);
     d.sync.top = (double *)(b + o_top);
+    d.sync.tslots = (unsigned long long *)(b + o_tslots);
+    d.sync.ttop = (unsigned long long *)(b + o_ttop);
     auto plan_at = [&](int k) {
         char *p = b + o_plans + (size_t)k * plan_bytes;
         SwapPlan s;
@@ -314,6 +321,16 @@ static int panel_rec(Ctx &x, int64_t c, int64_t w, hipStream_t st)
     Device *d = x.d;
     if (w <= x.base) {
         const int64_t m = x.n - c;
+        const int Gr = leaf_reg_groups(m, (int)w);
+        if (Gr > 0 && Gr <= x.gmax) {
+            if (d->tag_epoch > 0xF0000000u) {  // far from wrapping: clear the words, restart the tags
+                HPLX_PROPAGATE(launch_fill_u64(d->sync.tslots, (int64_t)(d->tag_area_bytes / 8), 0ull, st));
+                d->tag_epoch = 0;
+            }
+            const uint32_t tag0 = d->tag_epoch;
+            d->tag_epoch += (uint32_t)w + 1u;
+            return launch_leaf_reg(x.A, x.lda, c, m, (int)w, x.ipiv, d->sync, tag0, Gr, st);
+        }
         const int G = leaf_groups(m, (int)w, x.gmax);
         const unsigned long long base_ctr = d->bar_epoch;
         if (G > 1) d->bar_epoch += (unsigned long long)G * (unsigned long long)w;
@@ -443,9 +460,11 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
     const int aborted = *(int *)(d->hbuf + 1);
     if (aborted) {
         HPLX_PROPAGATE(launch_fill_u64(d->sync.counter, 1, 0ull, su));
+        HPLX_PROPAGATE(launch_fill_u64(d->sync.tslots, (int64_t)(d->tag_area_bytes / 8), 0ull, su));
         HPLX_TRY(hipMemsetAsync(d->sync.abort_flag, 0, sizeof(int), su));
         HPLX_TRY(hipStreamSynchronize(su));
         d->bar_epoch = 0;
+        d->tag_epoch = 0;
         HPLX_FAIL(HPL_ERR_INTERNAL, "panel barrier timed out");
     }
     const unsigned long long iv = d->hbuf[0];

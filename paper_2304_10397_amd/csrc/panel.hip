@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kLeafThreads) void panel_leaf_kernel(double *__rest
                 row[(int64_t)k * lda] = l;
                 for (int j = k + 1; j < w; ++j) {
                     const double a = swapped ? tr[j] : row[(int64_t)j * lda];
-                    const double nv = a - l * u[j];
+                    const double nv = __fma_rn(-l, u[j], a);
                     row[(int64_t)j * lda] = nv;
                     if (j == k + 1) {
                         const double v = fabs(nv);
@@ -201,7 +201,305 @@ __global__ __launch_bounds__(kLeafThreads) void panel_leaf_kernel(double *__rest
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident leaf.  Thread t of workgroup g holds rows rbeg + t + 512q
+// (q < 2) of the leaf in registers; v[q][j] is the row's value in column k + j
+// at step k (the active columns rotate down by one each step, so every register
+// index is a compile-time constant).  Column k of every active row is written
+// to memory at step k; the U row is written by workgroup 0.
+//
+// Cross-workgroup exchange without fences or counters: every published 64-bit
+// word carries a 32-bit tag (unique per launch and step) and 32 bits of
+// payload; writers use relaxed agent-scope atomic stores, readers poll with
+// relaxed agent-scope atomic loads until each word they need shows the current
+// tag, so each word validates itself and no ordering between words is needed.
+// Slot of workgroup g: words 0..2 = tagged (row index, |a| low, |a| high),
+// words 3 + 2j, 4 + 2j = tagged halves of the candidate row's value in column
+// k + j.  The diagonal row is published by workgroup 0 in a separate area.
+//
+// The interchanges of the leaf's own finished L columns (columns < k at step
+// k) are not done here; leaf_left_swaps_kernel applies them afterwards.
+// ---------------------------------------------------------------------------
+constexpr int kRegW = 32;                        // leaf width handled in registers
+constexpr int kRegRPT = 2;                       // rows per thread
+constexpr int kRegThreads = 512;
+constexpr int kRegWaves = kRegThreads / 64;
+constexpr int kRegRows = kRegThreads * kRegRPT;  // rows per workgroup (max)
+
+__device__ __forceinline__ void put_tagged(unsigned long long *p, uint32_t tag, uint32_t payload)
+{
+    __hip_atomic_store(p, ((unsigned long long)tag << 32) | payload, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spins until *p carries tag (or the abort flag rises / the wall-clock limit passes).
+__device__ __forceinline__ bool get_tagged(const unsigned long long *p, uint32_t tag, uint32_t &payload,
+                                           int *abort_flag, unsigned long long t0)
+{
+    for (;;) {
+        const unsigned long long v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 32) == tag) {
+            payload = (uint32_t)v;
+            return true;
+        }
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (wall_clock64() - t0 > kSpinLimit) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__device__ __forceinline__ double dbl_of(uint32_t lo, uint32_t hi)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ void block_argmax512(double &v, int64_t &i, double *rv, int64_t *ri)
+{
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    wave_argmax(v, i);
+    if (lane == 0) { rv[wid] = v; ri[wid] = i; }
+    __syncthreads();
+    v = rv[0];
+    i = ri[0];
+#pragma unroll
+    for (int q = 1; q < kRegWaves; ++q)
+        if (better(rv[q], ri[q], v, i)) { v = rv[q]; i = ri[q]; }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restrict__ A, int64_t lda, int64_t c,
+                                                               int64_t m, int w, int32_t *__restrict__ ipiv,
+                                                               LeafSync sync, uint32_t tag0, int G, int64_t R)
+{
+    __shared__ double cand[kRegW];   // candidate row (active columns) of this workgroup
+    __shared__ double topv[kRegW];   // diagonal row (workgroup 0)
+    __shared__ double u[kRegW];      // pivot row, active columns
+    __shared__ double tr[kRegW];     // old diagonal row, active columns
+    __shared__ double rv[kRegWaves];
+    __shared__ int64_t ri[kRegWaves];
+    __shared__ int s_abort;
+
+    double *S = A + off(c, c, lda);
+    const int g = blockIdx.x, t = threadIdx.x;
+    const int64_t rbeg = (int64_t)g * R;
+    const int64_t rend = (rbeg + R) < m ? (rbeg + R) : m;
+    unsigned long long *slots = sync.tslots;
+    unsigned long long *topw = sync.ttop;
+    const unsigned long long t0 = wall_clock64();
+
+    double v[kRegRPT][kRegW];
+    int64_t row[kRegRPT];
+    double bv = -1.0;
+    int64_t bi = INT64_MAX;
+#pragma unroll
+    for (int q = 0; q < kRegRPT; ++q) {
+        row[q] = rbeg + t + (int64_t)q * kRegThreads;
+        const bool live = row[q] < rend;
+#pragma unroll
+        for (int j = 0; j < kRegW; ++j) v[q][j] = (live && j < w) ? S[off(row[q], j, lda)] : 0.0;
+        if (live) {
+            const double a = fabs(v[q][0]);
+            if (better(a, row[q], bv, bi)) { bv = a; bi = row[q]; }
+        }
+    }
+    if (t == 0) s_abort = 0;
+
+    for (int k = 0; k < w; ++k) {
+        const int na = w - k;  // active columns
+        const uint32_t tag = tag0 + (uint32_t)k + 1u;
+        const int par = k & 1;
+        // ---- 1. this workgroup's candidate and the rows to publish
+        block_argmax512(bv, bi, rv, ri);
+#pragma unroll
+        for (int q = 0; q < kRegRPT; ++q) {
+            if (row[q] == bi && row[q] < rend) {
+#pragma unroll
+                for (int j = 0; j < kRegW; ++j)
+                    if (j < na) cand[j] = v[q][j];
+            }
+            if (g == 0 && row[q] == k) {
+#pragma unroll
+                for (int j = 0; j < kRegW; ++j)
+                    if (j < na) topv[j] = v[q][j];
+            }
+        }
+        __syncthreads();
+        double pv;
+        int64_t p;
+        if (G == 1) {
+            pv = bv;
+            p = bi;
+            if (t < na) {
+                u[t] = cand[t];
+                tr[t] = topv[t];
+            }
+        } else {
+            // ---- 2. publish (tagged words, no fences)
+            unsigned long long *my = slots + ((size_t)par * kLeafMaxWGs + g) * kLeafSlotWords;
+            if (t == 0) put_tagged(my, tag, (uint32_t)bi);
+            if (t == 1) put_tagged(my + 1, tag, (uint32_t)(__double_as_longlong(bv)));
+            if (t == 2) put_tagged(my + 2, tag, (uint32_t)((unsigned long long)__double_as_longlong(bv) >> 32));
+            if (t >= 64 && t < 64 + 2 * na) {
+                const int e = t - 64, j = e >> 1;
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(cand[j]);
+                put_tagged(my + 3 + e, tag, (e & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits);
+            }
+            if (g == 0 && t >= 128 && t < 128 + 2 * na) {
+                const int e = t - 128, j = e >> 1;
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(topv[j]);
+                put_tagged(topw + (size_t)par * 2 * kRegW + e, tag, (e & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits);
+            }
+            // ---- 3. gather every workgroup's candidate key
+            double gv = -1.0;
+            int64_t gi = INT64_MAX;
+            bool ok = true;
+            if (t < G) {
+                const unsigned long long *sq = slots + ((size_t)par * kLeafMaxWGs + t) * kLeafSlotWords;
+                uint32_t ix = 0, lo = 0, hi = 0;
+                ok = get_tagged(sq, tag, ix, sync.abort_flag, t0) && get_tagged(sq + 1, tag, lo, sync.abort_flag, t0) &&
+                     get_tagged(sq + 2, tag, hi, sync.abort_flag, t0);
+                if (ok) {
+                    gv = dbl_of(lo, hi);
+                    gi = (int64_t)ix;
+                }
+            }
+            if (!ok) s_abort = 1;
+            block_argmax512(gv, gi, rv, ri);
+            if (s_abort) return;
+            pv = gv;
+            p = gi;
+            // ---- 4. the winner's row and the diagonal row
+            const int64_t owner = (p == INT64_MAX) ? 0 : p / R;
+            const unsigned long long *sw = slots + ((size_t)par * kLeafMaxWGs + (owner < G ? owner : G - 1)) * kLeafSlotWords;
+            if (t < 2 * na) {
+                uint32_t lo = 0, hi = 0;
+                const int j = t >> 1;
+                bool ok2 = true;
+                if ((t & 1) == 0) {
+                    ok2 = get_tagged(sw + 3 + 2 * j, tag, lo, sync.abort_flag, t0) &&
+                          get_tagged(sw + 4 + 2 * j, tag, hi, sync.abort_flag, t0);
+                    if (ok2) u[j] = dbl_of(lo, hi);
+                } else {
+                    const unsigned long long *tw = topw + (size_t)par * 2 * kRegW;
+                    ok2 = get_tagged(tw + 2 * j, tag, lo, sync.abort_flag, t0) &&
+                          get_tagged(tw + 2 * j + 1, tag, hi, sync.abort_flag, t0);
+                    if (ok2) tr[j] = dbl_of(lo, hi);
+                }
+                if (!ok2) s_abort = 1;
+            }
+            __syncthreads();
+            if (s_abort) return;
+        }
+        __syncthreads();
+        const bool singular = !(pv > 0.0);
+        if (singular) p = k;  // no interchange; u already is the diagonal row when p == k
+        if (singular && t < na) u[t] = tr[t];
+        if (g == 0 && t == 0) {
+            ipiv[c + k] = (int32_t)(c + p);
+            if (singular) atomicMin(sync.info, (unsigned long long)(c + k + 1));
+        }
+        __syncthreads();
+        // ---- 5. U row k, interchange of the active parts, scale, rank-1 update
+        if (g == 0 && t < na) S[off(k, k + t, lda)] = u[t];
+        const double piv = u[0];
+        bv = -1.0;
+        bi = INT64_MAX;
+#pragma unroll
+        for (int q = 0; q < kRegRPT; ++q) {
+            const int64_t i = row[q];
+            if (i >= rend || i <= k) continue;
+            if (i == p) {
+#pragma unroll
+                for (int j = 0; j < kRegW; ++j)
+                    if (j < na) v[q][j] = tr[j];
+            }
+            const double l = singular ? v[q][0] : v[q][0] / piv;
+            S[off(i, k, lda)] = l;
+#pragma unroll
+            for (int j = 1; j < kRegW; ++j)
+                if (j < na) v[q][j - 1] = singular ? v[q][j] : __fma_rn(-l, u[j], v[q][j]);
+            if (na > 1) {
+                const double a = fabs(v[q][0]);
+                if (better(a, i, bv, bi)) { bv = a; bi = i; }
+            }
+        }
+    }
+}
+
+// In-leaf interchanges of the finished L columns: column c + j receives the
+// interchanges k = j+1 .. w-1 of the leaf (rows c+k <-> ipiv[c+k]), composed
+// into a permutation of the touched rows and applied by gather/scatter.
+__global__ __launch_bounds__(64) void leaf_left_swaps_kernel(double *__restrict__ A, int64_t lda, int64_t c, int w,
+                                                             const int32_t *__restrict__ ipiv)
+{
+    __shared__ int64_t rows[2 * kRegW];
+    __shared__ int cont[2 * kRegW];
+    __shared__ double vals[2 * kRegW];
+    __shared__ int64_t piv[kRegW];
+    __shared__ int ns;
+    const int j = blockIdx.x, t = threadIdx.x;
+    const int cnt = w - 1 - j;
+    if (t < w) piv[t] = ipiv[c + t];
+    __syncthreads();
+    if (t == 0) {
+        int n = cnt;
+        for (int s = 0; s < cnt; ++s) {
+            rows[s] = c + j + 1 + s;
+            cont[s] = s;
+        }
+        for (int k = j + 1; k < w; ++k) {
+            const int a = k - j - 1;
+            const int64_t p = piv[k];
+            int b = -1;
+            if (p < c + w) {
+                b = (int)(p - (c + j + 1));
+            } else {
+                for (int s = cnt; s < n; ++s)
+                    if (rows[s] == p) { b = s; break; }
+                if (b < 0) {
+                    rows[n] = p;
+                    cont[n] = n;
+                    b = n++;
+                }
+            }
+            const int ca = cont[a];
+            cont[a] = cont[b];
+            cont[b] = ca;
+        }
+        ns = n;
+    }
+    __syncthreads();
+    double *col = A + off(0, c + j, lda);
+    if (t < ns) vals[t] = col[rows[t]];
+    __syncthreads();
+    if (t < ns && cont[t] != t) col[rows[t]] = vals[cont[t]];
+}
+
 }  // namespace
+
+int leaf_reg_groups(int64_t m, int w)
+{
+    if (w > kRegW) return 0;
+    const int64_t g = (m + kRegRows - 1) / kRegRows;
+    return g <= kLeafMaxWGs ? (int)g : 0;
+}
+
+int launch_leaf_reg(double *A, int64_t lda, int64_t c, int64_t m, int w, int32_t *ipiv, LeafSync sync, uint32_t tag0,
+                    int G, hipStream_t st)
+{
+    if (w <= 0 || w > kRegW || G < 1 || G > kLeafMaxWGs || m < w) return HPL_ERR_INTERNAL;
+    const int64_t R = (m + G - 1) / G;
+    if (R > kRegRows || R < w) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(leaf_reg_kernel, dim3(G), dim3(kRegThreads), 0, st, A, lda, c, m, w, ipiv, sync, tag0, G, R);
+    HPLX_TRY_LAUNCH();
+    if (w > 1) {
+        hipLaunchKernelGGL(leaf_left_swaps_kernel, dim3(w - 1), dim3(64), 0, st, A, lda, c, w, (const int32_t *)ipiv);
+        HPLX_TRY_LAUNCH();
+    }
+    return HPL_OK;
+}
 
 int leaf_groups(int64_t m, int w, int gmax)
 {

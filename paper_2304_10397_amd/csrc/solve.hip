@@ -29,32 +29,36 @@ constexpr int kSvThreads = 256;  // 4 waves
 constexpr int kSvRhs = 8;        // right-hand sides per pass of the GEMV
 constexpr int kRowsPerThread = 4;
 
-// T_op(r, c) of the mode for global indices (r, c)
-__device__ __forceinline__ double top(const double *T, int64_t ldt, int64_t r, int64_t c, int mode)
-{
-    return (mode < 2) ? T[off(r, c, ldt)] : T[off(c, r, ldt)];
-}
-
+template <int mode>
 __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *__restrict__ T, int64_t ldt,
                                                                  double *__restrict__ B, int64_t ldb, int64_t nrhs,
                                                                  int64_t r0, int bs, int64_t row_begin,
-                                                                 int64_t row_end, int mode)
+                                                                 int64_t row_end)
 {
-    extern __shared__ double Y[];  // [nrhs][kBs] solved block
+    __shared__ double Td[kBs][kBs + 1];  // Td[r][c] = T(r0 + r, r0 + c), identity-padded past bs
+    extern __shared__ double Y[];        // [nrhs][kBs] solved block
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    const bool lower = (mode == 0 || mode == 2);
-    const bool unit = (mode == 0 || mode == 3);
+    constexpr bool lower = (mode == 0 || mode == 2);
+    constexpr bool unit = (mode == 0 || mode == 3);
+    constexpr bool tr = (mode >= 2);
 
-    // ---- 1. diagonal block, one wave per right-hand side
+    // ---- 1. diagonal block: stage it (coalesced), then one wave per right-hand side
+    for (int e = t; e < kBs * kBs; e += kSvThreads) {
+        const int r = e % kBs, c = e / kBs;
+        Td[r][c] = (r < bs && c < bs) ? T[off(r0 + r, r0 + c, ldt)] : (r == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
     for (int64_t c = wid; c < nrhs; c += kSvThreads / 64) {
         double x = (lane < bs) ? B[off(r0 + lane, c, ldb)] : 0.0;
-        for (int s = 0; s < bs; ++s) {
-            const int k = lower ? s : bs - 1 - s;
+#pragma unroll 8
+        for (int s = 0; s < kBs; ++s) {
+            const int k = lower ? s : kBs - 1 - s;
             double xk = __shfl(x, k, 64);
-            if (!unit) xk = xk / top(T, ldt, r0 + k, r0 + k, mode);
+            if (!unit) xk = xk / Td[k][k];
             if (lane == k) x = xk;
             const bool below = lower ? (lane > k) : (lane < k);
-            if (below && lane < bs) x = x - top(T, ldt, r0 + lane, r0 + k, mode) * xk;
+            const double a = tr ? Td[k][lane] : Td[lane][k];  // T_op(lane, k)
+            if (below) x = __fma_rn(-a, xk, x);
         }
         if (lane < bs) {
             Y[c * kBs + lane] = x;
@@ -76,7 +80,7 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *_
             double acc[kSvRhs];
 #pragma unroll
             for (int c = 0; c < kSvRhs; ++c) acc[c] = 0.0;
-            if (mode < 2) {
+            if constexpr (mode < 2) {
                 const double *col = T + off(i, r0, ldt);
                 for (int k = 0; k < bs; ++k) {
                     const double a = col[(size_t)k * (size_t)ldt];
@@ -143,8 +147,25 @@ int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int
     if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
     const size_t lds = sizeof(double) * (size_t)kBs * (size_t)nrhs;
     if (lds > 64 * 1024) return HPL_ERR_INTERNAL;
-    hipLaunchKernelGGL(solve_block_kernel, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs, r0,
-                       (int)bs, row_begin, row_end, mode);
+    switch (mode) {
+    case 0:
+        hipLaunchKernelGGL(solve_block_kernel<0>, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
+                           r0, (int)bs, row_begin, row_end);
+        break;
+    case 1:
+        hipLaunchKernelGGL(solve_block_kernel<1>, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
+                           r0, (int)bs, row_begin, row_end);
+        break;
+    case 2:
+        hipLaunchKernelGGL(solve_block_kernel<2>, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
+                           r0, (int)bs, row_begin, row_end);
+        break;
+    case 3:
+        hipLaunchKernelGGL(solve_block_kernel<3>, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
+                           r0, (int)bs, row_begin, row_end);
+        break;
+    default: return HPL_ERR_INTERNAL;
+    }
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }

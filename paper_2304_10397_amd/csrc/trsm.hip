@@ -54,9 +54,35 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
         }
     }
 
+    // Next step's operands are fetched as soon as the current step's MFMAs are
+    // issued, so their latency hides behind the next step's publish, barrier
+    // and substitution: the diagonal block of L (one
+    // element per thread of the upper half of the workgroup) and this wave's A
+    // fragments (-L[rb, i], 4 k-steps per row block).
+    double lsp = 0.0;
+    double afr[kTrQ][4];
+    auto fetch = [&](int i, double &ls, double (&af)[kTrQ][4]) {
+        if (t >= 256) {
+            const int e = t - 256, r = e & 15, c = e >> 4;
+            const int gr = 16 * i + r, gc = 16 * i + c;
+            ls = (i < nrb && gr < nbk && gc < nbk) ? L[off(gr, gc, ldl)] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kTrQ; ++q) {
+            const int rb = wave + kTrWaves * q;
+            const int lr = 16 * rb + (lane & 15);
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) {
+                const int kc = 4 * k4 + (lane >> 4);
+                af[q][k4] = (rb > i && rb < nrb && lr < nbk) ? -L[off(lr, 16 * i + kc, ldl)] : 0.0;
+            }
+        }
+    };
+    fetch(0, lsp, afr);
+
     for (int i = 0; i < nrb; ++i) {
         const int par = i & 1;
-        // 1. owner publishes row block i; others stage the diagonal block of L
+        // 1. owner publishes row block i; the upper half stages the diagonal block of L
         if (wave == (i % kTrWaves)) {
             const int q = i / kTrWaves;
 #pragma unroll
@@ -69,9 +95,8 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
             }
         }
         if (t >= 256) {
-            const int e = t - 256, r = e & 15, c = e >> 4;
-            const int gr = 16 * i + r, gc = 16 * i + c;
-            Ls[par][r][c] = (gr < nbk && gc < nbk) ? L[off(gr, gc, ldl)] : 0.0;
+            const int e = t - 256;
+            Ls[par][e & 15][e >> 4] = lsp;
         }
         __syncthreads();
         // 2. substitution of the 16 x kTrWB block: thread -> (row r, columns c, c + 32);
@@ -85,7 +110,7 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
 #pragma unroll
                 for (int kk = 0; kk < 15; ++kk) {
                     const double xk = __shfl(x, (lane & ~15) | kk, 64);
-                    if (r > kk) x = x - Ls[par][r][kk] * xk;
+                    if (r > kk) x = __fma_rn(-Ls[par][r][kk], xk, x);
                 }
                 Xs[par][r][cc] = x;
                 const int gr = 16 * i + r;
@@ -98,19 +123,18 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
         for (int q = 0; q < kTrQ; ++q) {
             const int rb = wave + kTrWaves * q;
             if (rb > i && rb < nrb) {
-                const int lr = 16 * rb + (lane & 15);
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
                     const int kc = 4 * k4 + (lane >> 4);
-                    const double a = (lr < nbk) ? -L[off(lr, 16 * i + kc, ldl)] : 0.0;
 #pragma unroll
                     for (int cb = 0; cb < kTrCB; ++cb) {
                         const double b = Xs[par][kc][16 * cb + (lane & 15)];
-                        acc[q][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q][cb], 0, 0, 0);
+                        acc[q][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[q][k4], b, acc[q][cb], 0, 0, 0);
                     }
                 }
             }
         }
+        fetch(i + 1, lsp, afr);
     }
 }
 

@@ -28,10 +28,9 @@ def to_gpu(a, ld=None, pad_value=np.nan):
     return M
 
 
-def padding_of(M):
-    """The rows between M.shape[0] and its leading dimension (None when there are none)."""
+def padding_of(M, ld):
+    """The rows between M.shape[0] and the leading dimension ld (None when there are none)."""
     n, m = M.shape
-    ld = M.stride(1) if m > 1 else n
     if ld == n or m == 0:
         return None
     base = M.as_strided((ld, m), (1, ld))

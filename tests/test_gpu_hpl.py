@@ -54,7 +54,7 @@ def test_generate_bitwise(rows, cols, ld, stream):
     want = oracle.gen(SEED, stream, rows, cols)
     got = to_host(M)
     assert np.array_equal(got.view(np.int64), np.asfortranarray(want).view(np.int64))
-    pad = padding_of(M)
+    pad = padding_of(M, ld)
     if pad is not None:
         assert np.all(pad == 7.0)
 
@@ -105,7 +105,7 @@ def test_factor_solve_vs_oracle(n, nb, pad):
     res = h.hpl_residual(A0g, b, bg)
     assert res[0] < 16.0
     if pad:
-        assert np.all(np.isnan(padding_of(A)))
+        assert np.all(np.isnan(padding_of(A, n + pad)))
 
 
 @pytest.mark.parametrize("n,nb,base", [(64, 16, 32), (200, 32, 16), (1000, 64, 32), (1031, 128, 64),
