@@ -86,7 +86,9 @@ int launch_residual(const double *A, int64_t lda, bool gen, uint64_t s0, int64_t
                     unsigned long long *red, hipStream_t st);
 int launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v, hipStream_t st);
 
-// gemm.hip: C(m x n) -= A(m x k) * B(k x n).
+// gemm.hip: C(m x n) -= A(m x k) * B(k x n).  variant: 0 auto, 1..4 tile shape;
+// OR kGemmTrailing for the trailing update (a separately named instance).
+constexpr int kGemmTrailing = 0x100;
 int launch_gemm_sub(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda,
                     const double *B, int64_t ldb, double *C, int64_t ldc, int variant,
                     hipStream_t st);

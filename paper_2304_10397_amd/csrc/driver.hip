@@ -376,7 +376,7 @@ static int update_cols(Ctx &x, int64_t c0, int64_t jb, int64_t col, int64_t ncol
     if (m > 0) {
         id = x.tm->begin(ST_GEMM, st);
         HPLX_PROPAGATE(launch_gemm_sub(m, ncols, jb, x.A + off(c1, c0, x.lda), x.lda, x.A + off(c0, col, x.lda),
-                                       x.lda, x.A + off(c1, col, x.lda), x.lda, x.gemm_tile, st));
+                                       x.lda, x.A + off(c1, col, x.lda), x.lda, x.gemm_tile | kGemmTrailing, st));
         HPLX_PROPAGATE(x.tm->end(id, st, 2.0 * (double)m * (double)ncols * (double)jb,
                                  16.0 * (double)m * (double)ncols + 8.0 * (double)jb * ((double)m + (double)ncols)));
     }

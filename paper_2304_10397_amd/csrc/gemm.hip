@@ -20,10 +20,12 @@
 //  * Block tile BM x BN, K staged BK = 16 at a time through double-buffered
 //    LDS (one barrier per stage); each wave owns a (BM/WM) x (BN/WN) sub-tile
 //    of accumulators that stay in registers for the whole K loop.
-//  * The accumulators start from C (loaded once) and A is negated on its way
-//    into LDS, so every element is C + sum_k (-a_ik) b_kj accumulated in the
-//    same k order with the same instruction whatever the tiling -- the
-//    look-ahead split of the update reproduces the unsplit update bit for bit.
+//  * Accumulators live in AGPRs (so the A/B operands do not compete with them
+//    for VGPR read ports) and start from zero; the epilogue applies
+//    C <- C - acc a column group at a time.  Every element is therefore
+//    C - sum_k a_ik b_kj with the same k order and the same instruction
+//    whatever the tiling -- the look-ahead split of the update reproduces the
+//    unsplit update bit for bit.
 //  * Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 //    L2).  The block index is remapped so that each XCD receives a contiguous
 //    run of tiles, and tiles are ordered in groups of kGroupM tile-rows so the
@@ -69,7 +71,9 @@ __device__ __forceinline__ void tile_of_block(int64_t bid, int64_t nwg, int64_t 
     tn = r / gm;
 }
 
-template <int BM, int BN, int WM, int WN>
+// TRAIL = 1 marks the instances used for the trailing update (same code; a
+// distinct symbol so that profiles separate it from the panel's inner GEMMs).
+template <int BM, int BN, int WM, int WN, int TRAIL>
 __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
     int64_t m, int64_t n, int64_t k, const double *__restrict__ A, int64_t lda,
     const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc, int64_t tiles_m,
@@ -77,6 +81,10 @@ __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
 {
     using Cfg = GemmCfg<BM, BN, WM, WN>;
     constexpr int NT = Cfg::NT, TM = Cfg::TM, TN = Cfg::TN, FI = Cfg::FI, FG = Cfg::FG;
+    // Marks the kernel as using AGPRs, so the compiler selects the MFMA form with
+    // accumulators in AGPRs: the A/B operands then have the VGPR read ports to
+    // themselves instead of competing with the accumulator in the same banks.
+    asm volatile("" ::: "a0");
     constexpr int AS = BM + Cfg::APAD, BS = BN + Cfg::BPAD;
     __shared__ double As[2][BK][AS];
     __shared__ double Bs[2][BK][BS];
@@ -127,26 +135,21 @@ __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < Cfg::AL; ++q) As[buf][a_k + AQ * q][a_r] = -ra[q];
+        for (int q = 0; q < Cfg::AL; ++q) As[buf][a_k + AQ * q][a_r] = ra[q];
 #pragma unroll
         for (int q = 0; q < Cfg::BL; ++q) Bs[buf][b_k][b_c + BQ * q] = rb[q];
     };
 
     load_stage(0);
 
-    // Accumulators start from C: lane d holds C(wm*TM + 4I + d/16, wn*TN + 16G + d%16).
+    // lane d accumulates element (wm*TM + 4I + d/16, wn*TN + 16G + d%16) of the tile
     double acc[FI][FG];
+#pragma unroll
+    for (int i = 0; i < FI; ++i)
+#pragma unroll
+        for (int g = 0; g < FG; ++g) acc[i][g] = 0.0;
     const int crow0 = wm * TM + (lane >> 4);
     const int ccol0 = wn * TN + (lane & 15);
-    double *pc = C + off(m0 + crow0, n0 + ccol0, ldc);
-    const int64_t c_step = 16 * ldc;
-#pragma unroll
-    for (int g = 0; g < FG; ++g) {
-        const bool col_ok = ccol0 + 16 * g < nrem;
-        const double *pcol = pc + (size_t)g * (size_t)c_step;
-#pragma unroll
-        for (int i = 0; i < FI; ++i) acc[i][g] = (col_ok && crow0 + 4 * i < mrem) ? pcol[4 * i] : 0.0;
-    }
 
     store_stage(0);
     __syncthreads();
@@ -176,24 +179,28 @@ __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
         __syncthreads();
     }
 
+    // C <- C - acc, one 16-column group at a time (bounded live registers)
+    double *pc = C + off(m0 + crow0, n0 + ccol0, ldc);
+    const int64_t c_step = 16 * ldc;
 #pragma unroll
     for (int g = 0; g < FG; ++g) {
         const bool col_ok = ccol0 + 16 * g < nrem;
         double *pcol = pc + (size_t)g * (size_t)c_step;
 #pragma unroll
         for (int i = 0; i < FI; ++i)
-            if (col_ok && crow0 + 4 * i < mrem) pcol[4 * i] = acc[i][g];
+            if (col_ok && crow0 + 4 * i < mrem) pcol[4 * i] = pcol[4 * i] - acc[i][g];
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int TRAIL>
 int launch_cfg(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B,
                int64_t ldb, double *C, int64_t ldc, hipStream_t st)
 {
     const int64_t tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
     const int64_t nwg = tiles_m * tiles_n;
     if (nwg > 0x7fffffffll) return HPL_ERR_INTERNAL;
-    hipLaunchKernelGGL((gemm_sub_kernel<BM, BN, WM, WN>), dim3((unsigned)nwg), dim3(WM * WN * 64), 0, st,
+    hipLaunchKernelGGL((gemm_sub_kernel<BM, BN, WM, WN, TRAIL>), dim3((unsigned)nwg), dim3(WM * WN * 64), 0, st,
                        m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
@@ -201,11 +208,14 @@ int launch_cfg(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, co
 
 }  // namespace
 
-// variant: 0 = auto, 1 = 128x128, 2 = 128x64, 3 = 64x64, 4 = 128x32
+// variant: 0 = auto, 1 = 128x128, 2 = 128x64, 3 = 64x64, 4 = 128x32; add kTrailing
+// (launch_gemm_sub's caller passes variant | kTrailingFlag) for the trailing update.
 int launch_gemm_sub(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B,
                     int64_t ldb, double *C, int64_t ldc, int variant, hipStream_t st)
 {
     if (m <= 0 || n <= 0 || k <= 0) return HPL_OK;
+    const bool trail = (variant & kGemmTrailing) != 0;
+    variant &= ~kGemmTrailing;
     if (variant == 0) {
         if (n <= 32)
             variant = 4;
@@ -216,11 +226,20 @@ int launch_gemm_sub(int64_t m, int64_t n, int64_t k, const double *A, int64_t ld
         else
             variant = 1;
     }
+    if (trail) {
+        switch (variant) {
+        case 1: return launch_cfg<128, 128, 2, 2, 1>(m, n, k, A, lda, B, ldb, C, ldc, st);
+        case 2: return launch_cfg<128, 64, 2, 2, 1>(m, n, k, A, lda, B, ldb, C, ldc, st);
+        case 3: return launch_cfg<64, 64, 2, 2, 1>(m, n, k, A, lda, B, ldb, C, ldc, st);
+        case 4: return launch_cfg<128, 32, 4, 1, 1>(m, n, k, A, lda, B, ldb, C, ldc, st);
+        default: return HPL_ERR_INTERNAL;
+        }
+    }
     switch (variant) {
-    case 1: return launch_cfg<128, 128, 2, 2>(m, n, k, A, lda, B, ldb, C, ldc, st);
-    case 2: return launch_cfg<128, 64, 2, 2>(m, n, k, A, lda, B, ldb, C, ldc, st);
-    case 3: return launch_cfg<64, 64, 2, 2>(m, n, k, A, lda, B, ldb, C, ldc, st);
-    case 4: return launch_cfg<128, 32, 4, 1>(m, n, k, A, lda, B, ldb, C, ldc, st);
+    case 1: return launch_cfg<128, 128, 2, 2, 0>(m, n, k, A, lda, B, ldb, C, ldc, st);
+    case 2: return launch_cfg<128, 64, 2, 2, 0>(m, n, k, A, lda, B, ldb, C, ldc, st);
+    case 3: return launch_cfg<64, 64, 2, 2, 0>(m, n, k, A, lda, B, ldb, C, ldc, st);
+    case 4: return launch_cfg<128, 32, 4, 1, 0>(m, n, k, A, lda, B, ldb, C, ldc, st);
     default: return HPL_ERR_INTERNAL;
     }
 }

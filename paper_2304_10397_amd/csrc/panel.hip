@@ -438,43 +438,47 @@ __global__ __launch_bounds__(64) void leaf_left_swaps_kernel(double *__restrict_
     __shared__ int cont[2 * kRegW];
     __shared__ double vals[2 * kRegW];
     __shared__ int64_t piv[kRegW];
+    __shared__ int bslot[kRegW];
     __shared__ int ns;
     const int j = blockIdx.x, t = threadIdx.x;
-    const int cnt = w - 1 - j;
+    const int cnt = w - 1 - j;  // interchanges k = j+1 .. w-1
     if (t < w) piv[t] = ipiv[c + t];
     __syncthreads();
-    if (t == 0) {
-        int n = cnt;
-        for (int s = 0; s < cnt; ++s) {
-            rows[s] = c + j + 1 + s;
-            cont[s] = s;
+    // slots: 0..cnt-1 are rows c+j+1 .. c+w-1; an outside row p gets slot cnt + (f - j - 1)
+    // where f is its first interchange index after j (found in parallel, one k per lane)
+    if (t > j && t < w) {
+        const int64_t p = piv[t];
+        int b;
+        if (p < c + w) {
+            b = (int)(p - (c + j + 1));
+        } else {
+            int f = t;
+            for (int k2 = j + 1; k2 < t; ++k2)
+                if (piv[k2] == p) { f = k2; break; }
+            b = cnt + (f - j - 1);
+            if (f == t) rows[b] = p;
         }
+        bslot[t] = b;
+    }
+    if (t < cnt) rows[t] = c + j + 1 + t;
+    if (t < 2 * cnt) cont[t] = t;
+    __syncthreads();
+    if (t == 0) {
         for (int k = j + 1; k < w; ++k) {
-            const int a = k - j - 1;
-            const int64_t p = piv[k];
-            int b = -1;
-            if (p < c + w) {
-                b = (int)(p - (c + j + 1));
-            } else {
-                for (int s = cnt; s < n; ++s)
-                    if (rows[s] == p) { b = s; break; }
-                if (b < 0) {
-                    rows[n] = p;
-                    cont[n] = n;
-                    b = n++;
-                }
-            }
+            const int a = k - j - 1, b = bslot[k];
             const int ca = cont[a];
             cont[a] = cont[b];
             cont[b] = ca;
         }
-        ns = n;
+        ns = 2 * cnt;
     }
     __syncthreads();
+    // slot cnt + q is in use only if some interchange put an outside row there
     double *col = A + off(0, c + j, lda);
-    if (t < ns) vals[t] = col[rows[t]];
+    const bool used = (t < cnt) || (t >= cnt && t < 2 * cnt && bslot[t - cnt + j + 1] == t);
+    if (t < ns && used) vals[t] = col[rows[t]];
     __syncthreads();
-    if (t < ns && cont[t] != t) col[rows[t]] = vals[cont[t]];
+    if (t < ns && used && cont[t] != t) col[rows[t]] = vals[cont[t]];
 }
 
 }  // namespace

@@ -73,29 +73,27 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *_
     const int64_t wb = row_begin + (int64_t)blockIdx.x * rows_per_wg;
     for (int64_t c0 = 0; c0 < nrhs; c0 += kSvRhs) {
         const int nr = (int)((nrhs - c0) < kSvRhs ? (nrhs - c0) : kSvRhs);
-#pragma unroll
+#pragma unroll 1
         for (int q = 0; q < kRowsPerThread; ++q) {
             const int64_t i = wb + t + (int64_t)q * kSvThreads;
             if (i >= row_end) break;
             double acc[kSvRhs];
 #pragma unroll
             for (int c = 0; c < kSvRhs; ++c) acc[c] = 0.0;
-            if constexpr (mode < 2) {
-                const double *col = T + off(i, r0, ldt);
-                for (int k = 0; k < bs; ++k) {
-                    const double a = col[(size_t)k * (size_t)ldt];
+            // the block's kBs operator values of this row, fetched in batches of 16
+            // independent loads (one round trip per batch, not one per element)
+            const double *base = (mode < 2) ? T + off(i, r0, ldt) : T + off(r0, i, ldt);
+            const size_t stride = (mode < 2) ? (size_t)ldt : 1;
+#pragma unroll 1
+            for (int k0 = 0; k0 < kBs; k0 += 16) {
+                double a[16];
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) a[kk] = (k0 + kk < bs) ? base[(size_t)(k0 + kk) * stride] : 0.0;
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk)
 #pragma unroll
                     for (int c = 0; c < kSvRhs; ++c)
-                        if (c < nr) acc[c] += a * Y[(c0 + c) * kBs + k];
-                }
-            } else {
-                const double *seg = T + off(r0, i, ldt);  // contiguous column segment
-                for (int k = 0; k < bs; ++k) {
-                    const double a = seg[k];
-#pragma unroll
-                    for (int c = 0; c < kSvRhs; ++c)
-                        if (c < nr) acc[c] += a * Y[(c0 + c) * kBs + k];
-                }
+                        if (c < nr) acc[c] += a[kk] * Y[(c0 + c) * kBs + k0 + kk];
             }
             for (int c = 0; c < nr; ++c) B[off(i, c0 + c, ldb)] -= acc[c];
         }

@@ -12,8 +12,11 @@
 //      rows sit in 16 lanes of one wave and x_k travels by lane shuffle; the
 //      solved rows go to global memory,
 //   3. every wave subtracts L[rb, i] * X_i from its row blocks rb > i with
-//      v_mfma_f64_16x16x4_f64 (A operand = -L fragment from L2, B operand = X_i
-//      from LDS).
+//      v_mfma_f64_4x4x4_4b_f64 (the fast FP64 MFMA form on gfx950): the four
+//      blocks b of one instruction take rows 16rb+4b..+3 of -L (lane l holds
+//      -L[16rb + l%16][l/16], fetched from L2 one step ahead) and the same
+//      4 columns of X_i (from LDS), so lane d accumulates
+//      (row 16rb + 4((d>>2)&3) + (d>>4), column 4J + (d&3)) for column group J.
 // Each column's arithmetic is independent of which workgroup holds it, so a
 // split of the columns (look-ahead) gives identical bits.
 #include "common.hpp"
@@ -23,7 +26,7 @@ namespace hplx {
 namespace {
 
 constexpr int kTrWB = 64;      // columns per workgroup
-constexpr int kTrCB = kTrWB / 16;  // column blocks
+constexpr int kTrCG = kTrWB / 4;   // 4-column groups
 constexpr int kTrWaves = 8;    // waves per workgroup
 constexpr int kTrMaxRB = 32;   // row blocks (nbk <= 512)
 constexpr int kTrQ = kTrMaxRB / kTrWaves;  // row blocks per wave
@@ -39,18 +42,17 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
     const int64_t crem = ncols - c0;
     const int nrb = (nbk + 15) >> 4;
 
-    dbl4 acc[kTrQ][kTrCB];
+    // lane d of accumulator (q, J): row 16rb + dr, column 4J + (d&3)
+    const int dr = 4 * ((lane >> 2) & 3) + (lane >> 4);
+    double acc[kTrQ][kTrCG];
 #pragma unroll
     for (int q = 0; q < kTrQ; ++q) {
         const int rb = wave + kTrWaves * q;
+        const int rr = 16 * rb + dr;
 #pragma unroll
-        for (int cb = 0; cb < kTrCB; ++cb) {
-            const int cc = 16 * cb + (lane & 15);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int rr = 16 * rb + (lane >> 4) + 4 * r;  // MFMA result layout: row l/16 + 4r
-                acc[q][cb][r] = (rb < nrb && rr < nbk && cc < crem) ? B[off(rr, c0 + cc, ldb)] : 0.0;
-            }
+        for (int J = 0; J < kTrCG; ++J) {
+            const int cc = 4 * J + (lane & 3);
+            acc[q][J] = (rb < nrb && rr < nbk && cc < crem) ? B[off(rr, c0 + cc, ldb)] : 0.0;
         }
     }
 
@@ -89,9 +91,7 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
             for (int qq = 0; qq < kTrQ; ++qq) {
                 if (qq != q) continue;
 #pragma unroll
-                for (int cb = 0; cb < kTrCB; ++cb)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) Xs[par][(lane >> 4) + 4 * r][16 * cb + (lane & 15)] = acc[qq][cb][r];
+                for (int J = 0; J < kTrCG; ++J) Xs[par][dr][4 * J + (lane & 3)] = acc[qq][J];
             }
         }
         if (t >= 256) {
@@ -127,10 +127,11 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
                 for (int k4 = 0; k4 < 4; ++k4) {
                     const int kc = 4 * k4 + (lane >> 4);
 #pragma unroll
-                    for (int cb = 0; cb < kTrCB; ++cb) {
-                        const double b = Xs[par][kc][16 * cb + (lane & 15)];
-                        acc[q][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[q][k4], b, acc[q][cb], 0, 0, 0);
+                    for (int J = 0; J < kTrCG; ++J) {
+                        const double b = Xs[par][kc][4 * J + (lane & 3)];
+                        acc[q][J] = __builtin_amdgcn_mfma_f64_4x4x4f64(afr[q][k4], b, acc[q][J], 0, 0, 0);
                     }
+                    __builtin_amdgcn_sched_barrier(0);  // bound the B fragments kept live
                 }
             }
         }
