@@ -135,7 +135,9 @@ int hpl_generate(uint64_t seed, uint64_t stream_id, double *M, int64_t rows, int
 
 /* Options (process-wide, read at the start of each call). */
 enum hpl_option {
-    HPL_OPT_LOOKAHEAD = 1,   /* 0 or 1 (default 1): depth of the panel look-ahead */
+    HPL_OPT_LOOKAHEAD = 1,   /* 0: none.  1 (default): panel j+1 is factored while the
+                                RS/TRSM of panel j finish; the trailing GEMM starts when
+                                the panel is done.  2: the panel also overlaps the GEMM. */
     HPL_OPT_PANEL_BASE = 2,  /* leaf width of the recursive panel: 8, 16, 32 or 64 (default 32) */
     HPL_OPT_PANEL_WGS = 3,   /* max workgroups of the panel leaf kernel, 1..256 (default 256) */
     HPL_OPT_TIMING = 4,      /* 1: time every kernel with HIP events (see hpl_get_stats) */

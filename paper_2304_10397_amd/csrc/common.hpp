@@ -21,6 +21,16 @@ __host__ __device__ __forceinline__ size_t off(int64_t i, int64_t j, int64_t ld)
     return (size_t)i + (size_t)j * (size_t)ld;
 }
 
+// Value of v held by lane l of the wave (l uniform across the wave): two
+// v_readlane_b32, a few cycles, instead of an LDS round trip.
+__device__ __forceinline__ double read_lane(double v, int l)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // ---------------------------------------------------------------------------
 // Error plumbing (host).
 // ---------------------------------------------------------------------------

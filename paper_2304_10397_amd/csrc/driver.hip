@@ -362,8 +362,22 @@ static int panel_full(Ctx &x, int64_t c0, int64_t jb, SwapPlan *plans, hipStream
     return make_plans(x.ipiv + c0, c0, jb, x.n, plans, false, st, x.tm);
 }
 
-// RS + TRSM + GEMM of panel (c0, jb) applied to columns [col, col+ncols).
-static int update_cols(Ctx &x, int64_t c0, int64_t jb, int64_t col, int64_t ncols, SwapPlan *plans, hipStream_t st)
+// Trailing GEMM of panel (c0, jb) on columns [col, col+ncols): A22 -= L21 U12.
+static int update_gemm(Ctx &x, int64_t c0, int64_t jb, int64_t col, int64_t ncols, hipStream_t st)
+{
+    const int64_t c1 = c0 + jb;
+    const int64_t m = x.n - c1;
+    if (m <= 0 || ncols <= 0) return HPL_OK;
+    int id = x.tm->begin(ST_GEMM, st);
+    HPLX_PROPAGATE(launch_gemm_sub(m, ncols, jb, x.A + off(c1, c0, x.lda), x.lda, x.A + off(c0, col, x.lda), x.lda,
+                                   x.A + off(c1, col, x.lda), x.lda, x.gemm_tile | kGemmTrailing, st));
+    return x.tm->end(id, st, 2.0 * (double)m * (double)ncols * (double)jb,
+                     16.0 * (double)m * (double)ncols + 8.0 * (double)jb * ((double)m + (double)ncols));
+}
+
+// RS + TRSM (+ GEMM when with_gemm) of panel (c0, jb) applied to columns [col, col+ncols).
+static int update_cols(Ctx &x, int64_t c0, int64_t jb, int64_t col, int64_t ncols, SwapPlan *plans, hipStream_t st,
+                       bool with_gemm)
 {
     if (ncols <= 0) return HPL_OK;
     HPLX_PROPAGATE(apply_plans(x.A, x.lda, col, ncols, jb, plans, st, x.tm));
@@ -371,16 +385,7 @@ static int update_cols(Ctx &x, int64_t c0, int64_t jb, int64_t col, int64_t ncol
     HPLX_PROPAGATE(trsm_any(x.A + off(c0, c0, x.lda), x.lda, x.A + off(c0, col, x.lda), x.lda, jb, ncols,
                             x.gemm_tile, st));
     HPLX_PROPAGATE(x.tm->end(id, st, (double)jb * (double)jb * (double)ncols, 16.0 * (double)jb * (double)ncols));
-    const int64_t c1 = c0 + jb;
-    const int64_t m = x.n - c1;
-    if (m > 0) {
-        id = x.tm->begin(ST_GEMM, st);
-        HPLX_PROPAGATE(launch_gemm_sub(m, ncols, jb, x.A + off(c1, c0, x.lda), x.lda, x.A + off(c0, col, x.lda),
-                                       x.lda, x.A + off(c1, col, x.lda), x.lda, x.gemm_tile | kGemmTrailing, st));
-        HPLX_PROPAGATE(x.tm->end(id, st, 2.0 * (double)m * (double)ncols * (double)jb,
-                                 16.0 * (double)m * (double)ncols + 8.0 * (double)jb * ((double)m + (double)ncols)));
-    }
-    return HPL_OK;
+    return with_gemm ? update_gemm(x, c0, jb, col, ncols, st) : HPL_OK;
 }
 
 // Reports (and clears) an out-of-range pivot seen by the plan kernel; hbuf[2] holds the flag.
@@ -405,7 +410,8 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
     Timer tm(d, opt_timing.load() != 0);
     Ctx x{d, A, n, lda, ipiv, (int)opt_panel_base.load(), (int)opt_panel_wgs.load(), (int)opt_gemm_tile.load(), &tm};
     const int64_t progress = opt_progress.load();
-    const bool la = opt_lookahead.load() != 0 && opt_serialize.load() == 0 && n > nb;
+    const int64_t la_mode = opt_lookahead.load();
+    const bool la = la_mode != 0 && opt_serialize.load() == 0 && n > nb;
     hipStream_t sp = la ? d->sp : su;
     const int64_t np = (n + nb - 1) / nb;
     const double t0 = now_s();
@@ -423,24 +429,38 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
         const int64_t jb = (n - c0) < nb ? (n - c0) : nb;
         const int64_t c1 = c0 + jb;
         SwapPlan *plans = d->ring[j % kRing];
+        bool left_done = false;
         if (la) HPLX_TRY(hipStreamWaitEvent(su, d->ev_panel[j % kRing], 0));
         if (c1 < n) {
             const int64_t jb2 = (n - c1) < nb ? (n - c1) : nb;
             SwapPlan *next_plans = d->ring[(j + 1) % kRing];
             if (la) {
-                HPLX_PROPAGATE(update_cols(x, c0, jb, c1, jb2, plans, su));
+                HPLX_PROPAGATE(update_cols(x, c0, jb, c1, jb2, plans, su, true));
                 HPLX_TRY(hipEventRecord(d->ev_la[j % kRing], su));
                 HPLX_TRY(hipStreamWaitEvent(sp, d->ev_la[j % kRing], 0));
                 HPLX_PROPAGATE(panel_full(x, c1, jb2, next_plans, sp));
                 HPLX_TRY(hipEventRecord(d->ev_panel[(j + 1) % kRing], sp));
-                HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, n - c1 - jb2, plans, su));
+                if (la_mode == 2) {
+                    // full overlap: the trailing GEMM shares the GPU with the panel
+                    HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, n - c1 - jb2, plans, su, true));
+                } else {
+                    // the panel overlaps the memory-bound RS and TRSM of the
+                    // remaining columns and the interchanges on the left; the
+                    // trailing GEMM starts once the panel is done, so the two
+                    // never compete for the CUs
+                    HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, n - c1 - jb2, plans, su, false));
+                    HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
+                    left_done = true;
+                    HPLX_TRY(hipStreamWaitEvent(su, d->ev_panel[(j + 1) % kRing], 0));
+                    HPLX_PROPAGATE(update_gemm(x, c0, jb, c1 + jb2, n - c1 - jb2, su));
+                }
             } else {
-                HPLX_PROPAGATE(update_cols(x, c0, jb, c1, n - c1, plans, su));
+                HPLX_PROPAGATE(update_cols(x, c0, jb, c1, n - c1, plans, su, true));
                 HPLX_PROPAGATE(panel_full(x, c1, jb2, next_plans, su));
             }
         }
         // interchanges of panel j on the columns to its left (L in LAPACK form)
-        HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
+        if (!left_done) HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
         HPLX_TRY(hipEventRecord(d->ev_iter[j % kRing], su));
         // keep at most two iterations queued ahead of the device
         if (j >= 2) HPLX_TRY(hipEventSynchronize(d->ev_iter[(j - 2) % kRing]));
@@ -654,7 +674,7 @@ int hpl_set_option(int key, int64_t value)
 {
     switch (key) {
     case HPL_OPT_LOOKAHEAD:
-        if (value != 0 && value != 1) return -2;
+        if (value < 0 || value > 2) return -2;
         opt_lookahead = value;
         return 0;
     case HPL_OPT_PANEL_BASE:

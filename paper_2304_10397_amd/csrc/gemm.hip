@@ -71,8 +71,6 @@ __device__ __forceinline__ void tile_of_block(int64_t bid, int64_t nwg, int64_t 
     tn = r / gm;
 }
 
-// TRAIL = 1 marks the instances used for the trailing update (same code; a
-// distinct symbol so that profiles separate it from the panel's inner GEMMs).
 template <int BM, int BN, int WM, int WN, int TRAIL>
 __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
     int64_t m, int64_t n, int64_t k, const double *__restrict__ A, int64_t lda,

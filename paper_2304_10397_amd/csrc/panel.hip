@@ -213,6 +213,8 @@ __global__ __launch_bounds__(kLeafThreads) void panel_leaf_kernel(double *__rest
 // payload; writers use relaxed agent-scope atomic stores, readers poll with
 // relaxed agent-scope atomic loads until each word they need shows the current
 // tag, so each word validates itself and no ordering between words is needed.
+// Each step costs one round trip: every workgroup reads all candidates' keys
+// and rows (and the diagonal row) at once and picks the pivot locally.
 // Slot of workgroup g: words 0..2 = tagged (row index, |a| low, |a| high),
 // words 3 + 2j, 4 + 2j = tagged halves of the candidate row's value in column
 // k + j.  The diagonal row is published by workgroup 0 in a separate area.
@@ -280,6 +282,7 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
     __shared__ double rv[kRegWaves];
     __shared__ int64_t ri[kRegWaves];
     __shared__ int s_abort;
+    __shared__ uint32_t xw[kLeafMaxWGs * (3 + 2 * kRegW) + 2 * kRegW];  // payloads of one exchange
 
     double *S = A + off(c, c, lda);
     const int g = blockIdx.x, t = threadIdx.x;
@@ -351,46 +354,42 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
                 const unsigned long long bits = (unsigned long long)__double_as_longlong(topv[j]);
                 put_tagged(topw + (size_t)par * 2 * kRegW + e, tag, (e & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits);
             }
-            // ---- 3. gather every workgroup's candidate key
-            double gv = -1.0;
-            int64_t gi = INT64_MAX;
-            bool ok = true;
-            if (t < G) {
-                const unsigned long long *sq = slots + ((size_t)par * kLeafMaxWGs + t) * kLeafSlotWords;
-                uint32_t ix = 0, lo = 0, hi = 0;
-                ok = get_tagged(sq, tag, ix, sync.abort_flag, t0) && get_tagged(sq + 1, tag, lo, sync.abort_flag, t0) &&
-                     get_tagged(sq + 2, tag, hi, sync.abort_flag, t0);
-                if (ok) {
-                    gv = dbl_of(lo, hi);
-                    gi = (int64_t)ix;
-                }
-            }
-            if (!ok) s_abort = 1;
-            block_argmax512(gv, gi, rv, ri);
-            if (s_abort) return;
-            pv = gv;
-            p = gi;
-            // ---- 4. the winner's row and the diagonal row
-            const int64_t owner = (p == INT64_MAX) ? 0 : p / R;
-            const unsigned long long *sw = slots + ((size_t)par * kLeafMaxWGs + (owner < G ? owner : G - 1)) * kLeafSlotWords;
-            if (t < 2 * na) {
-                uint32_t lo = 0, hi = 0;
-                const int j = t >> 1;
-                bool ok2 = true;
-                if ((t & 1) == 0) {
-                    ok2 = get_tagged(sw + 3 + 2 * j, tag, lo, sync.abort_flag, t0) &&
-                          get_tagged(sw + 4 + 2 * j, tag, hi, sync.abort_flag, t0);
-                    if (ok2) u[j] = dbl_of(lo, hi);
+            // ---- 3. one round trip: every candidate's key and row, and the
+            //      diagonal row, all as tagged words, into LDS
+            const int per = 3 + 2 * na;           // words per slot this step
+            const int nwords = G * per + 2 * na;  // + diagonal row
+            for (int e = t; e < nwords; e += kRegThreads) {
+                uint32_t pay = 0;
+                const unsigned long long *src;
+                if (e < G * per) {
+                    const int q = e / per, wi = e - q * per;
+                    src = slots + ((size_t)par * kLeafMaxWGs + q) * kLeafSlotWords + wi;
                 } else {
-                    const unsigned long long *tw = topw + (size_t)par * 2 * kRegW;
-                    ok2 = get_tagged(tw + 2 * j, tag, lo, sync.abort_flag, t0) &&
-                          get_tagged(tw + 2 * j + 1, tag, hi, sync.abort_flag, t0);
-                    if (ok2) tr[j] = dbl_of(lo, hi);
+                    src = topw + (size_t)par * 2 * kRegW + (e - G * per);
                 }
-                if (!ok2) s_abort = 1;
+                if (!get_tagged(src, tag, pay, sync.abort_flag, t0)) s_abort = 1;
+                xw[e] = pay;
             }
             __syncthreads();
             if (s_abort) return;
+            double gv = -1.0;
+            int64_t gi = INT64_MAX;
+            if (t < G) {
+                const uint32_t *kw = xw + t * per;
+                gv = dbl_of(kw[1], kw[2]);
+                gi = (int64_t)kw[0];
+            }
+            block_argmax512(gv, gi, rv, ri);
+            pv = gv;
+            p = gi;
+            // ---- 4. the winner's row and the diagonal row from LDS
+            const int64_t owner = (p == INT64_MAX) ? 0 : p / R;
+            const uint32_t *ww = xw + (owner < G ? owner : G - 1) * per;
+            const uint32_t *tw = xw + G * per;
+            if (t < na) {
+                u[t] = dbl_of(ww[3 + 2 * t], ww[4 + 2 * t]);
+                tr[t] = dbl_of(tw[2 * t], tw[2 * t + 1]);
+            }
         }
         __syncthreads();
         const bool singular = !(pv > 0.0);

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *_
 #pragma unroll 8
         for (int s = 0; s < kBs; ++s) {
             const int k = lower ? s : kBs - 1 - s;
-            double xk = __shfl(x, k, 64);
+            double xk = read_lane(x, k);
             if (!unit) xk = xk / Td[k][k];
             if (lane == k) x = xk;
             const bool below = lower ? (lane > k) : (lane < k);

@@ -139,12 +139,90 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
     }
 }
 
+// Small TRSM (the panel's inner solves: nbk <= 256, few columns).  One wave per
+// column of B: lane l holds rows l, l+64, l+128, l+192 of that column, and step
+// k broadcasts the finished x_k with v_readlane (k is uniform), so the
+// dependency chain per step is a readlane and an FMA.  The 4 waves of a
+// workgroup share L, staged through LDS 16 columns at a time (double-buffered:
+// the next chunk is fetched into registers while the current one is used).
+constexpr int kSmRPL = 4;    // rows per lane (nbk <= 256)
+constexpr int kSmChunk = 16; // columns of L per LDS stage
+__global__ __launch_bounds__(256) void trsm_small_kernel(const double *__restrict__ L, int64_t ldl,
+                                                         double *__restrict__ B, int64_t ldb, int nbk,
+                                                         int64_t ncols)
+{
+    __shared__ double Lc[2][kSmChunk][64 * kSmRPL + 1];  // Lc[buf][kk][r] = L(r, chunk*16 + kk)
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t col = (int64_t)blockIdx.x * 4 + wave;
+    const bool live = col < ncols;
+    double x[kSmRPL];
+#pragma unroll
+    for (int s = 0; s < kSmRPL; ++s) {
+        const int r = lane + 64 * s;
+        x[s] = (live && r < nbk) ? B[off(r, col, ldb)] : 0.0;
+    }
+    const int nchunk = (nbk + kSmChunk - 1) / kSmChunk;
+    // each thread fetches 16 of the 16 x 256 chunk entries: column kk = t / 16, rows (t % 16) + 16e
+    double pre[kSmChunk];
+    auto fetch = [&](int ch) {
+        const int kk = t >> 4, r0 = t & 15;
+        const int gc = ch * kSmChunk + kk;
+#pragma unroll
+        for (int e = 0; e < kSmChunk; ++e) {
+            const int r = r0 + 16 * e;
+            pre[e] = (gc < nbk && r < nbk) ? L[off(r, gc, ldl)] : 0.0;
+        }
+    };
+    auto stash = [&](int buf) {
+        const int kk = t >> 4, r0 = t & 15;
+#pragma unroll
+        for (int e = 0; e < kSmChunk; ++e) Lc[buf][kk][r0 + 16 * e] = pre[e];
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) fetch(ch + 1);
+        const int kend = (nbk - ch * kSmChunk) < kSmChunk ? (nbk - ch * kSmChunk) : kSmChunk;
+        for (int kk = 0; kk < kend; ++kk) {
+            const int k = ch * kSmChunk + kk;
+            const int sk = k >> 6, lk = k & 63;
+            double xs = x[0];
+#pragma unroll
+            for (int s = 1; s < kSmRPL; ++s)
+                if (sk == s) xs = x[s];
+            const double xk = read_lane(xs, lk);
+#pragma unroll
+            for (int s = 0; s < kSmRPL; ++s) {
+                const int r = lane + 64 * s;
+                if (r > k) x[s] = __fma_rn(-Lc[buf][kk][r], xk, x[s]);
+            }
+        }
+        if (ch + 1 < nchunk) stash(buf ^ 1);
+        __syncthreads();
+    }
+    if (live) {
+#pragma unroll
+        for (int s = 0; s < kSmRPL; ++s) {
+            const int r = lane + 64 * s;
+            if (r < nbk) B[off(r, col, ldb)] = x[s];
+        }
+    }
+}
+
 }  // namespace
 
 int launch_trsm_llnu(const double *L, int64_t ldl, double *B, int64_t ldb, int64_t nbk, int64_t ncols,
                      hipStream_t st)
 {
     if (nbk <= 0 || ncols <= 0) return HPL_OK;
+    if (nbk <= 64 * kSmRPL && ncols <= 4096) {
+        const int64_t g = (ncols + 3) / 4;
+        hipLaunchKernelGGL(trsm_small_kernel, dim3((unsigned)g), dim3(256), 0, st, L, ldl, B, ldb, (int)nbk, ncols);
+        HPLX_TRY_LAUNCH();
+        return HPL_OK;
+    }
     if (nbk > 16 * kTrMaxRB) return HPL_ERR_INTERNAL;
     const int64_t g = (ncols + kTrWB - 1) / kTrWB;
     if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;

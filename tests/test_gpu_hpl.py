@@ -141,7 +141,7 @@ def test_dyadic_bit_exact(n, nb, base):
 def test_lookahead_and_serialize_bitwise(n, nb):
     h = hpl()
     results = []
-    for la, ser, wgs in [(1, 0, 128), (0, 0, 128), (1, 1, 128), (1, 0, 5), (1, 0, 1)]:
+    for la, ser, wgs in [(1, 0, 128), (0, 0, 128), (2, 0, 128), (1, 1, 128), (1, 0, 5), (2, 0, 1)]:
         h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, la)
         h.hpl_set_option(h.HPL_OPT_SERIALIZE, ser)
         h.hpl_set_option(h.HPL_OPT_PANEL_WGS, wgs)
