@@ -23,6 +23,12 @@ METRIC = "HPL TFLOP/s (2N³/3+2N²) & % FP64 MFMA peak; MxP+IR speed-up at FP64 
 PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X datasheet, dense FP64 matrix
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per trailing-GEMM launch measured with rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by a 2048 MiB copy: x2.000 and x1.000) at the default
+# workload, valid only for the GEMM source with this SHA-256 prefix.
+MEASURED_TRAFFIC = {"gemm_sha256_16": "bd125ffb6ce5b673", "n": 163840, "nb": 512,
+                    "fetch_gb": 94.48, "write_gb": 35.86}
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -60,6 +66,18 @@ def cpu_baseline(n_sample, seed):
     }
 
 
+def measured_traffic(n, nb):
+    """Counter-measured bytes per trailing-GEMM launch, or None if the kernel or workload differs."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2304_10397_amd", "csrc", "gemm.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    t = MEASURED_TRAFFIC
+    if sha != t["gemm_sha256_16"] or n != t["n"] or nb != t["nb"]:
+        return None
+    return round((t["fetch_gb"] + t["write_gb"]) * 1e9)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,8 +88,11 @@ def main():
     ap.add_argument("--lookahead", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2304)
     ap.add_argument("--pad", type=int, default=0, help="lda = n + pad")
-    ap.add_argument("--cpu-sample", type=int, default=3072, help="N of the oracle sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="N of the oracle sample (0: skip)")
     ap.add_argument("--progress", type=int, default=32, help="progress line every k panels (stderr)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 3 device-to-device copies of MIB MiB (reference for the HBM byte "
+                         "counters FETCH_SIZE / WRITE_SIZE) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -84,6 +105,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nbytes} bytes ({nbytes >> 10} KiB read + written each)")
+        return
     n, nb = args.n, args.nb
     log(f"device {torch.cuda.get_device_name(dev)}; N={n} NB={nb} look-ahead={args.lookahead}")
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, args.lookahead)
@@ -169,7 +199,9 @@ def main():
             "launches": g["launches"],
             "avg_launch_ms": round(g["ms"] / g["launches"], 4) if g["launches"] else None,
             "avg_launch_gflop": round(g["flops"] / g["launches"] / 1e9, 3) if g["launches"] else None,
-            "traffic": None,
+            "traffic": measured_traffic(n, nb),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": round(g["bytes"] / g["launches"]) if g["launches"] else None,
         },
     }
     if args.cpu_sample > 0:
