@@ -143,7 +143,9 @@ enum hpl_option {
     HPL_OPT_TIMING = 4,      /* 1: time every kernel with HIP events (see hpl_get_stats) */
     HPL_OPT_PROGRESS = 5,    /* k > 0: print a progress line to stderr every k panels */
     HPL_OPT_SERIALIZE = 6,   /* 1: run every step on one stream (debug; bit-identical) */
-    HPL_OPT_GEMM_TILE = 7    /* trailing-update GEMM tile variant id (default 0 = auto) */
+    HPL_OPT_GEMM_TILE = 7    /* GEMM kernel variant (default 0 = auto): 1..4 the 4x4x4 tiles
+                                128x128, 128x64, 64x64, 128x32; 5, 6 the streamed 16x16x4
+                                tiles 128x128, 128x64 (where their preconditions hold) */
 };
 /* Returns 0, or -1 (bad key) / -2 (bad value); the option is unchanged on error. */
 int hpl_set_option(int key, int64_t value);

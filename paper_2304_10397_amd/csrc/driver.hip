@@ -698,7 +698,7 @@ int hpl_set_option(int key, int64_t value)
         opt_serialize = value;
         return 0;
     case HPL_OPT_GEMM_TILE:
-        if (value < 0 || value > 4) return -2;
+        if (value < 0 || value > 6) return -2;
         opt_gemm_tile = value;
         return 0;
     default: return -1;

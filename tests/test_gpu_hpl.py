@@ -157,6 +157,31 @@ def test_lookahead_and_serialize_bitwise(n, nb):
         assert np.array_equal(LU.view(np.int64), ref[0].view(np.int64))
 
 
+@pytest.mark.parametrize("n,nb", [(1000, 64), (1030, 96), (2048, 256), (998, 48)])
+def test_gemm_variants_vs_oracle(n, nb):
+    """Every GEMM kernel variant against the oracle at ragged trailing shapes
+    (m, n not multiples of the tile); the two streamed tiles must agree bit
+    for bit, since each element sees the same MFMA sequence.  nb = 48 is not
+    a multiple of 32, so there the streamed variants fall back."""
+    h = hpl()
+    _, _, LU_o, ipiv_o, _, _ = oracle_solution(n)
+    out = {}
+    try:
+        for v in (0, 1, 2, 3, 4, 5, 6):
+            h.hpl_set_option(h.HPL_OPT_GEMM_TILE, v)
+            A, _ = gpu_system(n)
+            ipiv, info = h.hpl_factor(A, nb)
+            assert info == 0
+            assert np.array_equal(ipiv.cpu().numpy(), ipiv_o), f"variant {v}"
+            LU = to_host(A)
+            assert np.max(np.abs(LU - LU_o)) <= 1e-11 * max(1.0, np.max(np.abs(LU_o))), f"variant {v}"
+            out[v] = LU
+    finally:
+        h.hpl_set_option(h.HPL_OPT_GEMM_TILE, 0)
+    assert np.array_equal(out[5].view(np.int64), out[6].view(np.int64))
+    assert np.array_equal(out[0].view(np.int64), out[5].view(np.int64))
+
+
 @pytest.mark.parametrize("base", [8, 16, 64])
 def test_panel_base_variants_vs_oracle(base):
     h = hpl()
