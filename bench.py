@@ -26,8 +26,8 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per trailing-GEMM launch measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 2048 MiB copy: x2.000 and x1.000) at the default
 # workload, valid only for the GEMM source with this SHA-256 prefix.
-MEASURED_TRAFFIC = {"gemm_sha256_16": "bd125ffb6ce5b673", "n": 163840, "nb": 512,
-                    "fetch_gb": 94.48, "write_gb": 35.86}
+MEASURED_TRAFFIC = {"gemm_sha256_16": "98606b6baad13aa9", "n": 163840, "nb": 512,
+                    "fetch_gb": 131.66, "write_gb": 35.79}
 
 
 def log(msg):
@@ -190,7 +190,7 @@ def main():
             "phase_ms_last_step": phases,
         },
         "roofline": {
-            "kernel": "gemm_sub_kernel (trailing-update DGEMM, FP64 MFMA)",
+            "kernel": "gemm_stream_kernel (trailing-update DGEMM, FP64 MFMA 16x16x4)",
             "bound": "mfma",
             "achieved": round(gemm_tflops, 3) if gemm_tflops else None,
             "peak": PEAK_FP64_MFMA_TFLOPS,
