@@ -129,6 +129,9 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
+    peak_measured, _ = h.hpl_mfma_peak(200000)
+    log(f"measured FP64 MFMA peak (pure 16x16x4 loop): {peak_measured:.2f} TFLOP/s")
+
     A = h.colmajor(n, n, ld=n + args.pad)
     b = h.colmajor(n, 1)
     x = h.colmajor(n, 1)
@@ -182,6 +185,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "pct_fp64_mfma_peak": round(100.0 * tflops / PEAK_FP64_MFMA_TFLOPS, 2),
+        "fp64_mfma_peak_measured": round(peak_measured, 3),
+        "pct_measured_fp64_mfma_peak": round(100.0 * tflops / peak_measured, 2) if peak_measured > 0 else None,
         "config": {
             "workload": f"HPL FP64 LU+solve, N={n}, NB={nb}, look-ahead {args.lookahead}, "
                         f"A,b ~ U[-0.5,0.5) seed {args.seed}",

@@ -165,6 +165,20 @@ int64_t hpl_get_option(int key);
 int hpl_get_stats(int64_t *launches, double *ms, double *flops, double *bytes, int cap);
 void hpl_reset_stats(void);
 
+/*
+ * hpl_mfma_peak -- measured FP64 matrix-core peak of the current device, the
+ * reference next to the datasheet figure when a run is reported as a fraction
+ * of peak.  Runs a pure v_mfma_f64_16x16x4_f64 issue loop (16 independent
+ * accumulator blocks per wave, accumulators in AGPRs, two 256-thread
+ * workgroups per CU) for `iters` rounds, three times after a warm-up, and
+ * keeps the fastest.
+ *   1 iters  rounds per wave, > 0 (2e5 takes about 0.2 s on MI355X).
+ *   2 out    host double[2] = {TFLOP/s, milliseconds of the fastest launch}.
+ *   3 hip_stream
+ * Uses the library's reduction workspace (1 MB); returns after completion.
+ */
+int hpl_mfma_peak(int64_t iters, double *out, void *hip_stream);
+
 /* Frees the per-device workspace, streams and events.  Returns 0 or HPL_ERR_HIP. */
 int hpl_release(void);
 

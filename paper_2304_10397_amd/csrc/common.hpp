@@ -168,4 +168,11 @@ int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int
 int launch_apply_plans_seq(double *B, int64_t ldb, int64_t nrhs, const int32_t *plans,
                            int64_t nchunks, bool reverse, hipStream_t st);
 
+// Pure FP64 MFMA issue loop (probe.hip): nwg workgroups of 256 threads, iters
+// rounds of 16 independent 16x16x4 MFMAs per wave; mfma_peak_flops is its flop count.
+// iters must be a multiple of the loop's unroll; mfma_peak_rounds rounds it up.
+int launch_mfma_peak(double *out, int64_t nwg, int64_t iters, hipStream_t st);
+int64_t mfma_peak_rounds(int64_t iters);
+double mfma_peak_flops(int64_t nwg, int64_t iters);
+
 }  // namespace hplx

@@ -63,6 +63,7 @@ def _load():
         "hpl_get_option": (i64, [i32]),
         "hpl_get_stats": (i32, [P, P, P, P, i32]),
         "hpl_reset_stats": (None, []),
+        "hpl_mfma_peak": (i32, [i64, P, P]),
         "hpl_release": (i32, []),
         "hpl_strerror": (ctypes.c_char_p, [i32]),
         "hpl_last_error_detail": (ctypes.c_char_p, []),
@@ -77,7 +78,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("hpl_factor", "hpl_solve", "hpl_residual", "hpl_residual_gen", "hpl_generate",
             "hpl_set_option", "hpl_get_option", "hpl_get_stats", "hpl_reset_stats",
-            "hpl_release", "hpl_strerror", "hpl_last_error_detail")
+            "hpl_mfma_peak", "hpl_release", "hpl_strerror", "hpl_last_error_detail")
 
 
 def lib():
@@ -221,6 +222,13 @@ def hpl_get_stats():
 
 def hpl_reset_stats():
     _lib.hpl_reset_stats()
+
+
+def hpl_mfma_peak(iters=200000, stream=None):
+    """(TFLOP/s, ms) of a pure FP64 16x16x4 MFMA loop on the current device."""
+    out = np.zeros(2)
+    _check("hpl_mfma_peak", _lib.hpl_mfma_peak(int(iters), out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return float(out[0]), float(out[1])
 
 
 def hpl_release():

@@ -81,6 +81,14 @@ def test_residual_generate_argument_errors():
     assert L.hpl_generate(1, 0, FAKE, 0, 4, 1, None) == 0
 
 
+def test_mfma_peak_argument_errors():
+    L = h.lib()
+    out = (ctypes.c_double * 2)()
+    assert L.hpl_mfma_peak(0, out, None) == -1
+    assert L.hpl_mfma_peak(-5, out, None) == -1
+    assert L.hpl_mfma_peak(10, None, None) == -2
+
+
 def test_options_roundtrip_and_rejects():
     old = h.hpl_get_option(h.HPL_OPT_LOOKAHEAD)
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 0)

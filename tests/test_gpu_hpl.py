@@ -296,6 +296,15 @@ def test_column_dominant_no_interchanges():
     assert np.array_equal(ipiv.cpu().numpy(), np.arange(700))
 
 
+def test_mfma_peak_probe():
+    """The measured FP64 matrix peak is a plausible fraction of the 78.6 TFLOP/s datasheet figure."""
+    h = hpl()
+    tflops, ms = h.hpl_mfma_peak(50000)
+    print(f"measured FP64 MFMA peak {tflops:.2f} TFLOP/s ({ms:.2f} ms)")
+    assert 40.0 < tflops < 90.0
+    assert ms > 0.0
+
+
 def test_n_zero_is_noop():
     h = hpl()
     t = torch()
