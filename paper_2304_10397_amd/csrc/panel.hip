@@ -213,8 +213,9 @@ __global__ __launch_bounds__(kLeafThreads) void panel_leaf_kernel(double *__rest
 // payload; writers use relaxed agent-scope atomic stores, readers poll with
 // relaxed agent-scope atomic loads until each word they need shows the current
 // tag, so each word validates itself and no ordering between words is needed.
-// Each step costs one round trip: every workgroup reads all candidates' keys
-// and rows (and the diagonal row) at once and picks the pivot locally.
+// Each step costs two short round trips: every workgroup reads the G
+// candidates' keys (one word per thread, polled side by side), picks the pivot
+// locally, then reads only the winner's row and the diagonal row.
 // Slot of workgroup g: words 0..2 = tagged (row index, |a| low, |a| high),
 // words 3 + 2j, 4 + 2j = tagged halves of the candidate row's value in column
 // k + j.  The diagonal row is published by workgroup 0 in a separate area.
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
     __shared__ double rv[kRegWaves];
     __shared__ int64_t ri[kRegWaves];
     __shared__ int s_abort;
-    __shared__ uint32_t xw[kLeafMaxWGs * (3 + 2 * kRegW) + 2 * kRegW];  // payloads of one exchange
+    __shared__ uint32_t xw[3 * kLeafMaxWGs + 4 * kRegW];  // payloads of one exchange: keys, then two rows
 
     double *S = A + off(c, c, lda);
     const int g = blockIdx.x, t = threadIdx.x;
@@ -354,19 +355,13 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
                 const unsigned long long bits = (unsigned long long)__double_as_longlong(topv[j]);
                 put_tagged(topw + (size_t)par * 2 * kRegW + e, tag, (e & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits);
             }
-            // ---- 3. one round trip: every candidate's key and row, and the
-            //      diagonal row, all as tagged words, into LDS
-            const int per = 3 + 2 * na;           // words per slot this step
-            const int nwords = G * per + 2 * na;  // + diagonal row
-            for (int e = t; e < nwords; e += kRegThreads) {
+            // ---- 3. two short round trips.  (a) every candidate's key (row,
+            //      |a|): one tagged word per thread, so the polls of a step run
+            //      side by side rather than one after another
+            for (int e = t; e < 3 * G; e += kRegThreads) {
                 uint32_t pay = 0;
-                const unsigned long long *src;
-                if (e < G * per) {
-                    const int q = e / per, wi = e - q * per;
-                    src = slots + ((size_t)par * kLeafMaxWGs + q) * kLeafSlotWords + wi;
-                } else {
-                    src = topw + (size_t)par * 2 * kRegW + (e - G * per);
-                }
+                const int q = e / 3, wi = e - 3 * q;
+                const unsigned long long *src = slots + ((size_t)par * kLeafMaxWGs + q) * kLeafSlotWords + wi;
                 if (!get_tagged(src, tag, pay, sync.abort_flag, t0)) s_abort = 1;
                 xw[e] = pay;
             }
@@ -375,20 +370,29 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
             double gv = -1.0;
             int64_t gi = INT64_MAX;
             if (t < G) {
-                const uint32_t *kw = xw + t * per;
-                gv = dbl_of(kw[1], kw[2]);
-                gi = (int64_t)kw[0];
+                gv = dbl_of(xw[3 * t + 1], xw[3 * t + 2]);
+                gi = (int64_t)xw[3 * t];
             }
             block_argmax512(gv, gi, rv, ri);
             pv = gv;
             p = gi;
-            // ---- 4. the winner's row and the diagonal row from LDS
-            const int64_t owner = (p == INT64_MAX) ? 0 : p / R;
-            const uint32_t *ww = xw + (owner < G ? owner : G - 1) * per;
-            const uint32_t *tw = xw + G * per;
+            // (b) the winner's row and the diagonal row (2 words per value)
+            const int64_t owner0 = (p == INT64_MAX) ? 0 : p / R;
+            const int owner = (int)(owner0 < G ? owner0 : G - 1);
+            uint32_t *rw = xw + 3 * kLeafMaxWGs;
+            if (t < 4 * na) {
+                uint32_t pay = 0;
+                const unsigned long long *src =
+                    (t < 2 * na) ? slots + ((size_t)par * kLeafMaxWGs + owner) * kLeafSlotWords + 3 + t
+                                 : topw + (size_t)par * 2 * kRegW + (t - 2 * na);
+                if (!get_tagged(src, tag, pay, sync.abort_flag, t0)) s_abort = 1;
+                rw[t] = pay;
+            }
+            __syncthreads();
+            if (s_abort) return;
             if (t < na) {
-                u[t] = dbl_of(ww[3 + 2 * t], ww[4 + 2 * t]);
-                tr[t] = dbl_of(tw[2 * t], tw[2 * t + 1]);
+                u[t] = dbl_of(rw[2 * t], rw[2 * t + 1]);
+                tr[t] = dbl_of(rw[2 * na + 2 * t], rw[2 * na + 2 * t + 1]);
             }
         }
         __syncthreads();
