@@ -42,6 +42,12 @@ def lib():
         L.oracle_residual.argtypes = [P, i64, i64, P, i64, P, i64, i64, P]
         L.oracle_residual_gen.restype = None
         L.oracle_residual_gen.argtypes = [u64, i64, P, i64, P, i64, i64, P]
+        L.oracle_normal.restype = dbl
+        L.oracle_normal.argtypes = [u64, u64]
+        L.oracle_gen_normal.restype = None
+        L.oracle_gen_normal.argtypes = [u64, u64, P, i64, i64, i64]
+        L.oracle_solve_grad.restype = i64
+        L.oracle_solve_grad.argtypes = [P, i64, i64, P, i64, i64, P, i64, P, i64, P, i64, P, i64]
         L.oracle_det.restype = None
         L.oracle_det.argtypes = [P, P, i64, i64, P, P, P]
         _lib = L
@@ -144,3 +150,31 @@ def det(LU, ipiv):
 def uniform(s0: int, idx: int) -> float:
     """Value of linear index idx of the stream whose SplitMix64 state is s0."""
     return float(lib().oracle_uniform(s0 & (2**64 - 1), idx & (2**64 - 1)))
+
+
+def normal(s0: int, idx: int) -> float:
+    """Box-Muller standard normal value of linear index idx of the stream with state s0."""
+    return float(lib().oracle_normal(s0 & (2**64 - 1), idx & (2**64 - 1)))
+
+
+def gen_normal(seed: int, stream: int, rows: int, cols: int, ld: int = None) -> np.ndarray:
+    """rows x cols Fortran-ordered matrix of standard normal values of the stream."""
+    ld = rows if ld is None else ld
+    buf = np.zeros((ld, cols), dtype=np.float64, order="F")
+    lib().oracle_gen_normal(seed, stream, _ptr(buf), rows, cols, max(ld, 1))
+    return buf[:rows, :]
+
+
+def solve_grad(A, B, W):
+    """(X, grad_B, grad_A, info) for X = A^{-1} B and the loss sum(W * X)."""
+    _check(A)
+    n = A.shape[0]
+    B = np.asfortranarray(B.reshape(n, -1), dtype=np.float64)
+    W = np.asfortranarray(W.reshape(n, -1), dtype=np.float64)
+    nrhs = B.shape[1]
+    X = np.zeros((n, nrhs), order="F")
+    GB = np.zeros((n, nrhs), order="F")
+    GA = np.zeros((n, n), order="F")
+    info = lib().oracle_solve_grad(_ptr(A), n, _ld(A), _ptr(B), _ld(B), nrhs, _ptr(W), _ld(W),
+                                   _ptr(X), max(n, 1), _ptr(GB), max(n, 1), _ptr(GA), max(n, 1))
+    return X, GB, GA, int(info)

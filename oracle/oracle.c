@@ -23,6 +23,10 @@
  * Precision: IEEE fp64 throughout (the paper's double precision), compiled
  * with -ffp-contract=off so every a*b+c is two correctly rounded operations.
  *
+ * Beyond the paper (the differentiable form of the solve): the standard
+ * normal input generator (Box-Muller) and the gradient of a linear solve,
+ * oracle_normal / oracle_solve_grad at the end of the file.
+ *
  * Parity pins (what ties this file to something other than itself) live in
  * tests/test_oracle_*.py: Leibniz and Bareiss determinants, exact dyadic
  * factorizations, integer systems with known solutions, special matrices,
@@ -33,6 +37,7 @@
 #include <stddef.h>
 #include <math.h>
 #include <string.h>
+#include <stdlib.h>
 
 #define IDX(i, j, ld) ((size_t)(i) + (size_t)(j) * (size_t)(ld))
 
@@ -261,4 +266,71 @@ void oracle_det(const double *LU, const int32_t *ipiv, int64_t n, int64_t lda,
     *sign = s;
     *log2abs = l2;
     *exact = s * fabs(prod);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Standard normal input (the weights W of the differentiable solve's loss). */
+/* Box-Muller transform (Box and Muller, 1958) of two uniforms of the stream */
+/* at the SplitMix64 outputs 2 idx and 2 idx + 1:                            */
+/*   u1 = (h(2 idx) >> 11) 2^-53,  u2 = (h(2 idx + 1) >> 11) 2^-53 in [0,1), */
+/*   z  = sqrt(-2 ln(1 - u1)) cos(2 pi u2)                                   */
+/* (1 - u1 lies in (0, 1], so the logarithm is finite).  The value depends   */
+/* on the C library's log and cos; another implementation of the same        */
+/* formula agrees to a few units in the last place, not bit for bit.         */
+/* ------------------------------------------------------------------------ */
+double oracle_normal(uint64_t s0, uint64_t idx)
+{
+    const double u1 = (double)(oracle_splitmix64_at(s0, 2 * idx) >> 11) * 0x1.0p-53;
+    const double u2 = (double)(oracle_splitmix64_at(s0, 2 * idx + 1) >> 11) * 0x1.0p-53;
+    const double two_pi = 6.283185307179586476925286766559;
+    return sqrt(-2.0 * log(1.0 - u1)) * cos(two_pi * u2);
+}
+
+/* M[i + j*ld] = normal value of linear index i + j*rows of stream (seed, stream). */
+void oracle_gen_normal(uint64_t seed, uint64_t stream, double *M, int64_t rows, int64_t cols, int64_t ld)
+{
+    const uint64_t s0 = oracle_stream_key(seed, stream);
+    for (int64_t j = 0; j < cols; ++j)
+        for (int64_t i = 0; i < rows; ++i) M[IDX(i, j, ld)] = oracle_normal(s0, (uint64_t)(i + j * rows));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradient of a linear solve.  For X = A^{-1} B and a loss L(X) whose       */
+/* gradient with respect to X is W (for L = sum_ij W_ij X_ij that is W       */
+/* itself), differentiating A X = B gives A dX = dB - dA X, so               */
+/*   dL = <W, dX> = <A^{-T} W, dB> - <(A^{-T} W) X^T, dA>,                   */
+/* i.e. grad_B = A^{-T} W and grad_A = -grad_B X^T.  The oracle takes the    */
+/* steps literally: factor a copy of A (oracle_lu), X by the forward solve,  */
+/* grad_B by the transposed solve with the same factors, grad_A as the       */
+/* explicit outer product summed over the right-hand sides in order.         */
+/* Outputs X (n x nrhs at ldx), GB (n x nrhs at ldgb), GA (n x n at ldga).   */
+/* Returns info of the factorization (0, or k+1 for a zero pivot).           */
+/* ------------------------------------------------------------------------ */
+int64_t oracle_solve_grad(const double *A, int64_t n, int64_t lda, const double *B, int64_t ldb, int64_t nrhs,
+                          const double *W, int64_t ldw, double *X, int64_t ldx, double *GB, int64_t ldgb,
+                          double *GA, int64_t ldga)
+{
+    if (n <= 0) return 0;
+    double *LU = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+    int32_t *ipiv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t info = 0;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) LU[IDX(i, j, n)] = A[IDX(i, j, lda)];
+    oracle_lu(LU, n, n, ipiv, &info);
+    for (int64_t r = 0; r < nrhs; ++r)
+        for (int64_t i = 0; i < n; ++i) {
+            X[IDX(i, r, ldx)] = B[IDX(i, r, ldb)];
+            GB[IDX(i, r, ldgb)] = W[IDX(i, r, ldw)];
+        }
+    oracle_solve(LU, ipiv, X, n, n, nrhs, ldx, 0);
+    oracle_solve(LU, ipiv, GB, n, n, nrhs, ldgb, 1);
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t r = 0; r < nrhs; ++r) s = s + GB[IDX(i, r, ldgb)] * X[IDX(j, r, ldx)];
+            GA[IDX(i, j, ldga)] = -s;
+        }
+    free(LU);
+    free(ipiv);
+    return info;
 }
