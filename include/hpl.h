@@ -133,6 +133,41 @@ int hpl_residual_gen(uint64_t seed, int64_t n, const double *X, int64_t ldx, con
 int hpl_generate(uint64_t seed, uint64_t stream_id, double *M, int64_t rows, int64_t cols,
                  int64_t ld, void *hip_stream);
 
+/*
+ * Differentiable solve.  For X = A^{-1} B (hpl_factor + hpl_solve) and a loss L
+ * with G = dL/dX, the adjoint of the solve is grad_B = A^{-T} G, obtained with
+ * hpl_solve(trans = 1) on the saved factors, and grad_A = -grad_B X^T
+ * (differentiating A X = B gives A dX = dB - dA X).
+ *
+ * hpl_solve_grad_a -- dA = -GB X^T, every entry of dA written once.
+ *   1 GB   device n x nrhs at ldgb (grad_B);  2 ldgb >= max(1, n)
+ *   3 X    device n x nrhs at ldx (the solution);  4 ldx >= max(1, n)
+ *   5 n    0 <= n <= 2097120;  6 nrhs >= 0 (nrhs = 0 writes zeros)
+ *   7 dA   device n x n at ldda (written, must not overlap GB or X);  8 ldda >= max(1, n)
+ *   9 hip_stream
+ * Each entry is -(sum over r = 0..nrhs-1 of GB(i,r) X(j,r)), summed in that order.
+ */
+int hpl_solve_grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ldx, int64_t n,
+                     int64_t nrhs, double *dA, int64_t ldda, void *hip_stream);
+
+/*
+ * hpl_generate_normal -- standard normal values for the loss weights of the
+ * differentiable solve: the Box-Muller transform (Box, Muller 1958) of the
+ * outputs 2 idx and 2 idx + 1 of the hpl_generate stream (seed, stream_id),
+ * u = (h >> 11) 2^-53, z = sqrt(-2 ln(1 - u1)) cos(2 pi u2), idx = i + j*rows.
+ * Arguments as hpl_generate.  The values depend on the device's log and cos
+ * (within a few units in the last place of a correctly rounded evaluation).
+ */
+int hpl_generate_normal(uint64_t seed, uint64_t stream_id, double *M, int64_t rows, int64_t cols,
+                        int64_t ld, void *hip_stream);
+
+/*
+ * hpl_add_diagonal -- M(i,i) += alpha for i < n (the differentiable-solve input
+ * A = U[-0.5, 0.5) + 8 I).  1 M device n x n at ld; 2 n >= 0; 3 ld >= max(1, n);
+ * 4 alpha; 5 hip_stream.
+ */
+int hpl_add_diagonal(double *M, int64_t n, int64_t ld, double alpha, void *hip_stream);
+
 /* Options (process-wide, read at the start of each call). */
 enum hpl_option {
     HPL_OPT_LOOKAHEAD = 1,   /* 0: none.  1 (default): panel j+1 is factored while the

@@ -175,4 +175,11 @@ int launch_mfma_peak(double *out, int64_t nwg, int64_t iters, hipStream_t st);
 int64_t mfma_peak_rounds(int64_t iters);
 double mfma_peak_flops(int64_t nwg, int64_t iters);
 
+// Differentiable solve (gen.hip, grad.hip): Box-Muller normal generator, M(i,i) += alpha,
+// and D = -G X^T for n x k panels G, X (rank-k outer product written once).
+int launch_generate_normal(uint64_t s0, double *M, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
+int launch_add_diagonal(double *M, int64_t n, int64_t ld, double alpha, hipStream_t st);
+int launch_grad_a(const double *G, int64_t ldg, const double *X, int64_t ldx, int64_t n, int64_t k, double *D,
+                  int64_t ldd, hipStream_t st);
+
 }  // namespace hplx

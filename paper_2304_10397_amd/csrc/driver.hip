@@ -670,6 +670,56 @@ int hpl_generate(uint64_t seed, uint64_t stream_id, double *M, int64_t rows, int
     return HPL_OK;
 }
 
+int hpl_generate_normal(uint64_t seed, uint64_t stream_id, double *M, int64_t rows, int64_t cols, int64_t ld,
+                        void *hip_stream)
+{
+    if (rows > 0 && cols > 0 && M == nullptr) return -3;
+    if (rows < 0) return -4;
+    if (cols < 0) return -5;
+    if (ld < (rows > 1 ? rows : 1)) return -6;
+    if (rows == 0 || cols == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HPLX_PROPAGATE(launch_generate_normal(stream_state(seed, stream_id), M, rows, cols, ld, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    return HPL_OK;
+}
+
+int hpl_add_diagonal(double *M, int64_t n, int64_t ld, double alpha, void *hip_stream)
+{
+    if (n > 0 && M == nullptr) return -1;
+    if (n < 0) return -2;
+    if (ld < (n > 1 ? n : 1)) return -3;
+    if (n == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HPLX_PROPAGATE(launch_add_diagonal(M, n, ld, alpha, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    return HPL_OK;
+}
+
+int hpl_solve_grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ldx, int64_t n, int64_t nrhs,
+                     double *dA, int64_t ldda, void *hip_stream)
+{
+    if (n > 0 && nrhs > 0 && GB == nullptr) return -1;
+    if (ldgb < (n > 1 ? n : 1)) return -2;
+    if (n > 0 && nrhs > 0 && X == nullptr) return -3;
+    if (ldx < (n > 1 ? n : 1)) return -4;
+    if (n < 0 || n > ((int64_t)65535 * 32)) return -5;
+    if (nrhs < 0) return -6;
+    if (n > 0 && dA == nullptr) return -7;
+    if (ldda < (n > 1 ? n : 1)) return -8;
+    if (n == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HPLX_PROPAGATE(launch_grad_a(GB, ldgb, X, ldx, n, nrhs, dA, ldda, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    return HPL_OK;
+}
+
 int hpl_set_option(int key, int64_t value)
 {
     switch (key) {

@@ -35,6 +35,38 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(uint64_t s0, doub
     }
 }
 
+// Standard normal values (the weights of the differentiable solve's loss):
+// Box-Muller of the stream's outputs 2 idx and 2 idx + 1,
+// z = sqrt(-2 ln(1 - u1)) cos(2 pi u2), u = (h >> 11) 2^-53 in [0, 1).
+__device__ __forceinline__ double normal_value(uint64_t s0, uint64_t idx)
+{
+    const double u1 = (double)(sm64_mix(s0 + (2ull * idx + 1ull) * kGamma) >> 11) * 0x1.0p-53;
+    const double u2 = (double)(sm64_mix(s0 + (2ull * idx + 2ull) * kGamma) >> 11) * 0x1.0p-53;
+    return sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586476925286766559 * u2);
+}
+
+__global__ __launch_bounds__(kGenThreads) void generate_normal_kernel(uint64_t s0, double *__restrict__ M,
+                                                                      int64_t rows, int64_t cols, int64_t ld)
+{
+    const int64_t rows_per_block = (int64_t)kGenThreads * kGenRowsPerThread;
+    const int64_t r_base = (int64_t)blockIdx.x * rows_per_block + threadIdx.x;
+    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) {
+        double *col = M + (size_t)j * (size_t)ld;
+        const uint64_t cbase = (uint64_t)j * (uint64_t)rows;
+#pragma unroll
+        for (int q = 0; q < kGenRowsPerThread; ++q) {
+            int64_t i = r_base + (int64_t)q * kGenThreads;
+            if (i < rows) col[i] = normal_value(s0, cbase + (uint64_t)i);
+        }
+    }
+}
+
+__global__ void add_diagonal_kernel(double *__restrict__ M, int64_t n, int64_t ld, double alpha)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) M[off(i, i, ld)] += alpha;
+}
+
 __global__ void fill_u64_kernel(unsigned long long *p, int64_t count, unsigned long long v)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -136,6 +168,29 @@ int launch_generate(uint64_t s0, double *M, int64_t rows, int64_t cols, int64_t 
     if (gx > 0x7fffffff) return HPL_ERR_INTERNAL;
     hipLaunchKernelGGL(generate_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(kGenThreads), 0, st, s0,
                        M, rows, cols, ld);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_generate_normal(uint64_t s0, double *M, int64_t rows, int64_t cols, int64_t ld, hipStream_t st)
+{
+    if (rows <= 0 || cols <= 0) return HPL_OK;
+    const int64_t rows_per_block = (int64_t)kGenThreads * kGenRowsPerThread;
+    int64_t gx = (rows + rows_per_block - 1) / rows_per_block;
+    int64_t gy = cols < 65535 ? cols : 65535;
+    if (gx > 0x7fffffff) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(generate_normal_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(kGenThreads), 0, st, s0,
+                       M, rows, cols, ld);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_add_diagonal(double *M, int64_t n, int64_t ld, double alpha, hipStream_t st)
+{
+    if (n <= 0) return HPL_OK;
+    const int64_t g = (n + 255) / 256;
+    if (g > 0x7fffffff) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(add_diagonal_kernel, dim3((unsigned)g), dim3(256), 0, st, M, n, ld, alpha);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }

@@ -64,6 +64,9 @@ def _load():
         "hpl_get_stats": (i32, [P, P, P, P, i32]),
         "hpl_reset_stats": (None, []),
         "hpl_mfma_peak": (i32, [i64, P, P]),
+        "hpl_solve_grad_a": (i32, [P, i64, P, i64, i64, i64, P, i64, P]),
+        "hpl_generate_normal": (i32, [u64, u64, P, i64, i64, i64, P]),
+        "hpl_add_diagonal": (i32, [P, i64, i64, dbl, P]),
         "hpl_release": (i32, []),
         "hpl_strerror": (ctypes.c_char_p, [i32]),
         "hpl_last_error_detail": (ctypes.c_char_p, []),
@@ -78,7 +81,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("hpl_factor", "hpl_solve", "hpl_residual", "hpl_residual_gen", "hpl_generate",
             "hpl_set_option", "hpl_get_option", "hpl_get_stats", "hpl_reset_stats",
-            "hpl_mfma_peak", "hpl_release", "hpl_strerror", "hpl_last_error_detail")
+            "hpl_mfma_peak", "hpl_solve_grad_a", "hpl_generate_normal", "hpl_add_diagonal",
+            "hpl_release", "hpl_strerror", "hpl_last_error_detail")
 
 
 def lib():
@@ -196,6 +200,92 @@ def hpl_generate(seed, stream_id, M, stream=None):
     rc = _lib.hpl_generate(int(seed) % 2**64, int(stream_id) % 2**64, pM, r, c, ld, _stream(stream))
     _check("hpl_generate", rc)
     return M
+
+
+def hpl_generate_normal(seed, stream_id, M, stream=None):
+    """Fill the column-major tensor M with Box-Muller normal values of (seed, stream_id); returns M."""
+    pM, r, c, ld = _matrix("M", M)
+    rc = _lib.hpl_generate_normal(int(seed) % 2**64, int(stream_id) % 2**64, pM, r, c, ld, _stream(stream))
+    _check("hpl_generate_normal", rc)
+    return M
+
+
+def hpl_add_diagonal(M, alpha, stream=None):
+    """M(i,i) += alpha in place (square column-major M); returns M."""
+    pM, r, c, ld = _matrix("M", M)
+    if r != c:
+        raise ValueError("M must be square")
+    _check("hpl_add_diagonal", _lib.hpl_add_diagonal(pM, r, ld, float(alpha), _stream(stream)))
+    return M
+
+
+def hpl_solve_grad_a(GB, X, dA=None, stream=None):
+    """dA = -GB X^T (n x n, column-major), written once; returns dA."""
+    pG, n, k, ldg = _matrix("GB", GB)
+    pX, n2, k2, ldx = _matrix("X", X)
+    if n2 != n or k2 != k:
+        raise ValueError("GB and X must have the same shape")
+    if dA is None:
+        dA = colmajor(n, n, device=GB.device)
+    pD, n3, m3, ldd = _matrix("dA", dA)
+    if n3 != n or m3 != n:
+        raise ValueError("dA must be n x n")
+    _check("hpl_solve_grad_a", _lib.hpl_solve_grad_a(pG, ldg, pX, ldx, n, k, pD, ldd, _stream(stream)))
+    return dA
+
+
+def _colmajor_copy(T):
+    """Column-major float64 copy of a 1-D or 2-D CUDA tensor (a device copy)."""
+    if T.dim() == 1:
+        return T.detach().to(dtype=_torch().float64).clone()
+    out = colmajor(T.shape[0], T.shape[1], device=T.device)
+    out.copy_(T.detach())
+    return out
+
+
+def _autograd():
+    torch = _torch()
+
+    class HplSolve(torch.autograd.Function):
+        """X = A^{-1} B through hpl_factor + hpl_solve; backward reuses the factors:
+        grad_B = A^{-T} G (hpl_solve, trans = 1) and grad_A = -grad_B X^T
+        (hpl_solve_grad_a)."""
+
+        @staticmethod
+        def forward(ctx, A, B, nb):
+            LU = _colmajor_copy(A)
+            ipiv, info = hpl_factor(LU, nb)
+            if info != 0:
+                raise ZeroDivisionError(f"hpl_factor: U({info - 1},{info - 1}) is exactly zero")
+            X = _colmajor_copy(B)
+            hpl_solve(LU, ipiv, X)
+            ctx.save_for_backward(LU, ipiv, X)
+            ctx.vec = B.dim() == 1
+            return X
+
+        @staticmethod
+        def backward(ctx, G):
+            LU, ipiv, X = ctx.saved_tensors
+            GB = _colmajor_copy(G)
+            hpl_solve(LU, ipiv, GB, trans=1)
+            n = LU.shape[0]
+            GB2 = GB.reshape(n, 1) if ctx.vec else GB
+            X2 = X.reshape(n, 1) if ctx.vec else X
+            GA = hpl_solve_grad_a(GB2, X2) if ctx.needs_input_grad[0] else None
+            return GA, (GB if ctx.needs_input_grad[1] else None), None
+
+    return HplSolve
+
+
+_HPL_SOLVE = None
+
+
+def hpl_solve_diff(A, B, nb=256):
+    """Differentiable X = A^{-1} B (float64 CUDA tensors; B n or n x nrhs)."""
+    global _HPL_SOLVE
+    if _HPL_SOLVE is None:
+        _HPL_SOLVE = _autograd()
+    return _HPL_SOLVE.apply(A, B, int(nb))
 
 
 def hpl_set_option(key, value):
