@@ -78,6 +78,87 @@ def measured_traffic(n, nb):
     return round((t["fetch_gb"] + t["write_gb"]) * 1e9)
 
 
+def bench_diffsolve(args, torch, h):
+    """Differentiable solve: X = A^{-1} B (forward: factor + solve) and the
+    backward (transposed solve + grad_A = -grad_B X^T), A = U[-0.5,0.5) + 8I,
+    B uniform, loss = sum(W * X) with W standard normal."""
+    n = 8192 if args.n == 163840 else args.n
+    nb = 256 if args.nb == 512 else args.nb
+    nrhs = 16
+    A = h.colmajor(n, n)
+    h.hpl_generate(args.seed, 0, A)
+    h.hpl_add_diagonal(A, 8.0)
+    B = h.colmajor(n, nrhs)
+    h.hpl_generate(args.seed, 1, B)
+    W = h.colmajor(n, nrhs)
+    h.hpl_generate_normal(args.seed, 2, W)
+    A.requires_grad_(True)
+    B.requires_grad_(True)
+    st = torch.cuda.current_stream()
+    fw, bw, ga = [], [], []
+    for step in range(args.warmup + args.steps):
+        A.grad = None
+        B.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X = h.hpl_solve_diff(A, B, nb=nb)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        X.backward(W)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        # the fused grad_A kernel alone, timed with events on its stream
+        GB = B.grad.detach()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        h.hpl_solve_grad_a(GB, X.detach(), A.grad)
+        e1.record(st)
+        torch.cuda.synchronize()
+        if step >= args.warmup:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+            ga.append(e0.elapsed_time(e1) * 1e-3)
+        log(f"step {step}: forward {1e3 * (t1 - t0):.2f} ms, backward {1e3 * (t2 - t1):.2f} ms")
+    k = len(fw)
+    t_fw, t_bw, t_ga = sum(fw) / k, sum(bw) / k, sum(ga) / k
+    lu_flops = 2.0 * n ** 3 / 3.0
+    solve_flops = 2.0 * n * n * nrhs
+    ga_bytes = 8.0 * n * n + 16.0 * n * nrhs   # grad_A written once, grad_B and X read
+    out = {
+        "metric": "differentiable FP64 solve: forward + backward time",
+        "value": round(1e3 * (t_fw + t_bw), 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * (t_fw + t_bw), 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"differentiable solve, N={n}, NB={nb}, {nrhs} right-hand sides, A ~ U[-0.5,0.5) + 8I, "
+                        f"B ~ U[-0.5,0.5), loss = sum(W*X), W ~ N(0,1), seed {args.seed}",
+            "n": n, "nb": nb, "nrhs": nrhs,
+            "forward_ms": round(1e3 * t_fw, 3), "backward_ms": round(1e3 * t_bw, 3),
+            "forward_tflops": round((lu_flops + solve_flops) / t_fw / 1e12, 3),
+        },
+        "roofline": {
+            "kernel": "grad_a_kernel (grad_A = -grad_B X^T)",
+            "bound": "hbm",
+            "achieved": round(ga_bytes / t_ga / 1e9, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(ga_bytes / t_ga / 1e9 / PEAK_HBM_GBS, 4),
+            "avg_launch_ms": round(1e3 * t_ga, 4),
+            "algorithmic_bytes_per_launch": ga_bytes,
+            "traffic": None,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +171,9 @@ def main():
     ap.add_argument("--pad", type=int, default=0, help="lda = n + pad")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="N of the oracle sample (0: skip)")
     ap.add_argument("--progress", type=int, default=32, help="progress line every k panels (stderr)")
+    ap.add_argument("--workload", choices=["hpl", "diffsolve"], default="hpl",
+                    help="hpl: the HPL factor + solve (default); diffsolve: the differentiable FP64 "
+                         "solve, N=8192 NB=256 16 right-hand sides, forward + backward")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (reference for the HBM byte "
                          "counters FETCH_SIZE / WRITE_SIZE) and exit")
@@ -114,6 +198,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 copies of {nbytes} bytes ({nbytes >> 10} KiB read + written each)")
         return
+    if args.workload == "diffsolve":
+        return bench_diffsolve(args, torch, h)
     n, nb = args.n, args.nb
     log(f"device {torch.cuda.get_device_name(dev)}; N={n} NB={nb} look-ahead={args.lookahead}")
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, args.lookahead)

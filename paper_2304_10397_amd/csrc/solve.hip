@@ -9,9 +9,10 @@
 //     lanes by shuffle -- no barrier, no second launch (workgroup 0 also
 //     stores the finished rows);
 //   * then the workgroup subtracts the block's contribution from its share of
-//     the rows not yet solved (a skinny GEMV: for L and U one row per lane,
-//     columns read coalesced; for the transposed operators one contiguous
-//     column segment per lane).
+//     the rows not yet solved, one row per thread (a skinny GEMV: for L and U
+//     the row's values are read coalesced across lanes; for the transposed
+//     operators each lane reads a contiguous column segment).  All 64 values
+//     of a row are loaded at once and reused for every right-hand side.
 // mode 0: L unit lower, forward.  mode 1: U upper, backward.
 // mode 2: U^T (lower, diagonal u_ii), forward.  mode 3: L^T unit upper, backward.
 //
@@ -26,8 +27,6 @@ namespace {
 
 constexpr int kBs = 64;          // diagonal block rows (one per lane)
 constexpr int kSvThreads = 256;  // 4 waves
-constexpr int kSvRhs = 8;        // right-hand sides per pass of the GEMV
-constexpr int kRowsPerThread = 4;
 
 template <int mode>
 __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *__restrict__ T, int64_t ldt,
@@ -68,35 +67,28 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *_
     __syncthreads();
     if (row_end <= row_begin) return;
 
-    // ---- 2. update of this workgroup's rows
-    const int64_t rows_per_wg = (int64_t)kSvThreads * kRowsPerThread;
-    const int64_t wb = row_begin + (int64_t)blockIdx.x * rows_per_wg;
-    for (int64_t c0 = 0; c0 < nrhs; c0 += kSvRhs) {
-        const int nr = (int)((nrhs - c0) < kSvRhs ? (nrhs - c0) : kSvRhs);
-#pragma unroll 1
-        for (int q = 0; q < kRowsPerThread; ++q) {
-            const int64_t i = wb + t + (int64_t)q * kSvThreads;
-            if (i >= row_end) break;
-            double acc[kSvRhs];
+    // ---- 2. update of this workgroup's rows: one row per thread; the row's kBs
+    //      operator values are loaded in one burst (independent loads, one
+    //      round trip) and reused for every right-hand side, whose solved
+    //      block values are LDS broadcasts
+    const int64_t i = row_begin + (int64_t)blockIdx.x * kSvThreads + t;
+    if (i >= row_end) return;
+    double a[kBs];
+    if (mode < 2) {
+        const double *base = T + off(i, r0, ldt);  // T_op(i, r0 + k) = T(i, r0 + k)
 #pragma unroll
-            for (int c = 0; c < kSvRhs; ++c) acc[c] = 0.0;
-            // the block's kBs operator values of this row, fetched in batches of 16
-            // independent loads (one round trip per batch, not one per element)
-            const double *base = (mode < 2) ? T + off(i, r0, ldt) : T + off(r0, i, ldt);
-            const size_t stride = (mode < 2) ? (size_t)ldt : 1;
-#pragma unroll 1
-            for (int k0 = 0; k0 < kBs; k0 += 16) {
-                double a[16];
+        for (int k = 0; k < kBs; ++k) a[k] = (k < bs) ? base[(size_t)k * (size_t)ldt] : 0.0;
+    } else {
+        const double *base = T + off(r0, i, ldt);  // T_op(i, r0 + k) = T(r0 + k, i)
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk) a[kk] = (k0 + kk < bs) ? base[(size_t)(k0 + kk) * stride] : 0.0;
+        for (int k = 0; k < kBs; ++k) a[k] = (k < bs) ? base[k] : 0.0;
+    }
+    for (int64_t c = 0; c < nrhs; ++c) {
+        const double *y = Y + c * kBs;
+        double acc = 0.0;
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk)
-#pragma unroll
-                    for (int c = 0; c < kSvRhs; ++c)
-                        if (c < nr) acc[c] += a[kk] * Y[(c0 + c) * kBs + k0 + kk];
-            }
-            for (int c = 0; c < nr; ++c) B[off(i, c0 + c, ldb)] -= acc[c];
-        }
+        for (int k = 0; k < kBs; ++k) acc += a[k] * y[k];
+        B[off(i, c, ldb)] -= acc;
     }
 }
 
@@ -139,7 +131,7 @@ int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int
     if (bs <= 0 || nrhs <= 0) return HPL_OK;
     if (bs > kBs) return HPL_ERR_INTERNAL;
     const int64_t rows = row_end > row_begin ? row_end - row_begin : 0;
-    const int64_t per = (int64_t)kSvThreads * kRowsPerThread;
+    const int64_t per = (int64_t)kSvThreads;  // one row per thread
     int64_t g = (rows + per - 1) / per;
     if (g < 1) g = 1;
     if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
