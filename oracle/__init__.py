@@ -48,6 +48,14 @@ def lib():
         L.oracle_gen_normal.argtypes = [u64, u64, P, i64, i64, i64]
         L.oracle_solve_grad.restype = i64
         L.oracle_solve_grad.argtypes = [P, i64, i64, P, i64, i64, P, i64, P, i64, P, i64, P, i64]
+        L.oracle_mxp_gen.restype = None
+        L.oracle_mxp_gen.argtypes = [u64, P, i64, i64]
+        L.oracle_round_fp16.restype = ctypes.c_float
+        L.oracle_round_fp16.argtypes = [ctypes.c_float]
+        L.oracle_round_bf16.restype = ctypes.c_float
+        L.oracle_round_bf16.argtypes = [ctypes.c_float]
+        L.oracle_lu_mxp.restype = i64
+        L.oracle_lu_mxp.argtypes = [P, i64, i64, i64, ctypes.c_int, P, i64]
         L.oracle_det.restype = None
         L.oracle_det.argtypes = [P, P, i64, i64, P, P, P]
         _lib = L
@@ -178,3 +186,32 @@ def solve_grad(A, B, W):
     info = lib().oracle_solve_grad(_ptr(A), n, _ld(A), _ptr(B), _ld(B), nrhs, _ptr(W), _ld(W),
                                    _ptr(X), max(n, 1), _ptr(GB), max(n, 1), _ptr(GA), max(n, 1))
     return X, GB, GA, int(info)
+
+
+def mxp_gen(seed: int, n: int, ld: int = None) -> np.ndarray:
+    """The diagonally dominant mixed-precision input: U[-0.5, 0.5) (stream 0), then
+    a_ii = sum_j |a_ij| of the generated row."""
+    ld = n if ld is None else ld
+    buf = np.zeros((max(ld, 1), n), dtype=np.float64, order="F")
+    lib().oracle_mxp_gen(seed, _ptr(buf), n, max(ld, 1))
+    return buf[:n, :]
+
+
+def round_fp16(x: float) -> float:
+    return float(lib().oracle_round_fp16(float(x)))
+
+
+def round_bf16(x: float) -> float:
+    return float(lib().oracle_round_bf16(float(x)))
+
+
+FMT_FP16, FMT_BF16, FMT_NONE = 0, 1, 2
+
+
+def lu_mxp(A: np.ndarray, nb: int, fmt: int):
+    """(LU float32 Fortran n x n, info): no-pivot LU in the mixed precision of the method."""
+    _check(A)
+    n = A.shape[0]
+    LU = np.zeros((max(n, 1), n), dtype=np.float32, order="F")
+    info = lib().oracle_lu_mxp(_ptr(A), n, _ld(A), int(nb), int(fmt), _ptr(LU), max(n, 1))
+    return LU[:n, :], int(info)

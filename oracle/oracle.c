@@ -334,3 +334,144 @@ int64_t oracle_solve_grad(const double *A, int64_t n, int64_t lda, const double 
     free(ipiv);
     return info;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Mixed precision (HPL-MxP, the paper's Sec. I mention of the mixed-        */
+/* precision benchmark).  The input is diagonally dominant so that LU needs  */
+/* no pivoting: a_ij uniform on [-0.5, 0.5) as above, then                   */
+/* a_ii := sum_j |a_ij| over the row as generated (diagonal included).       */
+/* ------------------------------------------------------------------------ */
+void oracle_mxp_gen(uint64_t seed, double *A, int64_t n, int64_t lda)
+{
+    oracle_gen(seed, 0, A, n, n, lda);
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) s = s + fabs(A[IDX(i, j, lda)]);
+        A[IDX(i, i, lda)] = s;
+    }
+}
+
+/* IEEE binary16 (1 sign, 5 exponent, 10 fraction bits) rounding of a float, */
+/* round to nearest, ties to even, with gradual underflow and overflow to    */
+/* infinity: written from the format's definition, value returned as float.  */
+float oracle_round_fp16(float x)
+{
+    if (!(x == x) || x == 0.0f) return x;
+    const double ax = fabs((double)x);
+    if (ax >= 65520.0) return x > 0 ? INFINITY : -INFINITY;  /* 65504 + half an ulp rounds up */
+    int e;
+    frexp(ax, &e);                        /* ax = m 2^e, m in [0.5, 1) */
+    int q = e - 11;                       /* ulp exponent for 11 significant bits */
+    if (q < -24) q = -24;                 /* subnormal spacing 2^-24 */
+    const double scaled = ldexp(ax, -q);  /* exact: a power-of-two scaling */
+    double r = floor(scaled);
+    const double frac = scaled - r;
+    if (frac > 0.5 || (frac == 0.5 && fmod(r, 2.0) != 0.0)) r += 1.0;
+    const double v = ldexp(r, q);
+    return (float)(x < 0 ? -v : v);
+}
+
+/* bfloat16 (the top 16 bits of binary32): round to nearest, ties to even on */
+/* the 16 discarded bits.                                                    */
+float oracle_round_bf16(float x)
+{
+    if (!(x == x)) return x;
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    const uint32_t lower = u & 0xFFFFu;
+    uint32_t upper = u >> 16;
+    if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u))) upper += 1u;
+    u = upper << 16;
+    float r;
+    memcpy(&r, &u, 4);
+    return r;
+}
+
+static float round_fmt(float x, int fmt)
+{
+    return fmt == 0 ? oracle_round_fp16(x) : (fmt == 1 ? oracle_round_bf16(x) : x);
+}
+
+/* Exponent s of the per-panel scaling: L21 is multiplied by 2^s and U12 by  */
+/* 2^-s (exact), s = round((log2 max|U12| - log2 max|L21|) / 2), so both      */
+/* operands sit around the geometric mean of their magnitudes.                */
+static int mxp_scale_exponent(float lmax, float umax)
+{
+    if (!(lmax > 0.0f) || !(umax > 0.0f)) return 0;
+    int el, eu;
+    frexpf(lmax, &el);
+    frexpf(umax, &eu);
+    const int d = eu - el;
+    return d >= 0 ? (d + 1) / 2 : -((-d + 1) / 2);
+}
+
+/* LU without pivoting in the method's mixed precision, blocked right-looking */
+/* with panel width nb, the steps in order for each panel [c0, c1):           */
+/*  1. FACT: column by column in FP32 (divide by the diagonal, rank-1 update  */
+/*     of the panel's remaining columns);                                     */
+/*  2. U12 = L11^{-1} A12 by forward substitution in FP32;                    */
+/*  3. UPDATE: A22 += (-(2^s L21) rounded to the format) x ((2^-s U12)        */
+/*     rounded to the format), products of the rounded operands summed in     */
+/*     FP32 over k in order (fmt 0 = FP16, 1 = BF16, 2 = no rounding).        */
+/* A (double, n x n at lda) is the input; LU (float, n x n at ldlu) receives  */
+/* the unit-lower L below the diagonal and U on and above it.  Returns info   */
+/* (k+1 for the first zero diagonal, whose column is then left unscaled).     */
+int64_t oracle_lu_mxp(const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU, int64_t ldlu)
+{
+    int64_t info = 0;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) LU[IDX(i, j, ldlu)] = (float)A[IDX(i, j, lda)];
+    float *lo = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1) * (size_t)(nb > 0 ? nb : 1));
+    float *up = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1) * (size_t)(nb > 0 ? nb : 1));
+    for (int64_t c0 = 0; c0 < n; c0 += nb) {
+        const int64_t c1 = (c0 + nb < n) ? c0 + nb : n, w = c1 - c0;
+        /* 1. panel */
+        for (int64_t k = c0; k < c1; ++k) {
+            const float piv = LU[IDX(k, k, ldlu)];
+            if (piv == 0.0f) {
+                if (!info) info = k + 1;
+                continue;
+            }
+            for (int64_t i = k + 1; i < n; ++i) LU[IDX(i, k, ldlu)] = LU[IDX(i, k, ldlu)] / piv;
+            for (int64_t j = k + 1; j < c1; ++j) {
+                const float ukj = LU[IDX(k, j, ldlu)];
+                for (int64_t i = k + 1; i < n; ++i) LU[IDX(i, j, ldlu)] = LU[IDX(i, j, ldlu)] - LU[IDX(i, k, ldlu)] * ukj;
+            }
+        }
+        if (c1 >= n) break;
+        /* 2. U12 */
+        for (int64_t j = c1; j < n; ++j)
+            for (int64_t i = c0; i < c1; ++i) {
+                float s = LU[IDX(i, j, ldlu)];
+                for (int64_t k = c0; k < i; ++k) s = s - LU[IDX(i, k, ldlu)] * LU[IDX(k, j, ldlu)];
+                LU[IDX(i, j, ldlu)] = s;
+            }
+        /* 3. scaled, rounded operands and the FP32 update */
+        float lmax = 0.0f, umax = 0.0f;
+        for (int64_t k = 0; k < w; ++k)
+            for (int64_t i = c1; i < n; ++i) {
+                const float v = fabsf(LU[IDX(i, c0 + k, ldlu)]);
+                if (v > lmax) lmax = v;
+            }
+        for (int64_t j = c1; j < n; ++j)
+            for (int64_t k = 0; k < w; ++k) {
+                const float v = fabsf(LU[IDX(c0 + k, j, ldlu)]);
+                if (v > umax) umax = v;
+            }
+        const int s = mxp_scale_exponent(lmax, umax);
+        const int64_t m = n - c1;
+        for (int64_t k = 0; k < w; ++k)
+            for (int64_t i = 0; i < m; ++i) lo[IDX(i, k, m)] = round_fmt(-ldexpf(LU[IDX(c1 + i, c0 + k, ldlu)], s), fmt);
+        for (int64_t j = 0; j < m; ++j)
+            for (int64_t k = 0; k < w; ++k) up[IDX(k, j, w)] = round_fmt(ldexpf(LU[IDX(c0 + k, c1 + j, ldlu)], -s), fmt);
+        for (int64_t j = 0; j < m; ++j)
+            for (int64_t i = 0; i < m; ++i) {
+                float acc = LU[IDX(c1 + i, c1 + j, ldlu)];
+                for (int64_t k = 0; k < w; ++k) acc = acc + lo[IDX(i, k, m)] * up[IDX(k, j, w)];
+                LU[IDX(c1 + i, c1 + j, ldlu)] = acc;
+            }
+    }
+    free(lo);
+    free(up);
+    return info;
+}
