@@ -168,6 +168,57 @@ int hpl_generate_normal(uint64_t seed, uint64_t stream_id, double *M, int64_t ro
  */
 int hpl_add_diagonal(double *M, int64_t n, int64_t ld, double alpha, void *hip_stream);
 
+/*
+ * Mixed precision (HPL-MxP, which the paper mentions alongside HPL, Sec. I):
+ * LU in FP16 or BF16 on the matrix cores, then FP64 iterative refinement to
+ * the FP64 scaled-residual test.
+ *
+ * hpl_mxp_generate -- the diagonally dominant input: the hpl_generate matrix
+ * of (seed, stream 0), then a_ii = sum_j |a_ij| of the generated row (j in
+ * order), so that LU needs no pivoting.
+ *   1 seed; 2 A device n x n at lda (written); 3 n >= 0; 4 lda >= max(1, n); 5 hip_stream
+ */
+int hpl_mxp_generate(uint64_t seed, double *A, int64_t n, int64_t lda, void *hip_stream);
+
+/*
+ * hpl_mxp_factor -- LU without pivoting, FP32 storage:
+ *   for each NB-column panel: FACT in FP32, U12 = L11^{-1} A12 in FP32, then
+ *   A22 += (-L21) U12 with L21 scaled by 2^s and U12 by 2^-s (s on the device
+ *   from their maxima: exact, and keeps small multipliers out of FP16's
+ *   subnormal range), both rounded to the format, products accumulated in FP32
+ *   on v_mfma_f32_16x16x32_{f16,bf16}.
+ *   1 A    device FP64 n x n at lda (input, not modified)
+ *   2 n    0 <= n < 2^31;  3 lda >= max(1, n)
+ *   4 nb   panel width, a multiple of 64 in [64, 1024]
+ *   5 fmt  0 = FP16, 1 = BF16
+ *   6 LU   device FP32 n x n at ldlu (written: unit-lower L below the
+ *          diagonal, U on and above it)
+ *   7 ldlu >= max(1, n)
+ *   8 info host int64*: 0, or k+1 for the first exactly-zero diagonal of U
+ *   9 hip_stream
+ * Workspace: 4 n nb bytes (the FP16/BF16 copies of L21 and U12), kept per device.
+ */
+int hpl_mxp_factor(const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU,
+                   int64_t ldlu, int64_t *info, void *hip_stream);
+
+/*
+ * hpl_mxp_solve -- x from the FP32 factors, refined in FP64:
+ *   x = U^{-1} L^{-1} b;  repeat  r = b - A x (FP64, explicit A);
+ *   scaled = ||r||inf / (eps (||A||inf ||x||inf + ||b||inf) n), eps = 2^-53;
+ *   stop if scaled < 16 or max_iter corrections were applied;
+ *   d = U^{-1} L^{-1} r;  x += d.
+ *   1 A device FP64 n x n at lda (the matrix that was factored); 2 lda
+ *   3 LU device FP32 factors from hpl_mxp_factor; 4 ldlu
+ *   5 n >= 0;  6 b device double[n];  7 x device double[n] (written)
+ *   8 max_iter >= 0 corrections at most
+ *   9 out host double[5] = {corrections applied, final scaled residual,
+ *     ||r||inf, ||A||inf, ||x||inf}
+ *  10 hip_stream
+ * The run passes when out[1] < 16.
+ */
+int hpl_mxp_solve(const double *A, int64_t lda, const float *LU, int64_t ldlu, int64_t n,
+                  const double *b, double *x, int64_t max_iter, double *out, void *hip_stream);
+
 /* Options (process-wide, read at the start of each call). */
 enum hpl_option {
     HPL_OPT_LOOKAHEAD = 1,   /* 0: none.  1 (default): panel j+1 is factored while the

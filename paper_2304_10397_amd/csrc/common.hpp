@@ -182,4 +182,25 @@ int launch_add_diagonal(double *M, int64_t n, int64_t ld, double alpha, hipStrea
 int launch_grad_a(const double *G, int64_t ldg, const double *X, int64_t ldx, int64_t n, int64_t k, double *D,
                   int64_t ldd, hipStream_t st);
 
+// Mixed-precision LU and refinement (mxp.hip); solve_block with FP32 factors (solve.hip).
+int launch_mxp_diag(double *A, int64_t n, int64_t lda, hipStream_t st);
+int launch_cvt_f64_f32(const double *A, int64_t lda, float *B, int64_t ldb, int64_t rows, int64_t cols,
+                       hipStream_t st);
+int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsigned long long *info,
+                        hipStream_t st);
+int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st);
+int launch_sgemm32(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B, int64_t ldb,
+                   float *C, int64_t ldc, hipStream_t st);
+int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols, int w,
+                     unsigned *mx, int *sexp, hipStream_t st);
+int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols,
+                       int w, const int *sexp, void *A16, void *B16, hipStream_t st);
+int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, const void *B16, float *C,
+                        int64_t ldc, hipStream_t st);
+int launch_mxp_residual(const double *A, int64_t lda, const double *x, const double *b, double *r, int64_t n,
+                        bool anorm, unsigned long long *red, hipStream_t st);
+int launch_axpy(double *x, const double *d, int64_t n, hipStream_t st);
+int launch_solve_block_f32(const float *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs, int64_t r0, int64_t bs,
+                           int64_t row_begin, int64_t row_end, int mode, hipStream_t st);
+
 }  // namespace hplx

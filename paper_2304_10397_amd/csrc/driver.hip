@@ -126,6 +126,10 @@ struct Device {
     int32_t *splans = nullptr;           // interchange plans of every chunk of ipiv (solve)
     int64_t splan_cap = 0;
     std::vector<hipEvent_t> ev_pool;      // timing events
+    void *mxp_ws = nullptr;               // mixed precision: FP16/BF16 copies of L21 and U12, scalars
+    size_t mxp_cap = 0;
+    double *mxp_vec = nullptr;            // refinement vectors r, d (2 n doubles)
+    int64_t mxp_vec_cap = 0;
 };
 
 static std::mutex g_dev_mu;
@@ -548,6 +552,138 @@ static int solve_impl(Device *d, const double *LU, const int32_t *ipiv, double *
     return check_pivot_error(d, st);
 }
 
+// ---------------------------------------------------------------------------
+// mixed precision (no pivoting; FP32 working matrix; FP16/BF16 trailing update)
+// ---------------------------------------------------------------------------
+static int ensure_mxp_ws(Device *d, size_t bytes)
+{
+    if (d->mxp_cap >= bytes) return HPL_OK;
+    if (d->mxp_ws) HPLX_TRY(hipFree(d->mxp_ws));
+    d->mxp_ws = nullptr;
+    d->mxp_cap = 0;
+    if (hipMalloc(&d->mxp_ws, bytes) != hipSuccess) HPLX_FAIL(HPL_ERR_NOMEM, "mixed-precision workspace allocation failed");
+    d->mxp_cap = bytes;
+    return HPL_OK;
+}
+
+// B (nbk x ncols) <- L^{-1} B, L unit lower (FP32): 32-row leaves joined by GEMMs.
+static int mxp_trsm(const float *L, int64_t ldl, int64_t nbk, float *B, int64_t ldb, int64_t ncols, hipStream_t st)
+{
+    if (nbk <= 0 || ncols <= 0) return HPL_OK;
+    if (nbk <= 32) return launch_trsm32_leaf(L, ldl, B, ldb, (int)nbk, ncols, st);
+    const int64_t h = ((nbk / 2 + 31) / 32) * 32;
+    HPLX_PROPAGATE(mxp_trsm(L, ldl, h, B, ldb, ncols, st));
+    HPLX_PROPAGATE(launch_sgemm32(nbk - h, ncols, h, L + h, ldl, B, ldb, B + h, ldb, st));
+    return mxp_trsm(L + off(h, h, ldl), ldl, nbk - h, B + h, ldb, ncols, st);
+}
+
+// FACT of columns [c, c+w), rows [c, n), no pivoting, FP32: recursive halves.
+static int mxp_panel(float *A, int64_t lda, int64_t n, int64_t c, int64_t w, unsigned long long *info, hipStream_t st)
+{
+    if (w <= 32) return launch_panel32_leaf(A, lda, c, n, (int)w, info, st);
+    int64_t w1 = ((w / 2 + 31) / 32) * 32;
+    if (w1 >= w) w1 = w - 1;
+    const int64_t w2 = w - w1;
+    HPLX_PROPAGATE(mxp_panel(A, lda, n, c, w1, info, st));
+    HPLX_PROPAGATE(mxp_trsm(A + off(c, c, lda), lda, w1, A + off(c, c + w1, lda), lda, w2, st));
+    HPLX_PROPAGATE(launch_sgemm32(n - c - w1, w2, w1, A + off(c + w1, c, lda), lda, A + off(c, c + w1, lda), lda,
+                                  A + off(c + w1, c + w1, lda), lda, st));
+    return mxp_panel(A, lda, n, c + w1, w2, info, st);
+}
+
+static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU,
+                           int64_t ldlu, int64_t *info, hipStream_t st)
+{
+    const size_t half_bytes = sizeof(uint16_t) * (size_t)n * (size_t)nb;
+    const size_t a16_off = 0, b16_off = (half_bytes + 255) / 256 * 256;
+    const size_t sc_off = b16_off + (half_bytes + 255) / 256 * 256;
+    HPLX_PROPAGATE(ensure_mxp_ws(d, sc_off + 256));
+    char *ws = (char *)d->mxp_ws;
+    void *A16 = ws + a16_off, *B16 = ws + b16_off;
+    unsigned *mx = (unsigned *)(ws + sc_off);
+    int *sexp = (int *)(ws + sc_off + 16);
+    unsigned long long *dinfo = (unsigned long long *)(ws + sc_off + 32);
+    HPLX_PROPAGATE(launch_fill_u64(dinfo, 1, ULLONG_MAX, st));
+    HPLX_PROPAGATE(launch_cvt_f64_f32(A, lda, LU, ldlu, n, n, st));
+    for (int64_t c0 = 0; c0 < n; c0 += nb) {
+        const int64_t w = (n - c0) < nb ? (n - c0) : nb;
+        const int64_t c1 = c0 + w;
+        HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c0, w, dinfo, st));
+        if (c1 >= n) break;
+        const int64_t m = n - c1;
+        HPLX_PROPAGATE(mxp_trsm(LU + off(c0, c0, ldlu), ldlu, w, LU + off(c0, c1, ldlu), ldlu, m, st));
+        HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c0, ldlu), ldlu, m, LU + off(c0, c1, ldlu), ldlu, m, (int)w, mx,
+                                        sexp, st));
+        HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c0, ldlu), ldlu, m, LU + off(c0, c1, ldlu), ldlu, m,
+                                          (int)w, sexp, A16, B16, st));
+        HPLX_PROPAGATE(launch_hgemm_update(fmt, m, m, w, A16, B16, LU + off(c1, c1, ldlu), ldlu, st));
+    }
+    unsigned long long hinfo = 0;
+    HPLX_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof hinfo, hipMemcpyDeviceToHost, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    *info = (hinfo == ULLONG_MAX) ? 0 : (int64_t)hinfo;
+    return HPL_OK;
+}
+
+static int mxp_solve_impl(Device *d, const double *A, int64_t lda, const float *LU, int64_t ldlu, int64_t n,
+                          const double *b, double *x, int64_t max_iter, double *out, hipStream_t st)
+{
+    if (d->mxp_vec_cap < 2 * n) {
+        if (d->mxp_vec) HPLX_TRY(hipFree(d->mxp_vec));
+        d->mxp_vec = nullptr;
+        d->mxp_vec_cap = 0;
+        if (hipMalloc((void **)&d->mxp_vec, sizeof(double) * 2 * (size_t)n) != hipSuccess)
+            HPLX_FAIL(HPL_ERR_NOMEM, "refinement vectors allocation failed");
+        d->mxp_vec_cap = 2 * n;
+    }
+    HPLX_PROPAGATE(ensure_red(d, 4));
+    double *r = d->mxp_vec, *dv = d->mxp_vec + n;
+    const int64_t bs = 64;
+    const int64_t nblk = (n + bs - 1) / bs;
+    auto lu_solve = [&](double *v) -> int {  // v <- U^{-1} L^{-1} v with the FP32 factors
+        for (int64_t q = 0; q < nblk; ++q) {
+            const int64_t r0 = q * bs, bb = (n - r0) < bs ? (n - r0) : bs;
+            HPLX_PROPAGATE(launch_solve_block_f32(LU, ldlu, v, n, 1, r0, bb, r0 + bb, n, 0, st));
+        }
+        for (int64_t q = nblk - 1; q >= 0; --q) {
+            const int64_t r0 = q * bs, bb = (n - r0) < bs ? (n - r0) : bs;
+            HPLX_PROPAGATE(launch_solve_block_f32(LU, ldlu, v, n, 1, r0, bb, 0, r0, 1, st));
+        }
+        return HPL_OK;
+    };
+    HPLX_TRY(hipMemcpyAsync(x, b, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st));
+    HPLX_PROPAGATE(lu_solve(x));
+    const double eps = 0x1.0p-53;
+    double anorm = 0.0, scaled = 0.0, rn = 0.0, xn = 0.0, bn = 0.0;
+    int64_t it = 0;
+    for (;;) {
+        HPLX_PROPAGATE(launch_fill_u64(d->red, 4, 0ull, st));
+        HPLX_PROPAGATE(launch_mxp_residual(A, lda, x, b, r, n, it == 0, d->red, st));
+        unsigned long long h[4];
+        HPLX_TRY(hipMemcpyAsync(h, d->red, sizeof h, hipMemcpyDeviceToHost, st));
+        HPLX_TRY(hipStreamSynchronize(st));
+        double v[4];
+        memcpy(v, h, sizeof v);
+        rn = v[0];
+        xn = v[1];
+        bn = v[2];
+        if (it == 0) anorm = v[3];
+        const double den = eps * (anorm * xn + bn) * (double)n;
+        scaled = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+        if (!(scaled >= 16.0) || it >= max_iter) break;  // NaN also stops
+        HPLX_TRY(hipMemcpyAsync(dv, r, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st));
+        HPLX_PROPAGATE(lu_solve(dv));
+        HPLX_PROPAGATE(launch_axpy(x, dv, n, st));
+        ++it;
+    }
+    out[0] = (double)it;
+    out[1] = scaled;
+    out[2] = rn;
+    out[3] = anorm;
+    out[4] = xn;
+    return HPL_OK;
+}
+
 static int residual_impl(const double *A, int64_t lda, bool gen, uint64_t seed, int64_t n, const double *X,
                          int64_t ldx, const double *B, int64_t ldb, int64_t nrhs, double *out, hipStream_t st)
 {
@@ -720,6 +856,58 @@ int hpl_solve_grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ld
     return HPL_OK;
 }
 
+int hpl_mxp_generate(uint64_t seed, double *A, int64_t n, int64_t lda, void *hip_stream)
+{
+    if (n > 0 && A == nullptr) return -2;
+    if (n < 0) return -3;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (n == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HPLX_PROPAGATE(launch_generate(stream_state(seed, 0), A, n, n, lda, st));
+    HPLX_PROPAGATE(launch_mxp_diag(A, n, lda, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    return HPL_OK;
+}
+
+int hpl_mxp_factor(const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU, int64_t ldlu,
+                   int64_t *info, void *hip_stream)
+{
+    if (n > 0 && A == nullptr) return -1;
+    if (n < 0 || n > 0x7fffffffll) return -2;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (nb < 64 || nb > 1024 || nb % 64 != 0) return -4;
+    if (fmt != 0 && fmt != 1) return -5;
+    if (n > 0 && LU == nullptr) return -6;
+    if (ldlu < (n > 1 ? n : 1)) return -7;
+    if (info == nullptr) return -8;
+    *info = 0;
+    if (n == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    return mxp_factor_impl(d, A, n, lda, nb, fmt, LU, ldlu, info, (hipStream_t)hip_stream);
+}
+
+int hpl_mxp_solve(const double *A, int64_t lda, const float *LU, int64_t ldlu, int64_t n, const double *b, double *x,
+                  int64_t max_iter, double *out, void *hip_stream)
+{
+    if (n > 0 && A == nullptr) return -1;
+    if (lda < (n > 1 ? n : 1)) return -2;
+    if (n > 0 && LU == nullptr) return -3;
+    if (ldlu < (n > 1 ? n : 1)) return -4;
+    if (n < 0) return -5;
+    if (n > 0 && b == nullptr) return -6;
+    if (n > 0 && x == nullptr) return -7;
+    if (max_iter < 0) return -8;
+    if (out == nullptr) return -9;
+    for (int i = 0; i < 5; ++i) out[i] = 0.0;
+    if (n == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    return mxp_solve_impl(d, A, lda, LU, ldlu, n, b, x, max_iter, out, (hipStream_t)hip_stream);
+}
+
 int hpl_set_option(int key, int64_t value)
 {
     switch (key) {
@@ -852,6 +1040,8 @@ int hpl_release(void)
         (void)hipStreamDestroy(d.sp);
         if (d.red) (void)hipFree(d.red);
         if (d.splans) (void)hipFree(d.splans);
+        if (d.mxp_ws) (void)hipFree(d.mxp_ws);
+        if (d.mxp_vec) (void)hipFree(d.mxp_vec);
         if (d.hbuf) (void)hipHostFree(d.hbuf);
         (void)hipFree(d.ws);
         d = Device();

@@ -1,0 +1,545 @@
+// mxp.hip -- mixed-precision LU (HPL-MxP, mentioned in the paper's Sec. I)
+// with FP64 iterative refinement.
+//
+// The input is diagonally dominant (a_ii = sum_j |a_ij| of the generated row),
+// so the factorization needs no pivoting.  The working matrix is FP32 and the
+// factorization is right-looking with NB-column panels:
+//   1. FACT in FP32: recursive halves; leaves of <= 32 columns factor their
+//      diagonal block in LDS and solve the rows below against it;
+//   2. U12 = L11^{-1} A12 in FP32 (recursive: 64-row leaf solves in LDS,
+//      FP32 GEMMs between them);
+//   3. UPDATE on the matrix cores: L21 and U12 are scaled by 2^s and 2^-s (a
+//      power of two chosen on the device from their maxima, so the scaling is
+//      exact and keeps FP16 multipliers out of the subnormal range), rounded
+//      to FP16 or BF16, and A22 += (-L21) U12 runs on
+//      v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation.
+// The solution is then refined in FP64: r = b - A x with the FP64 matrix, a
+// correction from the FP32 factors, x += d, until the FP64 scaled residual is
+// below 16.
+#include "common.hpp"
+
+namespace hplx {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// input: a_ii = sum_j |a_ij| over the row as generated (j in order, no FMA)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mxp_diag_kernel(double *__restrict__ A, int64_t n, int64_t lda)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t j = 0; j < n; ++j) s = s + fabs(A[off(i, j, lda)]);
+    A[off(i, i, lda)] = s;
+}
+
+__global__ __launch_bounds__(256) void cvt_f64_f32_kernel(const double *__restrict__ A, int64_t lda,
+                                                          float *__restrict__ B, int64_t ldb, int64_t rows,
+                                                          int64_t cols)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= rows) return;
+    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) B[off(i, j, ldb)] = (float)A[off(i, j, lda)];
+}
+
+// ---------------------------------------------------------------------------
+// FP32 panel leaf (w <= 32 columns, rows [c, n)): every workgroup factors the
+// w x w diagonal block in LDS without pivoting (row t owned by thread t; step
+// k divides column k and updates the rows below), then each thread solves one
+// row below the block: x U11 = a, x_j = (a_j - sum_{k<j} x_k u_kj) / u_jj with
+// the sum taken as successive subtractions in k order.  Workgroup 0 writes the
+// factored block back; info records the first zero diagonal.
+// ---------------------------------------------------------------------------
+constexpr int kLw = 32;
+
+__global__ __launch_bounds__(256) void panel32_leaf_kernel(float *__restrict__ A, int64_t lda, int64_t c,
+                                                           int64_t n, int w, unsigned long long *__restrict__ info)
+{
+    __shared__ float D[kLw][kLw + 1];
+    const int t = threadIdx.x;
+    for (int e = t; e < kLw * kLw; e += 256) {
+        const int r = e % kLw, q = e / kLw;
+        D[r][q] = (r < w && q < w) ? A[off(c + r, c + q, lda)] : (r == q ? 1.0f : 0.0f);
+    }
+    __syncthreads();
+    for (int k = 0; k < w; ++k) {
+        const float piv = D[k][k];
+        if (t > k && t < w && piv != 0.0f) {
+            const float l = D[t][k] / piv;
+            D[t][k] = l;
+            for (int j = k + 1; j < w; ++j) D[t][j] = D[t][j] - l * D[k][j];
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0) {
+        for (int e = t; e < w * w; e += 256) {
+            const int r = e % w, q = e / w;
+            A[off(c + r, c + q, lda)] = D[r][q];
+        }
+        if (t == 0)
+            for (int k = 0; k < w; ++k)
+                if (D[k][k] == 0.0f) {
+                    atomicMin(info, (unsigned long long)(c + k + 1));
+                    break;
+                }
+    }
+    const int64_t i = c + w + (int64_t)blockIdx.x * 256 + t;
+    if (i >= n) return;
+    float x[kLw];
+#pragma unroll
+    for (int j = 0; j < kLw; ++j) x[j] = (j < w) ? A[off(i, c + j, lda)] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < kLw; ++j) {
+        const float ujj = D[j][j];
+        if (j < w && ujj != 0.0f) {  // a zero pivot leaves its column as is (info reports it)
+            x[j] = x[j] / ujj;
+#pragma unroll
+            for (int q = j + 1; q < kLw; ++q)
+                if (q < w) x[q] = x[q] - x[j] * D[j][q];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kLw; ++j)
+        if (j < w) A[off(i, c + j, lda)] = x[j];
+}
+
+// ---------------------------------------------------------------------------
+// FP32 triangular-solve leaf: B (nbk x ncols, nbk <= 32) <- L^{-1} B with L
+// unit lower (staged in LDS); one column per thread, forward substitution.
+// ---------------------------------------------------------------------------
+constexpr int kTl = 32;
+
+template <bool FULL>
+__global__ __launch_bounds__(256) void trsm32_leaf_kernel(const float *__restrict__ L, int64_t ldl,
+                                                          float *__restrict__ B, int64_t ldb, int nbk,
+                                                          int64_t ncols)
+{
+    __shared__ float Ls[kTl][kTl + 1];
+    const int t = threadIdx.x;
+    for (int e = t; e < kTl * kTl; e += 256) {
+        const int r = e % kTl, q = e / kTl;
+        Ls[r][q] = (r < nbk && q < nbk) ? L[off(r, q, ldl)] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * 256 + t;
+    if (j >= ncols) return;
+    float x[kTl];
+    float *col = B + (size_t)j * (size_t)ldb;
+    if (FULL) {
+#pragma unroll
+        for (int i = 0; i < kTl; ++i) x[i] = col[i];
+    } else {
+        for (int i = 0; i < kTl; ++i) x[i] = 0.0f;
+        for (int i = 0; i < nbk; ++i) x[i] = col[i];
+    }
+    // row by row: x_i = b_i - sum_{k<i} l_ik x_k (successive subtractions in k
+    // order); the barrier keeps each row's LDS reads next to their use
+#pragma unroll
+    for (int i = 1; i < kTl; ++i) {
+        float acc = x[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc = acc - Ls[i][k] * x[k];
+        x[i] = acc;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (FULL) {
+#pragma unroll
+        for (int i = 0; i < kTl; ++i) col[i] = x[i];
+    } else {
+        for (int i = 0; i < nbk; ++i) col[i] = x[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 GEMM C(m x n) -= A(m x k) B(k x n), column-major, for the panel and
+// triangular-solve recursions: 64 x 64 tiles, 256 threads of 4 x 4 outputs,
+// k staged 16 at a time through LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void sgemm32_kernel(int64_t m, int64_t n, int64_t k, const float *__restrict__ A,
+                                                      int64_t lda, const float *__restrict__ B, int64_t ldb,
+                                                      float *__restrict__ C, int64_t ldc)
+{
+    __shared__ float As[16][64 + 4];
+    __shared__ float Bs[16][64 + 4];
+    const int t = threadIdx.x, tx = t % 16, ty = t / 16;
+    const int64_t m0 = (int64_t)blockIdx.x * 64, n0 = (int64_t)blockIdx.y * 64;
+    float acc[4][4] = {};
+    for (int64_t k0 = 0; k0 < k; k0 += 16) {
+        for (int e = t; e < 16 * 64; e += 256) {
+            const int r = e % 64, q = e / 64;  // A: row r, k q
+            As[q][r] = (m0 + r < m && k0 + q < k) ? A[off(m0 + r, k0 + q, lda)] : 0.0f;
+            const int q2 = e % 16, c2 = e / 16;  // B: k q2, column c2
+            Bs[q2][c2] = (k0 + q2 < k && n0 + c2 < n) ? B[off(k0 + q2, n0 + c2, ldb)] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            float a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = As[q][tx + 16 * u];
+                b[u] = Bs[q][ty + 16 * u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t i = m0 + tx + 16 * u, j = n0 + ty + 16 * v;
+            if (i < m && j < n) C[off(i, j, ldc)] -= acc[u][v];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// scaling: max |x| of a column-major block into *mx (non-negative floats order
+// as their bit patterns), then the exponent s = round((e_U - e_L) / 2) of the
+// maxima's binary exponents, written to *sexp.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void maxabs32_kernel(const float *__restrict__ M, int64_t ld, int64_t rows,
+                                                       int64_t cols, unsigned *__restrict__ mx)
+{
+    __shared__ float sh[4];
+    float v = 0.0f;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < rows)
+        for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) v = fmaxf(v, fabsf(M[off(i, j, ld)]));
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(mx, __float_as_uint(fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]))));
+}
+
+__global__ void scale_exp_kernel(const unsigned *__restrict__ mx, int *__restrict__ sexp)
+{
+    const float lmax = __uint_as_float(mx[0]), umax = __uint_as_float(mx[1]);
+    int s = 0;
+    if (lmax > 0.0f && umax > 0.0f) {
+        int el, eu;
+        frexpf(lmax, &el);
+        frexpf(umax, &eu);
+        const int d = eu - el;
+        s = d >= 0 ? (d + 1) / 2 : -((-d + 1) / 2);
+    }
+    *sexp = s;
+}
+
+template <int FMT> struct Half;
+template <> struct Half<0> { typedef _Float16 T; };
+template <> struct Half<1> { typedef __bf16 T; };
+
+// L21 (m x w at ld) -> A16 row-major m x w (k contiguous): -(2^s l) rounded
+template <int FMT>
+__global__ __launch_bounds__(256) void cvt_l_kernel(const float *__restrict__ L, int64_t ld, int64_t m, int w,
+                                                    const int *__restrict__ sexp, typename Half<FMT>::T *__restrict__ O)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int s = *sexp;
+    for (int k = 0; k < w; ++k) O[(size_t)i * (size_t)w + k] = (typename Half<FMT>::T)(-ldexpf(L[off(i, k, ld)], s));
+}
+
+// U12 (w x n at ld) -> B16 column-major w x n (ld w): 2^-s u rounded
+template <int FMT>
+__global__ __launch_bounds__(256) void cvt_u_kernel(const float *__restrict__ U, int64_t ld, int w, int64_t n,
+                                                    const int *__restrict__ sexp, typename Half<FMT>::T *__restrict__ O)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)w * n) return;
+    const int64_t j = e / w, k = e - j * w;
+    O[e] = (typename Half<FMT>::T)ldexpf(U[off(k, j, ld)], -*sexp);
+}
+
+// ---------------------------------------------------------------------------
+// Trailing update on the matrix cores: C (FP32, column-major) += A16 B16,
+// A16 m x K row-major (k contiguous), B16 K x n column-major (k contiguous).
+// Tile 128 x 128, 4 waves of 64 x 64 (4 x 4 blocks of 16 x 16); K staged 64 at
+// a time through double-buffered LDS (rows padded by 8 halves).  The
+// accumulators start from C.  B's fragment is the MFMA's first operand, so a
+// block comes out transposed: register r of lane l holds
+// C(16R + l%16, 16G + 4(l/16) + r) -- 16 consecutive rows of 4 columns.
+// Requires K % 64 == 0.
+// ---------------------------------------------------------------------------
+constexpr int kHBM = 128, kHBN = 128, kHBK = 64, kHPad = 8;
+
+template <int FMT>
+__global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t n, int64_t K,
+                                                              const typename Half<FMT>::T *__restrict__ A16,
+                                                              const typename Half<FMT>::T *__restrict__ B16,
+                                                              float *__restrict__ C, int64_t ldc, int64_t tiles_m)
+{
+    typedef typename Half<FMT>::T H;
+    typedef H h8 __attribute__((ext_vector_type(8)));
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    asm volatile("" ::: "a0");
+    __shared__ __attribute__((aligned(16))) H As[2][kHBM][kHBK + kHPad];
+    __shared__ __attribute__((aligned(16))) H Bs[2][kHBN][kHBK + kHPad];
+    const int64_t tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    const int64_t m0 = tm * kHBM, n0 = tn * kHBN;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 15, lg = lane >> 4;
+
+    // accumulators from C: acc[R][G][r] = C(m0 + 64wm + 16R + li, n0 + 64wn + 16G + 4lg + r)
+    f4 acc[4][4];
+    const int64_t rbase = m0 + 64 * wm + li, cbase = n0 + 64 * wn + 4 * lg;
+#pragma unroll
+    for (int R = 0; R < 4; ++R)
+#pragma unroll
+        for (int G = 0; G < 4; ++G)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
+                acc[R][G][r] = (i < m && j < n) ? C[off(i, j, ldc)] : 0.0f;
+            }
+
+    // global -> register staging: A tile 128 x 64 halves = 1024 x 16 B, 4 per thread
+    u4 ra[4], rb[4];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + 256 * q;           // 16-byte unit
+            const int row = e >> 3, kk = (e & 7) * 8;
+            const int64_t gi = m0 + row, gj = n0 + row;
+            ra[q] = (gi < m) ? *(const u4 *)(A16 + (size_t)gi * (size_t)K + k0 + kk) : (u4){0, 0, 0, 0};
+            rb[q] = (gj < n) ? *(const u4 *)(B16 + (size_t)gj * (size_t)K + k0 + kk) : (u4){0, 0, 0, 0};
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + 256 * q;
+            const int row = e >> 3, kk = (e & 7) * 8;
+            *(u4 *)&As[buf][row][kk] = ra[q];
+            *(u4 *)&Bs[buf][row][kk] = rb[q];
+        }
+    };
+    const int nst = (int)(K / kHBK);
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nst) load((int64_t)(s + 1) * kHBK);
+#pragma unroll
+        for (int kc = 0; kc < kHBK; kc += 32) {
+            h8 af[4], bf[4];
+#pragma unroll
+            for (int R = 0; R < 4; ++R) af[R] = *(const h8 *)&As[buf][64 * wm + 16 * R + li][kc + 8 * lg];
+#pragma unroll
+            for (int G = 0; G < 4; ++G) bf[G] = *(const h8 *)&Bs[buf][64 * wn + 16 * G + li][kc + 8 * lg];
+#pragma unroll
+            for (int R = 0; R < 4; ++R)
+#pragma unroll
+                for (int G = 0; G < 4; ++G) {
+                    if constexpr (FMT == 0)
+                        acc[R][G] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bf[G], af[R], acc[R][G], 0, 0, 0);
+                    else
+                        acc[R][G] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[G], af[R], acc[R][G], 0, 0, 0);
+                }
+        }
+        if (s + 1 < nst) store(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int R = 0; R < 4; ++R)
+#pragma unroll
+        for (int G = 0; G < 4; ++G)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
+                if (i < m && j < n) C[off(i, j, ldc)] = acc[R][G][r];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// refinement: r = b - A x (FP64, explicit A, j in order), and the maxima
+// |r_i|, |x_i|, |b_i| and (when anorm) sum_j |a_ij| into red[0..3] as bit
+// patterns of non-negative doubles.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mxp_residual_kernel(const double *__restrict__ A, int64_t lda,
+                                                           const double *__restrict__ x,
+                                                           const double *__restrict__ b, double *__restrict__ r,
+                                                           int64_t n, int anorm,
+                                                           unsigned long long *__restrict__ red)
+{
+    __shared__ double sh[4][4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double vr = 0.0, vx = 0.0, vb = 0.0, va = 0.0;
+    if (i < n) {
+        double s = 0.0, sa = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double a = A[off(i, j, lda)];
+            s = __fma_rn(a, x[j], s);
+            if (anorm) sa += fabs(a);
+        }
+        const double ri = b[i] - s;
+        r[i] = ri;
+        vr = fabs(ri);
+        vx = fabs(x[i]);
+        vb = fabs(b[i]);
+        va = sa;
+    }
+    double v[4] = {vr, vx, vb, va};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        for (int o = 32; o > 0; o >>= 1) v[q] = fmax(v[q], __shfl_xor(v[q], o, 64));
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh[threadIdx.x >> 6][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        const double m = fmax(fmax(sh[0][q], sh[1][q]), fmax(sh[2][q], sh[3][q]));
+        atomicMax(red + q, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+__global__ __launch_bounds__(256) void axpy_kernel(double *__restrict__ x, const double *__restrict__ d, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] += d[i];
+}
+
+int64_t blocks_of(int64_t n, int64_t per) { return (n + per - 1) / per; }
+
+}  // namespace
+
+int launch_mxp_diag(double *A, int64_t n, int64_t lda, hipStream_t st)
+{
+    if (n <= 0) return HPL_OK;
+    hipLaunchKernelGGL(mxp_diag_kernel, dim3((unsigned)blocks_of(n, 256)), dim3(256), 0, st, A, n, lda);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_cvt_f64_f32(const double *A, int64_t lda, float *B, int64_t ldb, int64_t rows, int64_t cols,
+                       hipStream_t st)
+{
+    if (rows <= 0 || cols <= 0) return HPL_OK;
+    const unsigned gy = (unsigned)(cols < 65535 ? cols : 65535);
+    hipLaunchKernelGGL(cvt_f64_f32_kernel, dim3((unsigned)blocks_of(rows, 256), gy), dim3(256), 0, st, A, lda, B,
+                       ldb, rows, cols);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsigned long long *info,
+                        hipStream_t st)
+{
+    if (w <= 0 || w > kLw) return HPL_ERR_INTERNAL;
+    const int64_t below = n - c - w;
+    const int64_t g = below > 0 ? blocks_of(below, 256) : 1;
+    hipLaunchKernelGGL(panel32_leaf_kernel, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st)
+{
+    if (ncols <= 0 || nbk <= 0) return HPL_OK;
+    if (nbk > kTl) return HPL_ERR_INTERNAL;
+    if (nbk == kTl)
+        hipLaunchKernelGGL(trsm32_leaf_kernel<true>, dim3((unsigned)blocks_of(ncols, 256)), dim3(256), 0, st, L, ldl, B,
+                           ldb, nbk, ncols);
+    else
+        hipLaunchKernelGGL(trsm32_leaf_kernel<false>, dim3((unsigned)blocks_of(ncols, 256)), dim3(256), 0, st, L, ldl,
+                           B, ldb, nbk, ncols);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_sgemm32(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B, int64_t ldb,
+                   float *C, int64_t ldc, hipStream_t st)
+{
+    if (m <= 0 || n <= 0 || k <= 0) return HPL_OK;
+    const int64_t gx = blocks_of(m, 64), gy = blocks_of(n, 64);
+    if (gy > 65535) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(sgemm32_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, m, n, k, A, lda, B, ldb,
+                       C, ldc);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols, int w,
+                     unsigned *mx, int *sexp, hipStream_t st)
+{
+    HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)mx, 1, 0ull, st));
+    const unsigned gyl = (unsigned)(w < 65535 ? w : 65535);
+    hipLaunchKernelGGL(maxabs32_kernel, dim3((unsigned)blocks_of(m, 256), gyl), dim3(256), 0, st, L, ldl, m,
+                       (int64_t)w, mx);
+    HPLX_TRY_LAUNCH();
+    const unsigned gyu = (unsigned)(ncols < 65535 ? ncols : 65535);
+    hipLaunchKernelGGL(maxabs32_kernel, dim3((unsigned)blocks_of(w, 256), gyu), dim3(256), 0, st, U, ldu,
+                       (int64_t)w, ncols, mx + 1);
+    HPLX_TRY_LAUNCH();
+    hipLaunchKernelGGL(scale_exp_kernel, dim3(1), dim3(1), 0, st, mx, sexp);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols,
+                       int w, const int *sexp, void *A16, void *B16, hipStream_t st)
+{
+    const int64_t gl = blocks_of(m, 256), gu = blocks_of((int64_t)w * ncols, 256);
+    if (gu > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    if (fmt == 0) {
+        hipLaunchKernelGGL(cvt_l_kernel<0>, dim3((unsigned)gl), dim3(256), 0, st, L, ldl, m, w, sexp,
+                           (_Float16 *)A16);
+        HPLX_TRY_LAUNCH();
+        hipLaunchKernelGGL(cvt_u_kernel<0>, dim3((unsigned)gu), dim3(256), 0, st, U, ldu, w, ncols, sexp,
+                           (_Float16 *)B16);
+    } else {
+        hipLaunchKernelGGL(cvt_l_kernel<1>, dim3((unsigned)gl), dim3(256), 0, st, L, ldl, m, w, sexp, (__bf16 *)A16);
+        HPLX_TRY_LAUNCH();
+        hipLaunchKernelGGL(cvt_u_kernel<1>, dim3((unsigned)gu), dim3(256), 0, st, U, ldu, w, ncols, sexp,
+                           (__bf16 *)B16);
+    }
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, const void *B16, float *C,
+                        int64_t ldc, hipStream_t st)
+{
+    if (m <= 0 || n <= 0 || K <= 0) return HPL_OK;
+    if (K % kHBK) return HPL_ERR_INTERNAL;
+    const int64_t tiles_m = blocks_of(m, kHBM), tiles_n = blocks_of(n, kHBN);
+    const int64_t g = tiles_m * tiles_n;
+    if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    if (fmt == 0)
+        hipLaunchKernelGGL(hgemm_update_kernel<0>, dim3((unsigned)g), dim3(256), 0, st, m, n, K,
+                           (const _Float16 *)A16, (const _Float16 *)B16, C, ldc, tiles_m);
+    else
+        hipLaunchKernelGGL(hgemm_update_kernel<1>, dim3((unsigned)g), dim3(256), 0, st, m, n, K,
+                           (const __bf16 *)A16, (const __bf16 *)B16, C, ldc, tiles_m);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_mxp_residual(const double *A, int64_t lda, const double *x, const double *b, double *r, int64_t n,
+                        bool anorm, unsigned long long *red, hipStream_t st)
+{
+    if (n <= 0) return HPL_OK;
+    hipLaunchKernelGGL(mxp_residual_kernel, dim3((unsigned)blocks_of(n, 256)), dim3(256), 0, st, A, lda, x, b, r, n,
+                       anorm ? 1 : 0, red);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+int launch_axpy(double *x, const double *d, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return HPL_OK;
+    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)blocks_of(n, 256)), dim3(256), 0, st, x, d, n);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+}  // namespace hplx

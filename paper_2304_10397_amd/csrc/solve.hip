@@ -28,8 +28,8 @@ namespace {
 constexpr int kBs = 64;          // diagonal block rows (one per lane)
 constexpr int kSvThreads = 256;  // 4 waves
 
-template <int mode>
-__global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *__restrict__ T, int64_t ldt,
+template <int mode, typename TT>
+__global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const TT *__restrict__ T, int64_t ldt,
                                                                  double *__restrict__ B, int64_t ldb, int64_t nrhs,
                                                                  int64_t r0, int bs, int64_t row_begin,
                                                                  int64_t row_end)
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *_
     // ---- 1. diagonal block: stage it (coalesced), then one wave per right-hand side
     for (int e = t; e < kBs * kBs; e += kSvThreads) {
         const int r = e % kBs, c = e / kBs;
-        Td[r][c] = (r < bs && c < bs) ? T[off(r0 + r, r0 + c, ldt)] : (r == c ? 1.0 : 0.0);
+        Td[r][c] = (r < bs && c < bs) ? (double)T[off(r0 + r, r0 + c, ldt)] : (r == c ? 1.0 : 0.0);
     }
     __syncthreads();
     for (int64_t c = wid; c < nrhs; c += kSvThreads / 64) {
@@ -75,13 +75,13 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const double *_
     if (i >= row_end) return;
     double a[kBs];
     if (mode < 2) {
-        const double *base = T + off(i, r0, ldt);  // T_op(i, r0 + k) = T(i, r0 + k)
+        const TT *base = T + off(i, r0, ldt);  // T_op(i, r0 + k) = T(i, r0 + k)
 #pragma unroll
-        for (int k = 0; k < kBs; ++k) a[k] = (k < bs) ? base[(size_t)k * (size_t)ldt] : 0.0;
+        for (int k = 0; k < kBs; ++k) a[k] = (k < bs) ? (double)base[(size_t)k * (size_t)ldt] : 0.0;
     } else {
-        const double *base = T + off(r0, i, ldt);  // T_op(i, r0 + k) = T(r0 + k, i)
+        const TT *base = T + off(r0, i, ldt);  // T_op(i, r0 + k) = T(r0 + k, i)
 #pragma unroll
-        for (int k = 0; k < kBs; ++k) a[k] = (k < bs) ? base[k] : 0.0;
+        for (int k = 0; k < kBs; ++k) a[k] = (k < bs) ? (double)base[k] : 0.0;
     }
     for (int64_t c = 0; c < nrhs; ++c) {
         const double *y = Y + c * kBs;
@@ -139,23 +139,47 @@ int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int
     if (lds > 64 * 1024) return HPL_ERR_INTERNAL;
     switch (mode) {
     case 0:
-        hipLaunchKernelGGL(solve_block_kernel<0>, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
+        hipLaunchKernelGGL((solve_block_kernel<0, double>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
                            r0, (int)bs, row_begin, row_end);
         break;
     case 1:
-        hipLaunchKernelGGL(solve_block_kernel<1>, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
+        hipLaunchKernelGGL((solve_block_kernel<1, double>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
                            r0, (int)bs, row_begin, row_end);
         break;
     case 2:
-        hipLaunchKernelGGL(solve_block_kernel<2>, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
+        hipLaunchKernelGGL((solve_block_kernel<2, double>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
                            r0, (int)bs, row_begin, row_end);
         break;
     case 3:
-        hipLaunchKernelGGL(solve_block_kernel<3>, dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
+        hipLaunchKernelGGL((solve_block_kernel<3, double>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
                            r0, (int)bs, row_begin, row_end);
         break;
     default: return HPL_ERR_INTERNAL;
     }
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+// FP32 factors (the mixed-precision LU), FP64 right-hand sides: modes 0 and 1.
+int launch_solve_block_f32(const float *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs, int64_t r0, int64_t bs,
+                           int64_t row_begin, int64_t row_end, int mode, hipStream_t st)
+{
+    if (bs <= 0 || nrhs <= 0) return HPL_OK;
+    if (bs > kBs) return HPL_ERR_INTERNAL;
+    const int64_t rows = row_end > row_begin ? row_end - row_begin : 0;
+    int64_t g = (rows + kSvThreads - 1) / kSvThreads;
+    if (g < 1) g = 1;
+    if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    const size_t lds = sizeof(double) * (size_t)kBs * (size_t)nrhs;
+    if (lds > 64 * 1024) return HPL_ERR_INTERNAL;
+    if (mode == 0)
+        hipLaunchKernelGGL((solve_block_kernel<0, float>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb,
+                           nrhs, r0, (int)bs, row_begin, row_end);
+    else if (mode == 1)
+        hipLaunchKernelGGL((solve_block_kernel<1, float>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb,
+                           nrhs, r0, (int)bs, row_begin, row_end);
+    else
+        return HPL_ERR_INTERNAL;
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }

@@ -67,6 +67,9 @@ def _load():
         "hpl_solve_grad_a": (i32, [P, i64, P, i64, i64, i64, P, i64, P]),
         "hpl_generate_normal": (i32, [u64, u64, P, i64, i64, i64, P]),
         "hpl_add_diagonal": (i32, [P, i64, i64, dbl, P]),
+        "hpl_mxp_generate": (i32, [u64, P, i64, i64, P]),
+        "hpl_mxp_factor": (i32, [P, i64, i64, i64, i32, P, i64, P, P]),
+        "hpl_mxp_solve": (i32, [P, i64, P, i64, i64, P, P, i64, P, P]),
         "hpl_release": (i32, []),
         "hpl_strerror": (ctypes.c_char_p, [i32]),
         "hpl_last_error_detail": (ctypes.c_char_p, []),
@@ -82,6 +85,7 @@ _lib = _load()
 EXPORTED = ("hpl_factor", "hpl_solve", "hpl_residual", "hpl_residual_gen", "hpl_generate",
             "hpl_set_option", "hpl_get_option", "hpl_get_stats", "hpl_reset_stats",
             "hpl_mfma_peak", "hpl_solve_grad_a", "hpl_generate_normal", "hpl_add_diagonal",
+            "hpl_mxp_generate", "hpl_mxp_factor", "hpl_mxp_solve",
             "hpl_release", "hpl_strerror", "hpl_last_error_detail")
 
 
@@ -232,6 +236,59 @@ def hpl_solve_grad_a(GB, X, dA=None, stream=None):
         raise ValueError("dA must be n x n")
     _check("hpl_solve_grad_a", _lib.hpl_solve_grad_a(pG, ldg, pX, ldx, n, k, pD, ldd, _stream(stream)))
     return dA
+
+
+MXP_FP16, MXP_BF16 = 0, 1
+
+
+def colmajor32(rows, cols, ld=None, device="cuda"):
+    """Empty column-major float32 tensor of shape (rows, cols), leading dimension ld."""
+    torch = _torch()
+    ld = rows if ld is None else ld
+    return torch.empty((max(cols, 1), max(ld, 1)), dtype=torch.float32, device=device).t()[:rows, :cols]
+
+
+def hpl_mxp_generate(seed, A, stream=None):
+    """Fill the square column-major float64 tensor A with the diagonally dominant MxP input."""
+    pA, n, m, lda = _matrix("A", A)
+    if n != m:
+        raise ValueError("A must be square")
+    _check("hpl_mxp_generate", _lib.hpl_mxp_generate(int(seed) % 2**64, pA, n, lda, _stream(stream)))
+    return A
+
+
+def hpl_mxp_factor(A, nb=512, fmt=MXP_FP16, LU=None, stream=None):
+    """No-pivot LU of A (float64) in mixed precision; returns (LU float32 column-major, info)."""
+    torch = _torch()
+    pA, n, m, lda = _matrix("A", A)
+    if n != m:
+        raise ValueError("A must be square")
+    if LU is None:
+        LU = colmajor32(n, n, device=A.device)
+    if LU.dtype != torch.float32 or not LU.is_cuda or LU.shape != (n, n) or (n > 1 and LU.stride(0) != 1):
+        raise TypeError("LU must be a column-major float32 CUDA tensor of A's shape")
+    ldlu = LU.stride(1) if n > 1 else max(1, n)
+    info = ctypes.c_int64(0)
+    _check("hpl_mxp_factor", _lib.hpl_mxp_factor(pA, n, lda, int(nb), int(fmt), ctypes.c_void_p(LU.data_ptr()),
+                                                  ldlu, ctypes.byref(info), _stream(stream)))
+    return LU, int(info.value)
+
+
+def hpl_mxp_solve(A, LU, b, x=None, max_iter=50, stream=None):
+    """x refined in FP64 from the FP32 factors; returns (x, out[5] numpy)."""
+    pA, n, m, lda = _matrix("A", A)
+    ldlu = LU.stride(1) if n > 1 else max(1, n)
+    if x is None:
+        x = _torch().empty(n, dtype=_torch().float64, device=A.device)
+    pb, nb_, _, _ = _matrix("b", b)
+    px, nx, _, _ = _matrix("x", x)
+    if nb_ != n or nx != n:
+        raise ValueError("b and x must have n entries")
+    out = np.zeros(5)
+    _check("hpl_mxp_solve", _lib.hpl_mxp_solve(pA, lda, ctypes.c_void_p(LU.data_ptr()), ldlu, n, pb, px,
+                                                int(max_iter), out.ctypes.data_as(ctypes.c_void_p),
+                                                _stream(stream)))
+    return x, out
 
 
 def _colmajor_copy(T):

@@ -89,6 +89,25 @@ def test_mfma_peak_argument_errors():
     assert L.hpl_mfma_peak(10, None, None) == -2
 
 
+def test_mxp_argument_errors():
+    L = h.lib()
+    info = ctypes.c_int64(0)
+    out = (ctypes.c_double * 5)()
+    assert L.hpl_mxp_factor(None, 4, 4, 64, 0, FAKE, 4, ctypes.byref(info), None) == -1
+    assert L.hpl_mxp_factor(FAKE, -1, 4, 64, 0, FAKE, 4, ctypes.byref(info), None) == -2
+    assert L.hpl_mxp_factor(FAKE, 4, 3, 64, 0, FAKE, 4, ctypes.byref(info), None) == -3
+    assert L.hpl_mxp_factor(FAKE, 4, 4, 96, 0, FAKE, 4, ctypes.byref(info), None) == -4
+    assert L.hpl_mxp_factor(FAKE, 4, 4, 64, 2, FAKE, 4, ctypes.byref(info), None) == -5
+    assert L.hpl_mxp_factor(FAKE, 4, 4, 64, 1, None, 4, ctypes.byref(info), None) == -6
+    assert L.hpl_mxp_factor(FAKE, 4, 4, 64, 1, FAKE, 2, ctypes.byref(info), None) == -7
+    assert L.hpl_mxp_factor(FAKE, 4, 4, 64, 1, FAKE, 4, None, None) == -8
+    assert L.hpl_mxp_solve(FAKE, 4, FAKE, 4, 4, FAKE, FAKE, -1, out, None) == -8
+    assert L.hpl_mxp_solve(FAKE, 4, FAKE, 4, 4, FAKE, FAKE, 5, None, None) == -9
+    assert L.hpl_mxp_solve(FAKE, 3, FAKE, 4, 4, FAKE, FAKE, 5, out, None) == -2
+    assert L.hpl_mxp_generate(1, None, 4, 4, None) == -2
+    assert L.hpl_mxp_generate(1, FAKE, 4, 2, None) == -4
+
+
 def test_options_roundtrip_and_rejects():
     old = h.hpl_get_option(h.HPL_OPT_LOOKAHEAD)
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 0)

@@ -1,0 +1,108 @@
+"""GPU parity tests of the mixed-precision LU and FP64 refinement (C ABI:
+hpl_mxp_generate, hpl_mxp_factor, hpl_mxp_solve) against the oracle
+(oracle.mxp_gen, oracle.lu_mxp, the FP64 oracle solve and residual)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import hpl, to_gpu, to_host, torch
+
+pytestmark = pytest.mark.gpu
+
+UNIT = {0: 2.0 ** -11, 1: 2.0 ** -8}   # unit roundoff of FP16, BF16
+
+
+def gpu_mxp_system(n, seed):
+    h = hpl()
+    A = h.colmajor(n, n)
+    h.hpl_mxp_generate(seed, A)
+    b = h.colmajor(n, 1)
+    h.hpl_generate(seed, 1, b)
+    return A, b[:, 0]
+
+
+@pytest.mark.parametrize("n", [1, 7, 300, 1000])
+def test_mxp_generate_bitwise(n):
+    A, _ = gpu_mxp_system(n, 11)
+    assert np.array_equal(to_host(A).view(np.int64), oracle.mxp_gen(11, n).view(np.int64))
+
+
+def dyadic_lu(n, seed):
+    rng = np.random.default_rng(seed)
+    L = np.tril(rng.integers(-4, 5, (n, n)) / 8.0, -1) + np.eye(n)
+    U = np.triu(rng.integers(-7, 8, (n, n)).astype(float), 1) + np.diag(2.0 ** rng.integers(0, 3, n))
+    return np.asfortranarray(L @ U), L, U
+
+
+@pytest.mark.parametrize("n,nb", [(64, 64), (200, 64), (300, 128), (517, 256)])
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_mxp_factor_dyadic_exact(n, nb, fmt):
+    h = hpl()
+    A, L, U = dyadic_lu(n, n + nb + fmt)
+    LU, info = h.hpl_mxp_factor(to_gpu(A), nb=nb, fmt=fmt)
+    assert info == 0
+    LUh = LU.cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.tril(LUh, -1) + np.eye(n), L)
+    assert np.array_equal(np.triu(LUh), U)
+
+
+@pytest.mark.parametrize("n,nb", [(256, 64), (1000, 128), (1536, 512)])
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_mxp_factor_vs_oracle(n, nb, fmt):
+    h = hpl()
+    A, _ = gpu_mxp_system(n, 5)
+    LU, info = h.hpl_mxp_factor(A, nb=nb, fmt=fmt)
+    assert info == 0
+    Ah = oracle.mxp_gen(5, n)
+    LUo, info_o = oracle.lu_mxp(Ah, nb, fmt)
+    assert info_o == 0
+    G = LU.cpu().numpy().astype(np.float64)
+    O = LUo.astype(np.float64)
+    # the same method in the same formats: differences only from FP32 rounding
+    # order (FMA, the panel's blocking, the MFMA's accumulation), each of which
+    # may move an operand across a rounding boundary of the format
+    Lg, Ug = np.tril(G, -1) + np.eye(n), np.triu(G)
+    scale = np.abs(np.tril(O, -1) + np.eye(n)) @ np.abs(np.triu(O))
+    d = np.abs(Lg @ Ug - (np.tril(O, -1) + np.eye(n)) @ np.triu(O))
+    ratio = float(np.max(d / (UNIT[fmt] * scale)))
+    print(f"n={n} nb={nb} fmt={fmt}: |LU_gpu - LU_oracle| <= {ratio:.3g} u |L||U|")
+    assert ratio <= 4.0
+    # and the GPU factors satisfy the backward-error bound of the format
+    E = np.abs(Ah - Lg @ Ug)
+    bound = 2.0 * n * UNIT[fmt] * (np.abs(Lg) @ np.abs(Ug)) + 4.0 * 2.0 ** -24 * np.abs(Ah)
+    assert np.all(E <= bound)
+
+
+@pytest.mark.parametrize("n,nb", [(512, 128), (2048, 256), (3000, 512)])
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_mxp_refinement_reaches_fp64(n, nb, fmt):
+    h = hpl()
+    A, b = gpu_mxp_system(n, 9)
+    LU, info = h.hpl_mxp_factor(A, nb=nb, fmt=fmt)
+    assert info == 0
+    x, out = h.hpl_mxp_solve(A, LU, b, max_iter=50)
+    print(f"n={n} fmt={fmt}: {int(out[0])} corrections, scaled residual {out[1]:.3g}")
+    assert out[1] < 16.0
+    Ah = oracle.mxp_gen(9, n)
+    bh = oracle.gen(9, 1, n, 1)[:, 0].copy()
+    xh = x.cpu().numpy()
+    res = oracle.residual(Ah, xh, bh)
+    assert res[0] < 16.0
+    LU64 = Ah.copy(order="F")
+    ipiv, _ = oracle.lu(LU64)
+    xo = bh.copy()
+    oracle.solve(LU64, ipiv, xo)
+    # refinement stops once the residual test passes (scaled residual < 16),
+    # which bounds the error at about scaled * n * eps relative (times the
+    # condition number); x is held to the 1e-10 relative tolerance of the FP64 path
+    err = np.max(np.abs(xh - xo)) / np.max(np.abs(xo))
+    print(f"   |x - x_oracle| / |x_oracle| = {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_mxp_zero_refinements_allowed():
+    h = hpl()
+    A, b = gpu_mxp_system(300, 3)
+    LU, _ = h.hpl_mxp_factor(A, nb=64, fmt=0)
+    x, out = h.hpl_mxp_solve(A, LU, b, max_iter=0)
+    assert out[0] == 0.0 and out[1] > 0.0
