@@ -159,6 +159,107 @@ def bench_diffsolve(args, torch, h):
     print(json.dumps(out), flush=True)
 
 
+def bench_mxp(args, torch, h):
+    """HPL-MxP: time from the diagonally dominant A (in HBM) to an x that passes
+    the FP64 scaled-residual test, mixed precision (FP16 and BF16 LU + FP64
+    refinement) against the FP64 path (partial-pivoting LU + solve) on the same
+    matrix; speed-up = t_fp64 / t_mxp."""
+    n = 65536 if args.n == 163840 else args.n
+    nb = args.nb
+    A = h.colmajor(n, n)
+    h.hpl_mxp_generate(args.seed, A)
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.hpl_generate(args.seed, 1, b)
+    flops = hpl_flops(n)
+    res = {}
+    # FP64 path on a copy of the same matrix
+    LU64 = h.colmajor(n, n)
+    x64 = torch.empty_like(b)
+    t64 = []
+    for step in range(args.warmup + args.steps):
+        LU64.copy_(A)
+        x64.copy_(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ipiv, info = h.hpl_factor(LU64, nb)
+        h.hpl_solve(LU64, ipiv, x64)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log(f"fp64 step {step}: {dt:.3f} s, info={info}")
+        if step >= args.warmup:
+            t64.append(dt)
+    r64 = h.hpl_residual(A, x64.reshape(n, 1), b.reshape(n, 1))
+    del LU64
+    torch.cuda.empty_cache()
+    t_fp64 = sum(t64) / len(t64)
+    LU = h.colmajor32(n, n)
+    x = torch.empty_like(b)
+    gemm_stats = None
+    for fmt, name in ((h.MXP_FP16, "fp16"), (h.MXP_BF16, "bf16")):
+        ts = []
+        for step in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            timed = step >= args.warmup
+            if timed and fmt == h.MXP_FP16:
+                h.hpl_reset_stats()
+                h.hpl_set_option(h.HPL_OPT_TIMING, 1)
+            t0 = time.perf_counter()
+            _, info = h.hpl_mxp_factor(A, nb=nb, fmt=fmt, LU=LU)
+            _, out = h.hpl_mxp_solve(A, LU, b, x=x, max_iter=50)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            h.hpl_set_option(h.HPL_OPT_TIMING, 0)
+            if timed and fmt == h.MXP_FP16:
+                gemm_stats = h.hpl_get_stats()
+            log(f"{name} step {step}: {dt:.3f} s, {int(out[0])} corrections, scaled residual {out[1]:.3g}, "
+                f"info={info}")
+            if timed:
+                ts.append(dt)
+        rr = h.hpl_residual(A, x.reshape(n, 1), b.reshape(n, 1))
+        res[name] = {"seconds": round(sum(ts) / len(ts), 4), "corrections": int(out[0]),
+                     "scaled_residual": float(rr[0]), "residual_pass": bool(rr[0] < 16.0),
+                     "speedup_vs_fp64": round(t_fp64 / (sum(ts) / len(ts)), 3),
+                     "effective_tflops": round(flops / (sum(ts) / len(ts)) / 1e12, 2)}
+    g = gemm_stats["mxp_gemm"]
+    f = gemm_stats["mxp_fact"]
+    out = {
+        "metric": "HPL-MxP: speed-up of FP16 LU + FP64 refinement over the FP64 path, to FP64 residual < 16",
+        "value": res["fp16"]["speedup_vs_fp64"],
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * res["fp16"]["seconds"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp16/bf16 MFMA, fp32 accumulate; fp64 refinement",
+        "data": "synthetic",
+        "config": {
+            "workload": f"HPL-MxP, N={n}, NB={nb}, A ~ U[-0.5,0.5) with a_ii = sum_j |a_ij|, "
+                        f"b ~ U[-0.5,0.5), seed {args.seed}",
+            "n": n, "nb": nb,
+            "fp64_path": {"seconds": round(t_fp64, 4), "tflops": round(flops / t_fp64 / 1e12, 2),
+                          "scaled_residual": float(r64[0])},
+            "fp16": res["fp16"], "bf16": res["bf16"],
+            "fp16_phase_ms": {"trailing_update": round(g["ms"], 2), "panel_u12_convert": round(f["ms"], 2)},
+        },
+        "roofline": {
+            "kernel": "hgemm_update_kernel (A22 += (-L21) U12, FP16 MFMA, FP32 C)",
+            "bound": "hbm",
+            "achieved": round(g["bytes"] / (g["ms"] * 1e-3) / 1e9, 1) if g["ms"] else None,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(g["bytes"] / (g["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if g["ms"] else None,
+            "launches": g["launches"],
+            "avg_launch_ms": round(g["ms"] / g["launches"], 4) if g["launches"] else None,
+            "tflops": round(g["flops"] / (g["ms"] * 1e-3) / 1e12, 2) if g["ms"] else None,
+            "traffic": None,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,9 +272,10 @@ def main():
     ap.add_argument("--pad", type=int, default=0, help="lda = n + pad")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="N of the oracle sample (0: skip)")
     ap.add_argument("--progress", type=int, default=32, help="progress line every k panels (stderr)")
-    ap.add_argument("--workload", choices=["hpl", "diffsolve"], default="hpl",
+    ap.add_argument("--workload", choices=["hpl", "diffsolve", "mxp"], default="hpl",
                     help="hpl: the HPL factor + solve (default); diffsolve: the differentiable FP64 "
-                         "solve, N=8192 NB=256 16 right-hand sides, forward + backward")
+                         "solve, N=8192 NB=256 16 right-hand sides, forward + backward; mxp: mixed-precision "
+                         "LU + FP64 refinement at N=65536 against the FP64 path on the same matrix")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (reference for the HBM byte "
                          "counters FETCH_SIZE / WRITE_SIZE) and exit")
@@ -200,6 +302,8 @@ def main():
         return
     if args.workload == "diffsolve":
         return bench_diffsolve(args, torch, h)
+    if args.workload == "mxp":
+        return bench_mxp(args, torch, h)
     n, nb = args.n, args.nb
     log(f"device {torch.cuda.get_device_name(dev)}; N={n} NB={nb} look-ahead={args.lookahead}")
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, args.lookahead)

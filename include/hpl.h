@@ -242,7 +242,9 @@ int64_t hpl_get_option(int key);
  * Per-kernel-class statistics of the calls made since the last
  * hpl_reset_stats, collected while HPL_OPT_TIMING is 1.  Entry k of the
  * arrays describes class k: 0 trailing GEMM, 1 panel (recursive FACT, all of
- * its kernels), 2 laswp, 3 trsm, 4 solve, 5 panel-internal GEMM.  For each
+ * its kernels), 2 laswp, 3 trsm, 4 solve, 5 interchange plans, 6 the mixed-
+ * precision trailing update, 7 the rest of a mixed-precision panel step
+ * (FACT, U12, scaling and conversion).  For each
  * class: launches[k], total device milliseconds ms[k] (sum of HIP-event
  * intervals around each launch on the stream it ran on) and algorithmic
  * flops[k] and bytes[k] (the method's own operation and HBM byte counts).

@@ -69,7 +69,8 @@ static std::atomic<int64_t> opt_gemm_tile{0};
 // ---------------------------------------------------------------------------
 // statistics (HPL_OPT_TIMING)
 // ---------------------------------------------------------------------------
-enum { ST_GEMM = 0, ST_PANEL = 1, ST_LASWP = 2, ST_TRSM = 3, ST_SOLVE = 4, ST_PLAN = 5, ST_N = 6 };
+enum { ST_GEMM = 0, ST_PANEL = 1, ST_LASWP = 2, ST_TRSM = 3, ST_SOLVE = 4, ST_PLAN = 5, ST_MXP_GEMM = 6,
+       ST_MXP_FACT = 7, ST_N = 8 };
 static std::mutex g_st_mu;
 static int64_t g_st_launch[ST_N];
 static double g_st_ms[ST_N], g_st_flops[ST_N], g_st_bytes[ST_N];
@@ -603,24 +604,34 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
     unsigned *mx = (unsigned *)(ws + sc_off);
     int *sexp = (int *)(ws + sc_off + 16);
     unsigned long long *dinfo = (unsigned long long *)(ws + sc_off + 32);
+    Timer tm(d, opt_timing.load() != 0);
     HPLX_PROPAGATE(launch_fill_u64(dinfo, 1, ULLONG_MAX, st));
     HPLX_PROPAGATE(launch_cvt_f64_f32(A, lda, LU, ldlu, n, n, st));
     for (int64_t c0 = 0; c0 < n; c0 += nb) {
         const int64_t w = (n - c0) < nb ? (n - c0) : nb;
         const int64_t c1 = c0 + w;
-        HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c0, w, dinfo, st));
-        if (c1 >= n) break;
         const int64_t m = n - c1;
-        HPLX_PROPAGATE(mxp_trsm(LU + off(c0, c0, ldlu), ldlu, w, LU + off(c0, c1, ldlu), ldlu, m, st));
-        HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c0, ldlu), ldlu, m, LU + off(c0, c1, ldlu), ldlu, m, (int)w, mx,
-                                        sexp, st));
-        HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c0, ldlu), ldlu, m, LU + off(c0, c1, ldlu), ldlu, m,
-                                          (int)w, sexp, A16, B16, st));
+        int id = tm.begin(ST_MXP_FACT, st);
+        HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c0, w, dinfo, st));
+        if (c1 < n) {
+            HPLX_PROPAGATE(mxp_trsm(LU + off(c0, c0, ldlu), ldlu, w, LU + off(c0, c1, ldlu), ldlu, m, st));
+            HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c0, ldlu), ldlu, m, LU + off(c0, c1, ldlu), ldlu, m, (int)w,
+                                            mx, sexp, st));
+            HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c0, ldlu), ldlu, m, LU + off(c0, c1, ldlu), ldlu, m,
+                                              (int)w, sexp, A16, B16, st));
+        }
+        HPLX_PROPAGATE(tm.end(id, st, (double)(n - c0) * (double)w * (double)w + (double)w * (double)w * (double)m,
+                              4.0 * (double)(n - c0) * (double)w * 2.0 + 4.0 * (double)w * (double)m * 2.0));
+        if (c1 >= n) break;
+        id = tm.begin(ST_MXP_GEMM, st);
         HPLX_PROPAGATE(launch_hgemm_update(fmt, m, m, w, A16, B16, LU + off(c1, c1, ldlu), ldlu, st));
+        HPLX_PROPAGATE(tm.end(id, st, 2.0 * (double)m * (double)m * (double)w,
+                              8.0 * (double)m * (double)m + 4.0 * (double)w * (double)m));
     }
     unsigned long long hinfo = 0;
     HPLX_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof hinfo, hipMemcpyDeviceToHost, st));
     HPLX_TRY(hipStreamSynchronize(st));
+    HPLX_PROPAGATE(tm.collect());
     *info = (hinfo == ULLONG_MAX) ? 0 : (int64_t)hinfo;
     return HPL_OK;
 }
