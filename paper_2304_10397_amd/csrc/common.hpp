@@ -23,6 +23,27 @@ __host__ __device__ __forceinline__ size_t off(int64_t i, int64_t j, int64_t ld)
 
 // Value of v held by lane l of the wave (l uniform across the wave): two
 // v_readlane_b32, a few cycles, instead of an LDS round trip.
+// Block index -> output tile (tm, tn) of a tiles_m x tiles_n grid.  Workgroups
+// are dispatched round-robin over the 8 XCDs, each with its own L2: the index
+// is remapped so that each XCD receives a contiguous run of tiles, and the run
+// is ordered in groups of group_m tile-rows (column-major inside a group), so
+// that the workgroups resident on one XCD share A row-panels and B
+// column-panels in that XCD's L2.
+__device__ __forceinline__ void tile_of_block(int64_t bid, int64_t nwg, int64_t tiles_m, int64_t tiles_n,
+                                              int64_t group_m, int64_t &tm, int64_t &tn)
+{
+    const int64_t xcd = bid & 7, in_xcd = bid >> 3;
+    const int64_t per = nwg >> 3, rem = nwg & 7;
+    const int64_t lin = xcd * per + (xcd < rem ? xcd : rem) + in_xcd;
+    const int64_t group_size = group_m * tiles_n;
+    const int64_t g = lin / group_size;
+    const int64_t first_m = g * group_m;
+    const int64_t gm = (tiles_m - first_m) < group_m ? (tiles_m - first_m) : group_m;
+    const int64_t r = lin - g * group_size;
+    tm = first_m + r % gm;
+    tn = r / gm;
+}
+
 __device__ __forceinline__ double read_lane(double v, int l)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -197,8 +218,10 @@ int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const fl
                        int w, const int *sexp, void *A16, void *B16, hipStream_t st);
 int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, const void *B16, float *C,
                         int64_t ldc, hipStream_t st);
+// r = b - A x with kResSplit column chunks; part holds 2 kResSplit n doubles of partial sums.
+constexpr int kResSplit = 16;
 int launch_mxp_residual(const double *A, int64_t lda, const double *x, const double *b, double *r, int64_t n,
-                        bool anorm, unsigned long long *red, hipStream_t st);
+                        bool anorm, double *part, unsigned long long *red, hipStream_t st);
 int launch_axpy(double *x, const double *d, int64_t n, hipStream_t st);
 int launch_solve_block_f32(const float *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs, int64_t r0, int64_t bs,
                            int64_t row_begin, int64_t row_end, int mode, hipStream_t st);

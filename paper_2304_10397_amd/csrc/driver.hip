@@ -639,16 +639,17 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
 static int mxp_solve_impl(Device *d, const double *A, int64_t lda, const float *LU, int64_t ldlu, int64_t n,
                           const double *b, double *x, int64_t max_iter, double *out, hipStream_t st)
 {
-    if (d->mxp_vec_cap < 2 * n) {
+    const int64_t need = (2 + 2 * (int64_t)kResSplit) * n;  // r, d, partial sums
+    if (d->mxp_vec_cap < need) {
         if (d->mxp_vec) HPLX_TRY(hipFree(d->mxp_vec));
         d->mxp_vec = nullptr;
         d->mxp_vec_cap = 0;
-        if (hipMalloc((void **)&d->mxp_vec, sizeof(double) * 2 * (size_t)n) != hipSuccess)
+        if (hipMalloc((void **)&d->mxp_vec, sizeof(double) * (size_t)need) != hipSuccess)
             HPLX_FAIL(HPL_ERR_NOMEM, "refinement vectors allocation failed");
-        d->mxp_vec_cap = 2 * n;
+        d->mxp_vec_cap = need;
     }
     HPLX_PROPAGATE(ensure_red(d, 4));
-    double *r = d->mxp_vec, *dv = d->mxp_vec + n;
+    double *r = d->mxp_vec, *dv = d->mxp_vec + n, *part = d->mxp_vec + 2 * n;
     const int64_t bs = 64;
     const int64_t nblk = (n + bs - 1) / bs;
     auto lu_solve = [&](double *v) -> int {  // v <- U^{-1} L^{-1} v with the FP32 factors
@@ -669,7 +670,7 @@ static int mxp_solve_impl(Device *d, const double *A, int64_t lda, const float *
     int64_t it = 0;
     for (;;) {
         HPLX_PROPAGATE(launch_fill_u64(d->red, 4, 0ull, st));
-        HPLX_PROPAGATE(launch_mxp_residual(A, lda, x, b, r, n, it == 0, d->red, st));
+        HPLX_PROPAGATE(launch_mxp_residual(A, lda, x, b, r, n, it == 0, part, d->red, st));
         unsigned long long h[4];
         HPLX_TRY(hipMemcpyAsync(h, d->red, sizeof h, hipMemcpyDeviceToHost, st));
         HPLX_TRY(hipStreamSynchronize(st));

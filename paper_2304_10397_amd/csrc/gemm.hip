@@ -55,22 +55,6 @@ struct GemmCfg {
     static_assert((BM * BK) % NT == 0 && (BK * BN) % NT == 0, "loads must divide evenly");
 };
 
-// Block index -> (tile_m, tile_n): XCD-contiguous runs, then grouped ordering.
-__device__ __forceinline__ void tile_of_block(int64_t bid, int64_t nwg, int64_t tiles_m, int64_t tiles_n,
-                                              int64_t &tm, int64_t &tn)
-{
-    const int64_t xcd = bid & 7, in_xcd = bid >> 3;
-    const int64_t per = nwg >> 3, rem = nwg & 7;
-    const int64_t lin = xcd * per + (xcd < rem ? xcd : rem) + in_xcd;
-    const int64_t group_size = (int64_t)kGroupM * tiles_n;
-    const int64_t g = lin / group_size;
-    const int64_t first_m = g * kGroupM;
-    const int64_t gm = (tiles_m - first_m) < kGroupM ? (tiles_m - first_m) : kGroupM;
-    const int64_t r = lin - g * group_size;
-    tm = first_m + r % gm;
-    tn = r / gm;
-}
-
 template <int BM, int BN, int WM, int WN, int TRAIL>
 __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
     int64_t m, int64_t n, int64_t k, const double *__restrict__ A, int64_t lda,
@@ -88,7 +72,7 @@ __global__ __launch_bounds__(WM *WN * 64, 2) void gemm_sub_kernel(
     __shared__ double Bs[2][BK][BS];
 
     int64_t tm, tn;
-    tile_of_block(blockIdx.x, (int64_t)gridDim.x, tiles_m, tiles_n, tm, tn);
+    tile_of_block(blockIdx.x, (int64_t)gridDim.x, tiles_m, tiles_n, kGroupM, tm, tn);
     const int64_t m0 = tm * BM, n0 = tn * BN;
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
@@ -244,7 +228,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_stream_kernel(
     __shared__ __attribute__((aligned(16))) double Bs[2][BN][SBK];
 
     int64_t tm, tn;
-    tile_of_block(blockIdx.x, (int64_t)gridDim.x, tiles_m, tiles_n, tm, tn);
+    tile_of_block(blockIdx.x, (int64_t)gridDim.x, tiles_m, tiles_n, kGroupM, tm, tn);
     const int64_t m0 = tm * SBM, n0 = tn * BN;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & (NW - 1);

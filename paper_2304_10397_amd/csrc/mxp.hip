@@ -58,9 +58,17 @@ __global__ __launch_bounds__(256) void panel32_leaf_kernel(float *__restrict__ A
 {
     __shared__ float D[kLw][kLw + 1];
     const int t = threadIdx.x;
-    for (int e = t; e < kLw * kLw; e += 256) {
-        const int r = e % kLw, q = e / kLw;
-        D[r][q] = (r < w && q < w) ? A[off(c + r, c + q, lda)] : (r == q ? 1.0f : 0.0f);
+    static_assert(kLw * kLw % 256 == 0, "staging must divide evenly");
+    float sv[kLw * kLw / 256];  // all loads in flight before the first LDS store
+#pragma unroll
+    for (int q = 0; q < kLw * kLw / 256; ++q) {
+        const int e = t + 256 * q, r = e % kLw, cc = e / kLw;
+        sv[q] = (r < w && cc < w) ? A[off(c + r, c + cc, lda)] : (r == cc ? 1.0f : 0.0f);
+    }
+#pragma unroll
+    for (int q = 0; q < kLw * kLw / 256; ++q) {
+        const int e = t + 256 * q;
+        D[e % kLw][e / kLw] = sv[q];
     }
     __syncthreads();
     for (int k = 0; k < w; ++k) {
@@ -117,9 +125,17 @@ __global__ __launch_bounds__(256) void trsm32_leaf_kernel(const float *__restric
 {
     __shared__ float Ls[kTl][kTl + 1];
     const int t = threadIdx.x;
-    for (int e = t; e < kTl * kTl; e += 256) {
-        const int r = e % kTl, q = e / kTl;
-        Ls[r][q] = (r < nbk && q < nbk) ? L[off(r, q, ldl)] : 0.0f;
+    static_assert(kTl * kTl % 256 == 0, "staging must divide evenly");
+    float sv[kTl * kTl / 256];  // all loads in flight before the first LDS store
+#pragma unroll
+    for (int q = 0; q < kTl * kTl / 256; ++q) {
+        const int e = t + 256 * q, r = e % kTl, cc = e / kTl;
+        sv[q] = (r < nbk && cc < nbk) ? L[off(r, cc, ldl)] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kTl * kTl / 256; ++q) {
+        const int e = t + 256 * q;
+        Ls[e % kTl][e / kTl] = sv[q];
     }
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * 256 + t;
@@ -154,7 +170,8 @@ __global__ __launch_bounds__(256) void trsm32_leaf_kernel(const float *__restric
 // ---------------------------------------------------------------------------
 // FP32 GEMM C(m x n) -= A(m x k) B(k x n), column-major, for the panel and
 // triangular-solve recursions: 64 x 64 tiles, 256 threads of 4 x 4 outputs,
-// k staged 16 at a time through LDS.
+// k staged 16 at a time through LDS; the next k tile is loaded into registers
+// while the current one is multiplied.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void sgemm32_kernel(int64_t m, int64_t n, int64_t k, const float *__restrict__ A,
                                                       int64_t lda, const float *__restrict__ B, int64_t ldb,
@@ -165,14 +182,26 @@ __global__ __launch_bounds__(256) void sgemm32_kernel(int64_t m, int64_t n, int6
     const int t = threadIdx.x, tx = t % 16, ty = t / 16;
     const int64_t m0 = (int64_t)blockIdx.x * 64, n0 = (int64_t)blockIdx.y * 64;
     float acc[4][4] = {};
+    float ra[4], rb[4];
+    // element u of this thread: A row (t % 64), k (t / 64 + 4u); B k (t % 16), column (t / 16 + 16u)
+    auto load = [&](int64_t k0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = t % 64, q = t / 64 + 4 * u;
+            ra[u] = (m0 + r < m && k0 + q < k) ? A[off(m0 + r, k0 + q, lda)] : 0.0f;
+            const int q2 = t % 16, c2 = t / 16 + 16 * u;
+            rb[u] = (k0 + q2 < k && n0 + c2 < n) ? B[off(k0 + q2, n0 + c2, ldb)] : 0.0f;
+        }
+    };
+    load(0);
     for (int64_t k0 = 0; k0 < k; k0 += 16) {
-        for (int e = t; e < 16 * 64; e += 256) {
-            const int r = e % 64, q = e / 64;  // A: row r, k q
-            As[q][r] = (m0 + r < m && k0 + q < k) ? A[off(m0 + r, k0 + q, lda)] : 0.0f;
-            const int q2 = e % 16, c2 = e / 16;  // B: k q2, column c2
-            Bs[q2][c2] = (k0 + q2 < k && n0 + c2 < n) ? B[off(k0 + q2, n0 + c2, ldb)] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            As[t / 64 + 4 * u][t % 64] = ra[u];
+            Bs[t % 16][t / 16 + 16 * u] = rb[u];
         }
         __syncthreads();
+        if (k0 + 16 < k) load(k0 + 16);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             float a[4], b[4];
@@ -207,9 +236,11 @@ __global__ __launch_bounds__(256) void maxabs32_kernel(const float *__restrict__
 {
     __shared__ float sh[4];
     float v = 0.0f;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < rows)
-        for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) v = fmaxf(v, fabsf(M[off(i, j, ld)]));
+    const int64_t total = rows * cols, stride = (int64_t)gridDim.x * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += stride) {
+        const int64_t j = e / rows, i = e - j * rows;  // consecutive threads walk down a column
+        v = fmaxf(v, fabsf(M[off(i, j, ld)]));
+    }
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -234,15 +265,26 @@ template <int FMT> struct Half;
 template <> struct Half<0> { typedef _Float16 T; };
 template <> struct Half<1> { typedef __bf16 T; };
 
-// L21 (m x w at ld) -> A16 row-major m x w (k contiguous): -(2^s l) rounded
+// L21 (m x w at ld) -> A16 row-major m x w (k contiguous): -(2^s l) rounded.
+// A 64 x 64 tile goes through LDS: read down the columns, written along rows.
 template <int FMT>
 __global__ __launch_bounds__(256) void cvt_l_kernel(const float *__restrict__ L, int64_t ld, int64_t m, int w,
                                                     const int *__restrict__ sexp, typename Half<FMT>::T *__restrict__ O)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= m) return;
+    __shared__ float tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int k0 = blockIdx.y * 64;
     const int s = *sexp;
-    for (int k = 0; k < w; ++k) O[(size_t)i * (size_t)w + k] = (typename Half<FMT>::T)(-ldexpf(L[off(i, k, ld)], s));
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e % 64, q = e / 64;
+        tile[r][q] = (i0 + r < m && k0 + q < w) ? L[off(i0 + r, k0 + q, ld)] : 0.0f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int q = e % 64, r = e / 64;
+        if (i0 + r < m && k0 + q < w)
+            O[(size_t)(i0 + r) * (size_t)w + k0 + q] = (typename Half<FMT>::T)(-ldexpf(tile[r][q], s));
+    }
 }
 
 // U12 (w x n at ld) -> B16 column-major w x n (ld w): 2^-s u rounded
@@ -360,25 +402,48 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// refinement: r = b - A x (FP64, explicit A, j in order), and the maxima
-// |r_i|, |x_i|, |b_i| and (when anorm) sum_j |a_ij| into red[0..3] as bit
-// patterns of non-negative doubles.
+// refinement: r = b - A x (FP64, explicit A) in two passes, deterministic:
+//   1. workgroup (row block, column chunk q) writes the partial sums
+//      P[q][i] = sum_{j in chunk q} a_ij x_j (FMA chain, j in order) and, on
+//      the first pass, PA[q][i] = sum_{j in chunk q} |a_ij|;
+//   2. one thread per row adds the kResSplit partials in q order, writes
+//      r_i = b_i - sum, and the maxima |r_i|, |x_i|, |b_i|, sum_j |a_ij| go to
+//      red[0..3] as bit patterns of non-negative doubles.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void mxp_residual_kernel(const double *__restrict__ A, int64_t lda,
-                                                           const double *__restrict__ x,
-                                                           const double *__restrict__ b, double *__restrict__ r,
-                                                           int64_t n, int anorm,
-                                                           unsigned long long *__restrict__ red)
+__global__ __launch_bounds__(256) void mxp_resid_partial_kernel(const double *__restrict__ A, int64_t lda,
+                                                                const double *__restrict__ x, int64_t n,
+                                                                int64_t chunk, int anorm, double *__restrict__ P,
+                                                                double *__restrict__ PA)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int q = blockIdx.y;
+    if (i >= n) return;
+    const int64_t j0 = (int64_t)q * chunk, j1 = (j0 + chunk) < n ? (j0 + chunk) : n;
+    double s = 0.0, sa = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        const double a = A[off(i, j, lda)];
+        s = __fma_rn(a, x[j], s);
+        if (anorm) sa += fabs(a);
+    }
+    P[(size_t)q * (size_t)n + i] = s;
+    if (anorm) PA[(size_t)q * (size_t)n + i] = sa;
+}
+
+__global__ __launch_bounds__(256) void mxp_resid_final_kernel(const double *__restrict__ P,
+                                                              const double *__restrict__ PA, int nsplit,
+                                                              const double *__restrict__ x,
+                                                              const double *__restrict__ b, double *__restrict__ r,
+                                                              int64_t n, int anorm,
+                                                              unsigned long long *__restrict__ red)
 {
     __shared__ double sh[4][4];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double vr = 0.0, vx = 0.0, vb = 0.0, va = 0.0;
     if (i < n) {
         double s = 0.0, sa = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            const double a = A[off(i, j, lda)];
-            s = __fma_rn(a, x[j], s);
-            if (anorm) sa += fabs(a);
+        for (int q = 0; q < nsplit; ++q) {
+            s += P[(size_t)q * (size_t)n + i];
+            if (anorm) sa += PA[(size_t)q * (size_t)n + i];
         }
         const double ri = b[i] - s;
         r[i] = ri;
@@ -397,8 +462,8 @@ __global__ __launch_bounds__(256) void mxp_residual_kernel(const double *__restr
     __syncthreads();
     if (threadIdx.x < 4) {
         const int q = threadIdx.x;
-        const double m = fmax(fmax(sh[0][q], sh[1][q]), fmax(sh[2][q], sh[3][q]));
-        atomicMax(red + q, (unsigned long long)__double_as_longlong(m));
+        const double mm = fmax(fmax(sh[0][q], sh[1][q]), fmax(sh[2][q], sh[3][q]));
+        atomicMax(red + q, (unsigned long long)__double_as_longlong(mm));
     }
 }
 
@@ -472,12 +537,11 @@ int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int
                      unsigned *mx, int *sexp, hipStream_t st)
 {
     HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)mx, 1, 0ull, st));
-    const unsigned gyl = (unsigned)(w < 65535 ? w : 65535);
-    hipLaunchKernelGGL(maxabs32_kernel, dim3((unsigned)blocks_of(m, 256), gyl), dim3(256), 0, st, L, ldl, m,
+    const int64_t gl = blocks_of(m * w, 256 * 16), gu = blocks_of((int64_t)w * ncols, 256 * 16);
+    hipLaunchKernelGGL(maxabs32_kernel, dim3((unsigned)(gl < 2048 ? gl : 2048)), dim3(256), 0, st, L, ldl, m,
                        (int64_t)w, mx);
     HPLX_TRY_LAUNCH();
-    const unsigned gyu = (unsigned)(ncols < 65535 ? ncols : 65535);
-    hipLaunchKernelGGL(maxabs32_kernel, dim3((unsigned)blocks_of(w, 256), gyu), dim3(256), 0, st, U, ldu,
+    hipLaunchKernelGGL(maxabs32_kernel, dim3((unsigned)(gu < 2048 ? gu : 2048)), dim3(256), 0, st, U, ldu,
                        (int64_t)w, ncols, mx + 1);
     HPLX_TRY_LAUNCH();
     hipLaunchKernelGGL(scale_exp_kernel, dim3(1), dim3(1), 0, st, mx, sexp);
@@ -488,16 +552,17 @@ int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int
 int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols,
                        int w, const int *sexp, void *A16, void *B16, hipStream_t st)
 {
-    const int64_t gl = blocks_of(m, 256), gu = blocks_of((int64_t)w * ncols, 256);
-    if (gu > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    const int64_t gl = blocks_of(m, 64), gk = blocks_of(w, 64), gu = blocks_of((int64_t)w * ncols, 256);
+    if (gu > 0x7fffffffll || gl > 0x7fffffffll) return HPL_ERR_INTERNAL;
     if (fmt == 0) {
-        hipLaunchKernelGGL(cvt_l_kernel<0>, dim3((unsigned)gl), dim3(256), 0, st, L, ldl, m, w, sexp,
+        hipLaunchKernelGGL(cvt_l_kernel<0>, dim3((unsigned)gl, (unsigned)gk), dim3(256), 0, st, L, ldl, m, w, sexp,
                            (_Float16 *)A16);
         HPLX_TRY_LAUNCH();
         hipLaunchKernelGGL(cvt_u_kernel<0>, dim3((unsigned)gu), dim3(256), 0, st, U, ldu, w, ncols, sexp,
                            (_Float16 *)B16);
     } else {
-        hipLaunchKernelGGL(cvt_l_kernel<1>, dim3((unsigned)gl), dim3(256), 0, st, L, ldl, m, w, sexp, (__bf16 *)A16);
+        hipLaunchKernelGGL(cvt_l_kernel<1>, dim3((unsigned)gl, (unsigned)gk), dim3(256), 0, st, L, ldl, m, w, sexp,
+                           (__bf16 *)A16);
         HPLX_TRY_LAUNCH();
         hipLaunchKernelGGL(cvt_u_kernel<1>, dim3((unsigned)gu), dim3(256), 0, st, U, ldu, w, ncols, sexp,
                            (__bf16 *)B16);
@@ -525,11 +590,16 @@ int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A1
 }
 
 int launch_mxp_residual(const double *A, int64_t lda, const double *x, const double *b, double *r, int64_t n,
-                        bool anorm, unsigned long long *red, hipStream_t st)
+                        bool anorm, double *part, unsigned long long *red, hipStream_t st)
 {
     if (n <= 0) return HPL_OK;
-    hipLaunchKernelGGL(mxp_residual_kernel, dim3((unsigned)blocks_of(n, 256)), dim3(256), 0, st, A, lda, x, b, r, n,
-                       anorm ? 1 : 0, red);
+    const int64_t chunk = (n + kResSplit - 1) / kResSplit;
+    double *P = part, *PA = part + (size_t)kResSplit * (size_t)n;
+    hipLaunchKernelGGL(mxp_resid_partial_kernel, dim3((unsigned)blocks_of(n, 256), kResSplit), dim3(256), 0, st, A,
+                       lda, x, n, chunk, anorm ? 1 : 0, P, PA);
+    HPLX_TRY_LAUNCH();
+    hipLaunchKernelGGL(mxp_resid_final_kernel, dim3((unsigned)blocks_of(n, 256)), dim3(256), 0, st, P, PA, kResSplit,
+                       x, b, r, n, anorm ? 1 : 0, red);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }

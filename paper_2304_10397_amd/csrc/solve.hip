@@ -41,10 +41,21 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const TT *__res
     constexpr bool unit = (mode == 0 || mode == 3);
     constexpr bool tr = (mode >= 2);
 
-    // ---- 1. diagonal block: stage it (coalesced), then one wave per right-hand side
-    for (int e = t; e < kBs * kBs; e += kSvThreads) {
-        const int r = e % kBs, c = e / kBs;
-        Td[r][c] = (r < bs && c < bs) ? (double)T[off(r0 + r, r0 + c, ldt)] : (r == c ? 1.0 : 0.0);
+    // ---- 1. diagonal block: stage it (coalesced; all loads issued before the
+    //      first LDS store, so the staging costs one memory round trip), then
+    //      one wave per right-hand side
+    constexpr int kStage = kBs * kBs / kSvThreads;
+    static_assert(kBs * kBs % kSvThreads == 0, "staging must divide evenly");
+    double sv[kStage];
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+        const int e = t + q * kSvThreads, r = e % kBs, c = e / kBs;
+        sv[q] = (r < bs && c < bs) ? (double)T[off(r0 + r, r0 + c, ldt)] : (r == c ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+        const int e = t + q * kSvThreads;
+        Td[e % kBs][e / kBs] = sv[q];
     }
     __syncthreads();
     for (int64_t c = wid; c < nrhs; c += kSvThreads / 64) {
