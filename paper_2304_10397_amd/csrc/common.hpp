@@ -23,6 +23,17 @@ __host__ __device__ __forceinline__ size_t off(int64_t i, int64_t j, int64_t ld)
 
 // Value of v held by lane l of the wave (l uniform across the wave): two
 // v_readlane_b32, a few cycles, instead of an LDS round trip.
+// p[0] when ok, else z, with the load issued unconditionally (from p, or from
+// the always-valid address safe): a guarded load written as "ok ? p[0] : z"
+// is compiled to a branch around the load followed by a wait for it, so a
+// run of such loads costs one memory round trip each; these do not.
+template <typename T>
+__device__ __forceinline__ T load_or(bool ok, const T *p, const T *safe, T z)
+{
+    const T v = *(ok ? p : safe);
+    return ok ? v : z;
+}
+
 // Block index -> output tile (tm, tn) of a tiles_m x tiles_n grid.  Workgroups
 // are dispatched round-robin over the 8 XCDs, each with its own L2: the index
 // is remapped so that each XCD receives a contiguous run of tiles, and the run

@@ -128,8 +128,8 @@ __global__ __launch_bounds__(kLwThreads) void laswp_kernel(double *__restrict__ 
     for (int s = threadIdx.x; s < ns; s += kLwThreads) {
         const int64_t r = rows[s];
 #pragma unroll
-        for (int c = 0; c < kLwCols; ++c)
-            if (c < nc) vals[s][c] = A[off(r, cb + c, lda)];
+        for (int c = 0; c < kLwCols; ++c)  // entries past nc are never written back
+            vals[s][c] = load_or(c < nc, A + off(r, cb + c, lda), A + off(r, cb, lda), 0.0);
     }
     __syncthreads();
     for (int s = threadIdx.x; s < ns; s += kLwThreads) {

@@ -217,12 +217,21 @@ __global__ __launch_bounds__(256) void sgemm32_kernel(int64_t m, int64_t n, int6
         }
         __syncthreads();
     }
+    // every C value is loaded (from clamped indexes) before the first store
+    float cv[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t i = m0 + tx + 16 * u, j = n0 + ty + 16 * v;
-            if (i < m && j < n) C[off(i, j, ldc)] -= acc[u][v];
+            cv[u][v] = C[off(i < m ? i : m - 1, j < n ? j : n - 1, ldc)];
+        }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t i = m0 + tx + 16 * u, j = n0 + ty + 16 * v;
+            if (i < m && j < n) C[off(i, j, ldc)] = cv[u][v] - acc[u][v];
         }
 }
 

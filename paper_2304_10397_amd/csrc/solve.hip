@@ -50,7 +50,9 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const TT *__res
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
         const int e = t + q * kSvThreads, r = e % kBs, c = e / kBs;
-        sv[q] = (r < bs && c < bs) ? (double)T[off(r0 + r, r0 + c, ldt)] : (r == c ? 1.0 : 0.0);
+        const bool in = r < bs && c < bs;
+        const double v = (double)load_or(in, T + off(r0 + r, r0 + c, ldt), T + off(r0, r0, ldt), (TT)0);
+        sv[q] = in ? v : (r == c ? 1.0 : 0.0);
     }
 #pragma unroll
     for (int q = 0; q < kStage; ++q) {
@@ -88,11 +90,11 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const TT *__res
     if (mode < 2) {
         const TT *base = T + off(i, r0, ldt);  // T_op(i, r0 + k) = T(i, r0 + k)
 #pragma unroll
-        for (int k = 0; k < kBs; ++k) a[k] = (k < bs) ? (double)base[(size_t)k * (size_t)ldt] : 0.0;
+        for (int k = 0; k < kBs; ++k) a[k] = (double)load_or(k < bs, base + (size_t)k * (size_t)ldt, base, (TT)0);
     } else {
         const TT *base = T + off(r0, i, ldt);  // T_op(i, r0 + k) = T(r0 + k, i)
 #pragma unroll
-        for (int k = 0; k < kBs; ++k) a[k] = (k < bs) ? (double)base[k] : 0.0;
+        for (int k = 0; k < kBs; ++k) a[k] = (double)load_or(k < bs, base + k, base, (TT)0);
     }
     for (int64_t c = 0; c < nrhs; ++c) {
         const double *y = Y + c * kBs;

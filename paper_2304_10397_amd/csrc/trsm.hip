@@ -52,7 +52,11 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
 #pragma unroll
         for (int J = 0; J < kTrCG; ++J) {
             const int cc = 4 * J + (lane & 3);
-            acc[q][J] = (rb < nrb && rr < nbk && cc < crem) ? B[off(rr, c0 + cc, ldb)] : 0.0;
+            // unconditional load from clamped (always valid) indexes, then the mask
+            const int rc = rr < nbk ? rr : nbk - 1;
+            const int64_t ccc = cc < crem ? cc : crem - 1;
+            const double v = B[off(rc, c0 + ccc, ldb)];
+            acc[q][J] = (rb < nrb && rr < nbk && cc < crem) ? v : 0.0;
         }
     }
 
@@ -60,14 +64,15 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
     // issued, so their latency hides behind the next step's publish, barrier
     // and substitution: the diagonal block of L (one
     // element per thread of the upper half of the workgroup) and this wave's A
-    // fragments (-L[rb, i], 4 k-steps per row block).
+    // fragments (L[rb, i], 4 k-steps per row block, negated at use).
     double lsp = 0.0;
     double afr[kTrQ][4];
     auto fetch = [&](int i, double &ls, double (&af)[kTrQ][4]) {
         if (t >= 256) {
             const int e = t - 256, r = e & 15, c = e >> 4;
             const int gr = 16 * i + r, gc = 16 * i + c;
-            ls = (i < nrb && gr < nbk && gc < nbk) ? L[off(gr, gc, ldl)] : 0.0;
+            const double v = L[off(gr < nbk ? gr : nbk - 1, gc < nbk ? gc : nbk - 1, ldl)];
+            ls = (i < nrb && gr < nbk && gc < nbk) ? v : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < kTrQ; ++q) {
@@ -76,7 +81,11 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
                 const int kc = 4 * k4 + (lane >> 4);
-                af[q][k4] = (rb > i && rb < nrb && lr < nbk) ? -L[off(lr, 16 * i + kc, ldl)] : 0.0;
+                // raw L value, loaded unconditionally from clamped indexes
+                // (in range wherever the fragment is used); the sign and the
+                // row mask are applied at the MFMA
+                const int lc = 16 * i + kc;
+                af[q][k4] = L[off(lr < nbk ? lr : nbk - 1, lc < nbk ? lc : nbk - 1, ldl)];
             }
         }
     };
@@ -123,13 +132,15 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
         for (int q = 0; q < kTrQ; ++q) {
             const int rb = wave + kTrWaves * q;
             if (rb > i && rb < nrb) {
+                const bool row_ok = 16 * rb + (lane & 15) < nbk;
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
                     const int kc = 4 * k4 + (lane >> 4);
+                    const double a = row_ok ? -afr[q][k4] : 0.0;  // -L[rb, i] fragment
 #pragma unroll
                     for (int J = 0; J < kTrCG; ++J) {
                         const double b = Xs[par][kc][4 * J + (lane & 3)];
-                        acc[q][J] = __builtin_amdgcn_mfma_f64_4x4x4f64(afr[q][k4], b, acc[q][J], 0, 0, 0);
+                        acc[q][J] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, acc[q][J], 0, 0, 0);
                     }
                     __builtin_amdgcn_sched_barrier(0);  // bound the B fragments kept live
                 }
