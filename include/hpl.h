@@ -189,7 +189,7 @@ int hpl_mxp_generate(uint64_t seed, double *A, int64_t n, int64_t lda, void *hip
  *   on v_mfma_f32_16x16x32_{f16,bf16}.
  *   1 A    device FP64 n x n at lda (input, not modified)
  *   2 n    0 <= n < 2^31;  3 lda >= max(1, n)
- *   4 nb   panel width, a multiple of 64 in [64, 1024]
+ *   4 nb   panel width, a multiple of 64 in [64, 4096]
  *   5 fmt  0 = FP16, 1 = BF16
  *   6 LU   device FP32 n x n at ldlu (written: unit-lower L below the
  *          diagonal, U on and above it)
@@ -244,7 +244,7 @@ int64_t hpl_get_option(int key);
  * arrays describes class k: 0 trailing GEMM, 1 panel (recursive FACT, all of
  * its kernels), 2 laswp, 3 trsm, 4 solve, 5 interchange plans, 6 the mixed-
  * precision trailing update, 7 the rest of a mixed-precision panel step
- * (FACT, U12, scaling and conversion).  For each
+ * (FACT, U12, scaling and conversion), 8 hpl_solve_grad_a.  For each
  * class: launches[k], total device milliseconds ms[k] (sum of HIP-event
  * intervals around each launch on the stream it ran on) and algorithmic
  * flops[k] and bytes[k] (the method's own operation and HBM byte counts).

@@ -70,7 +70,7 @@ static std::atomic<int64_t> opt_gemm_tile{0};
 // statistics (HPL_OPT_TIMING)
 // ---------------------------------------------------------------------------
 enum { ST_GEMM = 0, ST_PANEL = 1, ST_LASWP = 2, ST_TRSM = 3, ST_SOLVE = 4, ST_PLAN = 5, ST_MXP_GEMM = 6,
-       ST_MXP_FACT = 7, ST_N = 8 };
+       ST_MXP_FACT = 7, ST_GRAD_A = 8, ST_N = 9 };
 static std::mutex g_st_mu;
 static int64_t g_st_launch[ST_N];
 static double g_st_ms[ST_N], g_st_flops[ST_N], g_st_bytes[ST_N];
@@ -863,9 +863,13 @@ int hpl_solve_grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ld
     Device *d = nullptr;
     HPLX_PROPAGATE(get_device(&d));
     hipStream_t st = (hipStream_t)hip_stream;
+    Timer tm(d, opt_timing.load() != 0);
+    const int id = tm.begin(ST_GRAD_A, st);
     HPLX_PROPAGATE(launch_grad_a(GB, ldgb, X, ldx, n, nrhs, dA, ldda, st));
+    HPLX_PROPAGATE(tm.end(id, st, 2.0 * (double)n * (double)n * (double)nrhs,
+                          8.0 * (double)n * (double)n + 16.0 * (double)n * (double)nrhs));
     HPLX_TRY(hipStreamSynchronize(st));
-    return HPL_OK;
+    return tm.collect();
 }
 
 int hpl_mxp_generate(uint64_t seed, double *A, int64_t n, int64_t lda, void *hip_stream)
@@ -889,7 +893,7 @@ int hpl_mxp_factor(const double *A, int64_t n, int64_t lda, int64_t nb, int fmt,
     if (n > 0 && A == nullptr) return -1;
     if (n < 0 || n > 0x7fffffffll) return -2;
     if (lda < (n > 1 ? n : 1)) return -3;
-    if (nb < 64 || nb > 1024 || nb % 64 != 0) return -4;
+    if (nb < 64 || nb > 4096 || nb % 64 != 0) return -4;
     if (fmt != 0 && fmt != 1) return -5;
     if (n > 0 && LU == nullptr) return -6;
     if (ldlu < (n > 1 ? n : 1)) return -7;

@@ -97,6 +97,8 @@ def test_mxp_argument_errors():
     assert L.hpl_mxp_factor(FAKE, -1, 4, 64, 0, FAKE, 4, ctypes.byref(info), None) == -2
     assert L.hpl_mxp_factor(FAKE, 4, 3, 64, 0, FAKE, 4, ctypes.byref(info), None) == -3
     assert L.hpl_mxp_factor(FAKE, 4, 4, 96, 0, FAKE, 4, ctypes.byref(info), None) == -4
+    assert L.hpl_mxp_factor(FAKE, 4, 4, 4160, 0, FAKE, 4, ctypes.byref(info), None) == -4
+    assert L.hpl_mxp_factor(FAKE, 4, 4, 0, 0, FAKE, 4, ctypes.byref(info), None) == -4
     assert L.hpl_mxp_factor(FAKE, 4, 4, 64, 2, FAKE, 4, ctypes.byref(info), None) == -5
     assert L.hpl_mxp_factor(FAKE, 4, 4, 64, 1, None, 4, ctypes.byref(info), None) == -6
     assert L.hpl_mxp_factor(FAKE, 4, 4, 64, 1, FAKE, 2, ctypes.byref(info), None) == -7

@@ -34,7 +34,7 @@ def dyadic_lu(n, seed):
     return np.asfortranarray(L @ U), L, U
 
 
-@pytest.mark.parametrize("n,nb", [(64, 64), (200, 64), (300, 128), (517, 256)])
+@pytest.mark.parametrize("n,nb", [(64, 64), (200, 64), (300, 128), (517, 256), (2100, 2048)])
 @pytest.mark.parametrize("fmt", [0, 1])
 def test_mxp_factor_dyadic_exact(n, nb, fmt):
     h = hpl()
