@@ -239,12 +239,56 @@ int hpl_set_option(int key, int64_t value);
 int64_t hpl_get_option(int key);
 
 /*
+ * hpl_batched_sizes -- the sizes of a seeded batch of systems (host only):
+ * n_i = nmin + min(floor(u_i (nmax - nmin + 1)), nmax - nmin) with
+ * u_i = value(seed, stream 3, i) + 1/2 in [0, 1), the generator of
+ * hpl_generate.
+ *   1 seed; 2 count >= 0; 3 nmin >= 1; 4 nmax >= nmin
+ *   5 sizes  host int32[count] (written)
+ */
+int hpl_batched_sizes(uint64_t seed, int64_t count, int32_t nmin, int32_t nmax, int32_t *sizes);
+
+/*
+ * hpl_batched_solve -- count independent systems A_i X_i = B_i (the method of
+ * Sec. II -- LU with partial pivoting, then the triangular solves -- applied
+ * to each small system) and, optionally, the adjoint of the solve for a loss
+ * whose gradient with respect to X_i is W_i: grad_B_i = A_i^{-T} W_i,
+ * grad_A_i = -grad_B_i X_i^T.  ONE persistent launch for the whole batch,
+ * systems taken largest first from a device-side queue.
+ * Packed layout (all column-major with leading dimension n_i, device memory):
+ * A_i at offset sum_{j<i} n_j^2 (elements); B_i, W_i, grad_B_i at
+ * nrhs * sum_{j<i} n_j; ipiv_i at sum_{j<i} n_j (0-based within the system,
+ * sequential interchanges, L in LAPACK form: P A = L U); grad_A_i like A_i.
+ *   1 count >= 0
+ *   2 sizes  host int32[count], 1 <= n_i <= 512
+ *   3 nrhs   1 <= nrhs <= 16
+ *   4 A      mode & 1: the systems, overwritten by their LU factors;
+ *            mode == 2: the LU factors (input)
+ *   5 ipiv   device int32[sum n_i]: written (mode & 1) or read (mode == 2)
+ *   6 B      mode & 1: the right-hand sides, overwritten by X;
+ *            mode == 2: X (input)
+ *   7 W      mode & 2: device, layout of B (input)
+ *   8 GB     mode & 2: device, layout of B (written: grad_B)
+ *   9 GA     mode & 2: device, layout of A (written: grad_A)
+ *  10 mode   1 = factor + solve, 2 = adjoint from stored factors and X,
+ *            3 = both in the same launch
+ *  11 info   host int64[count]: 0, or k+1 for the first exactly-zero pivot
+ *            column of system i (that column is left unscaled)
+ *  12 hip_stream
+ * Workspace: 32 bytes per system (offsets, order, info), kept per device.
+ * Every grid wave exits once the queue passes the batch size.
+ */
+int hpl_batched_solve(int64_t count, const int32_t *sizes, int64_t nrhs, double *A, int32_t *ipiv, double *B,
+                      const double *W, double *GB, double *GA, int mode, int64_t *info, void *hip_stream);
+
+/*
  * Per-kernel-class statistics of the calls made since the last
  * hpl_reset_stats, collected while HPL_OPT_TIMING is 1.  Entry k of the
  * arrays describes class k: 0 trailing GEMM, 1 panel (recursive FACT, all of
  * its kernels), 2 laswp, 3 trsm, 4 solve, 5 interchange plans, 6 the mixed-
  * precision trailing update, 7 the rest of a mixed-precision panel step
- * (FACT, U12, scaling and conversion), 8 hpl_solve_grad_a.  For each
+ * (FACT, U12, scaling and conversion), 8 hpl_solve_grad_a, 9
+ * hpl_batched_solve.  For each
  * class: launches[k], total device milliseconds ms[k] (sum of HIP-event
  * intervals around each launch on the stream it ran on) and algorithmic
  * flops[k] and bytes[k] (the method's own operation and HBM byte counts).

@@ -68,15 +68,15 @@ def _ptr(a):
 
 def _ld(a):
     """Leading dimension of a Fortran-ordered 2-D float64 array (or 1-D vector)."""
-    if a.ndim == 1 or a.size == 0:
-        return max(1, a.shape[0])
+    if a.ndim == 1 or a.size == 0 or a.shape[0] == 1:
+        return max(1, a.shape[0])   # one row: the row stride is never used
     assert a.strides[0] == a.itemsize, "matrix must be column-major (Fortran order)"
     return max(1, a.strides[1] // a.itemsize, a.shape[0])
 
 
 def _check(a, dtype=np.float64):
     assert isinstance(a, np.ndarray) and a.dtype == dtype
-    if a.ndim == 2 and a.size > 0:
+    if a.ndim == 2 and a.size > 0 and a.shape[0] > 1:
         assert a.strides[0] == a.itemsize, "matrix must be column-major (Fortran order)"
     return a
 
@@ -215,3 +215,69 @@ def lu_mxp(A: np.ndarray, nb: int, fmt: int):
     LU = np.zeros((max(n, 1), n), dtype=np.float32, order="F")
     info = lib().oracle_lu_mxp(_ptr(A), n, _ld(A), int(nb), int(fmt), _ptr(LU), max(n, 1))
     return LU[:n, :], int(info)
+
+
+# ---------------------------------------------------------------------------
+# Batches of independent small systems (packed column-major, leading dimension
+# n_i): A_i at sum_{j<i} n_j^2, B_i / W_i / X_i / grad_B_i at nrhs sum_{j<i} n_j.
+# ---------------------------------------------------------------------------
+BATCH_SIZE_STREAM = 3
+
+
+def batched_sizes(seed: int, count: int, nmin: int, nmax: int) -> np.ndarray:
+    """n_i = nmin + min(floor(u_i (nmax - nmin + 1)), nmax - nmin), u_i = value(seed, stream 3, i) + 1/2."""
+    v = gen(seed, BATCH_SIZE_STREAM, count, 1)[:, 0]
+    u = v + 0.5
+    rng = nmax - nmin + 1
+    k = np.minimum(np.floor(u * float(rng)), rng - 1).astype(np.int64)
+    return (nmin + k).astype(np.int32)
+
+
+def batch_offsets(sizes, nrhs):
+    sizes = np.asarray(sizes, dtype=np.int64)
+    aoff = np.concatenate([[0], np.cumsum(sizes * sizes)]).astype(np.int64)
+    voff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return aoff, voff
+
+
+def batch_system(sizes, packed, aoff, i):
+    """View of system i of a packed A-layout array as an n x n Fortran matrix."""
+    n = int(sizes[i])
+    return packed[aoff[i]:aoff[i] + n * n].reshape((n, n), order="F")
+
+
+def batch_rhs(sizes, packed, voff, nrhs, i):
+    n = int(sizes[i])
+    return packed[nrhs * voff[i]:nrhs * voff[i] + n * nrhs].reshape((n, nrhs), order="F")
+
+
+def batched_solve(sizes, A, B, nrhs, W=None):
+    """Per system: LU with partial pivoting, X = A^{-1} B and, with W, the adjoint
+    grad_B = A^{-T} W, grad_A = -grad_B X^T.  Inputs and outputs packed; returns
+    dict(LU, ipiv, X, GB, GA, info) (GB, GA None without W)."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    aoff, voff = batch_offsets(sizes, nrhs)
+    LU = np.array(A, dtype=np.float64, copy=True)
+    X = np.array(B, dtype=np.float64, copy=True)
+    ipiv = np.zeros(int(voff[-1]), dtype=np.int32)
+    GB = np.zeros_like(X) if W is not None else None
+    GA = np.zeros_like(LU) if W is not None else None
+    info = np.zeros(sizes.size, dtype=np.int64)
+    for i in range(sizes.size):
+        n = int(sizes[i])
+        Ai = np.asfortranarray(batch_system(sizes, np.asarray(A, dtype=np.float64), aoff, i))
+        F = Ai.copy(order="F")
+        piv, inf = lu(F)
+        info[i] = inf
+        LU[aoff[i]:aoff[i] + n * n] = F.reshape(-1, order="F")
+        ipiv[voff[i]:voff[i] + n] = piv
+        Bi = np.asfortranarray(batch_rhs(sizes, np.asarray(B, dtype=np.float64), voff, nrhs, i))
+        Xi = Bi.copy(order="F")
+        solve(F, piv, Xi)
+        X[nrhs * voff[i]:nrhs * voff[i] + n * nrhs] = Xi.reshape(-1, order="F")
+        if W is not None:
+            Wi = np.asfortranarray(batch_rhs(sizes, np.asarray(W, dtype=np.float64), voff, nrhs, i))
+            _, gb, ga, _ = solve_grad(Ai, Bi, Wi)
+            GB[nrhs * voff[i]:nrhs * voff[i] + n * nrhs] = gb.reshape(-1, order="F")
+            GA[aoff[i]:aoff[i] + n * n] = ga.reshape(-1, order="F")
+    return {"LU": LU, "ipiv": ipiv, "X": X, "GB": GB, "GA": GA, "info": info}

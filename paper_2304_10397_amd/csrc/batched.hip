@@ -1,0 +1,566 @@
+// batched.hip -- many independent small dense systems A_i X_i = B_i (n_i <= 512)
+// in ONE persistent launch: LU with partial pivoting (the method of Sec. II
+// applied to each system: panel FACT, interchanges, U12 = L11^{-1} A12, rank-NB
+// trailing update), the solve, and optionally the adjoint of the solve
+// (grad_B = A^{-T} W, grad_A = -grad_B X^T) for a loss whose gradient with
+// respect to X is W.
+//
+// Layout (all packed, column-major, leading dimension n_i): A_i at
+// aoff_i = sum_{j<i} n_j^2; B_i, X_i, W_i and grad_B_i at nrhs * voff_i, with
+// voff_i = sum_{j<i} n_j; ipiv_i at voff_i (0-based within the system,
+// sequential-interchange semantics, LAPACK form of L: P A = L U).
+//
+// Scheduling: 256 persistent workgroups of 512 threads (one per CU; 8 waves,
+// 2 per SIMD); each takes the next system from an atomic counter over a
+// largest-first order, so the n^3-heavy systems start first and the small
+// ones fill the tail.  A system's matrix stays in global memory (L2 / MALL
+// resident at these sizes); per 32-column panel step:
+//   1. FACT: thread t holds row k0+t of the panel in registers; per column one
+//      barrier: each wave publishes its best candidate (|a|, row) and that
+//      row's values in LDS (double-buffered by column parity), the diagonal
+//      row is published too, and every thread then knows the pivot row and
+//      performs the interchange and the rank-1 update of its own row.
+//   2. The 32 interchanges are composed (by thread 0, during FACT) into one
+//      permutation of the <= 64 rows they touch; every other column (left:
+//      LAPACK-form L; right: U12 and the trailing columns; the right-hand
+//      sides, carried as extra columns so that B becomes L^{-1} P B as in
+//      HPL's augmented system) is permuted with one burst of loads, and the
+//      right columns' top 32 rows are solved with the unit-lower L11 (LDS).
+//   3. Trailing update C -= L21 U12 over rows [k0+32, n) and columns
+//      [k0+32, n+nrhs): 8 x 4 register tiles, L21 and U12 staged through LDS
+//      16 k at a time; the product is accumulated from zero in k order and
+//      then subtracted from C.  FP64 FMA on the VALU: on this chip the FP64
+//      vector and matrix peaks are equal, and the VALU form needs no
+//      16-alignment at these small, ragged sizes.
+// Then U X = Y by 32-row blocks from the bottom.  The adjoint: U^T z = W by
+// blocks from the top, L^T v = z from the bottom, grad_B = P^T v (a scatter
+// through the row permutation tracked during FACT), grad_A = -grad_B X^T.
+// Every wave of every workgroup reaches the queue's exit test, so the grid
+// drains when the counter passes the batch size.
+#include "common.hpp"
+
+namespace hplx {
+
+namespace {
+
+constexpr int kBT = 512;               // threads per workgroup
+constexpr int kBW = kBT / 64;          // waves
+constexpr int kPB = 32;                // panel width
+constexpr int kKC = 16;                // k per LDS stage of the trailing update
+constexpr int kTM = 8, kTN = 4;        // register tile of the trailing update (rows x columns)
+constexpr int kMaxColGroups = 64;      // <= 256 columns per update chunk
+constexpr int kMaxSlots = 2 * kPB;     // rows touched by one panel's interchanges
+
+struct BatchArgs {
+    int64_t count;
+    const int32_t *sizes;  // [count]
+    const int64_t *aoff;   // [count] element offset of A_i
+    const int64_t *voff;   // [count] sum of the preceding sizes
+    const int32_t *order;  // [count] processing order (largest first)
+    double *A;
+    int32_t *ipiv;
+    double *B;
+    const double *W;
+    double *GB;
+    double *GA;
+    int nrhs;
+    int mode;              // bit 0: factor + solve; bit 1: adjoint
+    int64_t *info;         // [count]
+    unsigned *counter;     // zero before the launch
+};
+
+struct BatchShared {
+    double Lc[kKC][kBatchMaxN];            // L21 stage [k][row]; also the right-hand-side stage
+    double Uc[kKC][kTN * kMaxColGroups];   // U12 stage [k][column]
+    double T[kPB][kPB + 1];                // diagonal block (L11, or a block of U / L for the solves)
+    double prow[2][kBW][kPB];              // per-wave candidate rows
+    double drow[2][kPB];                   // the diagonal row
+    double pv[2][kBW];                     // per-wave candidate |a|
+    int pr[2][kBW];                        // per-wave candidate row (-1: none)
+    double Ys[kBatchMaxRhs][kPB];          // solved block of the solves
+    int perm[kBatchMaxN];                  // row permutation: row i of P A is row perm[i] of A
+    int slot_row[kMaxSlots];               // interchange composition: destination rows ...
+    int slot_src[kMaxSlots];               // ... and the original row each receives
+    int nslots;
+    int64_t info;
+    int64_t job;
+};
+
+__device__ __forceinline__ double *col_ptr(double *a, double *b, int n, int c)
+{
+    return c < n ? a + (size_t)c * (size_t)n : b + (size_t)(c - n) * (size_t)n;
+}
+
+// slot of row r in the composition list (appending it if new); thread 0 only
+__device__ __forceinline__ int slot_of(BatchShared &sh, int k0, int r)
+{
+    if (r < k0 + kPB) return r - k0;
+    for (int s = kPB; s < sh.nslots; ++s)
+        if (sh.slot_row[s] == r) return s;
+    const int s = sh.nslots++;
+    sh.slot_row[s] = r;
+    sh.slot_src[s] = r;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// forward: LU with partial pivoting of the augmented [A | B], then U X = Y
+// ---------------------------------------------------------------------------
+__device__ void batch_forward(BatchShared &sh, double *a, double *b, int32_t *ip, int n, int nrhs)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int ncol = n + nrhs;
+    for (int i = t; i < n; i += kBT) sh.perm[i] = i;
+    if (t == 0) sh.info = 0;
+    __syncthreads();
+
+    for (int k0 = 0; k0 < n; k0 += kPB) {
+        const int w = (n - k0) < kPB ? (n - k0) : kPB;
+        const int r = k0 + t;
+        const bool own = r < n;
+        if (t == 0) {
+            // slots 0..w-1 are the panel's rows; pivot rows below the panel
+            // are appended (only when w == kPB: otherwise every row is in it)
+            sh.nslots = w;
+            for (int s = 0; s < w; ++s) {
+                sh.slot_row[s] = k0 + s;
+                sh.slot_src[s] = k0 + s;
+            }
+        }
+        // ---- 1. FACT of columns [k0, k0+w): row k0+t in registers
+        double v[kPB];
+        {
+            const int rr = own ? r : n - 1;
+#pragma unroll
+            for (int j = 0; j < kPB; ++j) {
+                const int cj = (k0 + j) < n ? (k0 + j) : (n - 1);
+                const double x = a[(size_t)rr + (size_t)cj * (size_t)n];
+                v[j] = (own && j < w) ? x : 0.0;
+            }
+        }
+        __syncthreads();  // slot lists initialised
+#pragma unroll
+        for (int j = 0; j < kPB; ++j) {
+            if (j < w) {
+                const int par = j & 1;
+                // wave argmax of |v[j]| over rows >= k0+j (ties: lowest row)
+                double cv = (own && t >= j) ? fabs(v[j]) : -1.0;
+                int cr = (own && t >= j) ? r : 0x7fffffff;
+                for (int o = 32; o > 0; o >>= 1) {
+                    const double ov = __shfl_xor(cv, o, 64);
+                    const int orr = __shfl_xor(cr, o, 64);
+                    if (ov > cv || (ov == cv && orr < cr)) {
+                        cv = ov;
+                        cr = orr;
+                    }
+                }
+                if (lane == 0) {
+                    sh.pv[par][wave] = cv;
+                    sh.pr[par][wave] = cv >= 0.0 ? cr : -1;
+                }
+                if (own && r == cr && cv >= 0.0) {
+#pragma unroll
+                    for (int q = 0; q < kPB; ++q) sh.prow[par][wave][q] = v[q];
+                }
+                if (r == k0 + j) {
+#pragma unroll
+                    for (int q = 0; q < kPB; ++q) sh.drow[par][q] = v[q];
+                }
+                __syncthreads();
+                double gv = -1.0;
+                int gp = 0x7fffffff, gw = 0;
+#pragma unroll
+                for (int q = 0; q < kBW; ++q) {
+                    const double qv = sh.pv[par][q];
+                    const int qr = sh.pr[par][q];
+                    if (qr >= 0 && (qv > gv || (qv == gv && qr < gp))) {
+                        gv = qv;
+                        gp = qr;
+                        gw = q;
+                    }
+                }
+                // no valid candidate (a NaN column): keep the diagonal row, so
+                // every row index stays inside the system
+                if (gp == 0x7fffffff) gp = k0 + j;
+                const double *u = (gp == k0 + j) ? sh.drow[par] : sh.prow[par][gw];
+                if (gp != k0 + j) {
+                    if (r == k0 + j) {
+#pragma unroll
+                        for (int q = 0; q < kPB; ++q) v[q] = u[q];
+                    } else if (r == gp) {
+#pragma unroll
+                        for (int q = 0; q < kPB; ++q) v[q] = sh.drow[par][q];
+                    }
+                }
+                if (t == 0) {
+                    ip[k0 + j] = gp;
+                    if (gp != k0 + j) {
+                        const int pk = sh.perm[k0 + j];
+                        sh.perm[k0 + j] = sh.perm[gp];
+                        sh.perm[gp] = pk;
+                        const int s1 = j, s2 = slot_of(sh, k0, gp);
+                        const int tmp = sh.slot_src[s1];
+                        sh.slot_src[s1] = sh.slot_src[s2];
+                        sh.slot_src[s2] = tmp;
+                    }
+                }
+                const double piv = u[j];
+                if (piv == 0.0) {
+                    if (t == 0 && sh.info == 0) sh.info = k0 + j + 1;  // column left unscaled
+                } else if (own && r > k0 + j) {
+                    const double l = v[j] / piv;
+                    v[j] = l;
+#pragma unroll
+                    for (int q = j + 1; q < kPB; ++q) v[q] = __fma_rn(-l, u[q], v[q]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);  // one column's LDS traffic at a time
+        }
+        // write the factored panel back; L11 to LDS
+        if (own) {
+#pragma unroll
+            for (int j = 0; j < kPB; ++j)
+                if (j < w) a[(size_t)r + (size_t)(k0 + j) * (size_t)n] = v[j];
+        }
+        if (t < w) {
+#pragma unroll
+            for (int j = 0; j < kPB; ++j) sh.T[t][j] = v[j];
+        }
+        __syncthreads();
+
+        // ---- 2. interchanges on every other column; U12 = L11^{-1} A12 on the right
+        const int nslots = sh.nslots;
+        const int nother = ncol - w;
+        for (int e = t; e < nother; e += kBT) {
+            const int c = e < k0 ? e : e + w;
+            double *cp = col_ptr(a, b, n, c);
+            // all sources are read before any row is written (a row may be
+            // both a source and a destination)
+            double x[kPB], xe[kPB];
+#pragma unroll
+            for (int s = 0; s < kPB; ++s) {
+                const int ss = s < nslots ? s : nslots - 1;
+                x[s] = cp[sh.slot_src[ss]];
+                const int se = kPB + s < nslots ? kPB + s : nslots - 1;
+                xe[s] = cp[sh.slot_src[se]];
+            }
+#pragma unroll
+            for (int s = 0; s < kPB; ++s)
+                if (kPB + s < nslots) cp[sh.slot_row[kPB + s]] = xe[s];
+            if (c >= k0 + w) {
+#pragma unroll
+                for (int i = 1; i < kPB; ++i) {
+                    if (i < w) {
+                        double acc = x[i];
+#pragma unroll
+                        for (int k = 0; k < i; ++k) acc = __fma_rn(-sh.T[i][k], x[k], acc);
+                        x[i] = acc;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);  // keep each row's LDS reads next to their use
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < kPB; ++s)
+                if (s < nslots) cp[sh.slot_row[s]] = x[s];
+        }
+        __syncthreads();
+
+        // ---- 3. trailing update C -= L21 U12
+        const int m = n - k0 - w, nc = ncol - k0 - w;
+        if (m > 0 && nc > 0) {
+            const int R = (m + kTM - 1) / kTM;
+            int G = kBT / R;
+            if (G > kMaxColGroups) G = kMaxColGroups;
+            const int CW = kTN * G;
+            const int tr = t / G, tc = t - (t / G) * G;
+            const bool act = tr < R;
+            for (int cc0 = 0; cc0 < nc; cc0 += CW) {
+                double acc[kTM][kTN];
+#pragma unroll
+                for (int i = 0; i < kTM; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < kTN; ++jj) acc[i][jj] = 0.0;
+                for (int kc = 0; kc < w; kc += kKC) {
+                    const int kw = (w - kc) < kKC ? (w - kc) : kKC;
+                    // stage L21[:, kc..kc+kw) as Lc[k][i] and U12[kc.., cc0..cc0+CW) as Uc[k][j]
+                    for (int e = t; e < kKC * m; e += kBT) {
+                        const int i = e % m, k = e / m;
+                        const int kk = k < kw ? k : kw - 1;
+                        const double x = a[(size_t)(k0 + w + i) + (size_t)(k0 + kc + kk) * (size_t)n];
+                        sh.Lc[k][i] = k < kw ? x : 0.0;
+                    }
+                    for (int e = t; e < kKC * CW; e += kBT) {
+                        const int k = e % kKC, j = e / kKC;
+                        const int kk = k < kw ? k : kw - 1;
+                        const int jc = (cc0 + j) < nc ? (cc0 + j) : (nc - 1);
+                        const double x = col_ptr(a, b, n, k0 + w + jc)[k0 + kc + kk];
+                        sh.Uc[k][j] = (k < kw && cc0 + j < nc) ? x : 0.0;
+                    }
+                    __syncthreads();
+                    if (act) {
+                        const int i0 = kTM * tr;
+#pragma unroll 4
+                        for (int k = 0; k < kKC; ++k) {
+                            double lv[kTM], uv[kTN];
+#pragma unroll
+                            for (int i = 0; i < kTM; ++i) lv[i] = sh.Lc[k][(i0 + i) < m ? (i0 + i) : (m - 1)];
+#pragma unroll
+                            for (int jj = 0; jj < kTN; ++jj) uv[jj] = sh.Uc[k][kTN * tc + jj];
+#pragma unroll
+                            for (int i = 0; i < kTM; ++i)
+#pragma unroll
+                                for (int jj = 0; jj < kTN; ++jj) acc[i][jj] = __fma_rn(lv[i], uv[jj], acc[i][jj]);
+                        }
+                    }
+                    __syncthreads();
+                }
+                if (act) {
+#pragma unroll
+                    for (int jj = 0; jj < kTN; ++jj) {
+                        const int j = cc0 + kTN * tc + jj;
+                        if (j < nc) {
+                            double *cp = col_ptr(a, b, n, k0 + w + j) + (k0 + w);
+                            double cv[kTM];
+#pragma unroll
+                            for (int i = 0; i < kTM; ++i) {
+                                const int ii = kTM * tr + i;
+                                cv[i] = cp[ii < m ? ii : m - 1];
+                            }
+#pragma unroll
+                            for (int i = 0; i < kTM; ++i)
+                                if (kTM * tr + i < m) cp[kTM * tr + i] = cv[i] - acc[i][jj];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- U X = Y, 32-row blocks from the bottom (Y = L^{-1} P B is in b)
+    const int nb0 = (n - 1) / kPB * kPB;
+    for (int r0 = nb0; r0 >= 0; r0 -= kPB) {
+        const int bw = (n - r0) < kPB ? (n - r0) : kPB;
+        for (int e = t; e < kPB * kPB; e += kBT) {
+            const int i = e % kPB, k = e / kPB;
+            const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
+            sh.T[i][k] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
+        }
+        __syncthreads();
+        for (int rh = wave; rh < nrhs; rh += kBW) {
+            double *bp = b + (size_t)rh * (size_t)n;
+            double y = bp[r0 + (lane < bw ? lane : bw - 1)];
+            for (int s = bw - 1; s >= 0; --s) {
+                const double xs = read_lane(y, s) / sh.T[s][s];
+                if (lane == s) y = xs;
+                if (lane < s) y = __fma_rn(-sh.T[lane][s], xs, y);
+            }
+            if (lane < bw) {
+                bp[r0 + lane] = y;
+                sh.Ys[rh][lane] = y;
+            }
+        }
+        __syncthreads();
+        for (int i = t; i < r0; i += kBT) {
+            double u[kPB];
+#pragma unroll
+            for (int k = 0; k < kPB; ++k) {
+                const int kc = k < bw ? k : bw - 1;
+                u[k] = a[(size_t)i + (size_t)(r0 + kc) * (size_t)n];
+            }
+            for (int rh = 0; rh < nrhs; ++rh) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < kPB; ++k)
+                    if (k < bw) acc = __fma_rn(u[k], sh.Ys[rh][k], acc);
+                double *bp = b + (size_t)rh * (size_t)n;
+                bp[i] = bp[i] - acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint: grad_B = A^{-T} W = P^T L^{-T} U^{-T} W, grad_A = -grad_B X^T
+// ---------------------------------------------------------------------------
+__device__ void batch_adjoint(BatchShared &sh, const double *a, const double *x, const double *wv, double *gb,
+                              double *ga, int n, int nrhs)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int e = t; e < n * nrhs; e += kBT) gb[e] = wv[e];
+    __syncthreads();
+    // U^T z = W: lower with diagonal u_ii, blocks from the top
+    for (int r0 = 0; r0 < n; r0 += kPB) {
+        const int bw = (n - r0) < kPB ? (n - r0) : kPB;
+        for (int e = t; e < kPB * kPB; e += kBT) {
+            const int i = e % kPB, k = e / kPB;
+            const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
+            sh.T[i][k] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
+        }
+        __syncthreads();
+        for (int rh = wave; rh < nrhs; rh += kBW) {
+            double *zp = gb + (size_t)rh * (size_t)n;
+            double y = zp[r0 + (lane < bw ? lane : bw - 1)];
+            for (int s = 0; s < bw; ++s) {
+                const double xs = read_lane(y, s) / sh.T[s][s];
+                if (lane == s) y = xs;
+                if (lane > s && lane < bw) y = __fma_rn(-sh.T[s][lane], xs, y);  // U^T(lane, s) = U(s, lane)
+            }
+            if (lane < bw) {
+                zp[r0 + lane] = y;
+                sh.Ys[rh][lane] = y;
+            }
+        }
+        __syncthreads();
+        for (int i = r0 + bw + t; i < n; i += kBT) {
+            double u[kPB];  // U(r0 + k, i): column i, contiguous
+#pragma unroll
+            for (int k = 0; k < kPB; ++k) u[k] = a[(size_t)(r0 + (k < bw ? k : bw - 1)) + (size_t)i * (size_t)n];
+            for (int rh = 0; rh < nrhs; ++rh) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < kPB; ++k)
+                    if (k < bw) acc = __fma_rn(u[k], sh.Ys[rh][k], acc);
+                double *zp = gb + (size_t)rh * (size_t)n;
+                zp[i] = zp[i] - acc;
+            }
+        }
+        __syncthreads();
+    }
+    // L^T v = z: unit upper, blocks from the bottom
+    const int nb0 = (n - 1) / kPB * kPB;
+    for (int r0 = nb0; r0 >= 0; r0 -= kPB) {
+        const int bw = (n - r0) < kPB ? (n - r0) : kPB;
+        for (int e = t; e < kPB * kPB; e += kBT) {
+            const int i = e % kPB, k = e / kPB;
+            const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
+            sh.T[i][k] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
+        }
+        __syncthreads();
+        for (int rh = wave; rh < nrhs; rh += kBW) {
+            double *zp = gb + (size_t)rh * (size_t)n;
+            double y = zp[r0 + (lane < bw ? lane : bw - 1)];
+            for (int s = bw - 1; s >= 0; --s) {
+                const double xs = read_lane(y, s);
+                if (lane < s) y = __fma_rn(-sh.T[s][lane], xs, y);  // L^T(lane, s) = L(s, lane)
+            }
+            if (lane < bw) {
+                zp[r0 + lane] = y;
+                sh.Ys[rh][lane] = y;
+            }
+        }
+        __syncthreads();
+        for (int i = t; i < r0; i += kBT) {
+            double l[kPB];  // L(r0 + k, i): column i, contiguous
+#pragma unroll
+            for (int k = 0; k < kPB; ++k) l[k] = a[(size_t)(r0 + (k < bw ? k : bw - 1)) + (size_t)i * (size_t)n];
+            for (int rh = 0; rh < nrhs; ++rh) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < kPB; ++k)
+                    if (k < bw) acc = __fma_rn(l[k], sh.Ys[rh][k], acc);
+                double *zp = gb + (size_t)rh * (size_t)n;
+                zp[i] = zp[i] - acc;
+            }
+        }
+        __syncthreads();
+    }
+    // grad_B = P^T v: entry perm[i] receives v_i (staged through LDS)
+    for (int rh = 0; rh < nrhs; rh += kKC) {
+        const int nr = (nrhs - rh) < kKC ? (nrhs - rh) : kKC;
+        for (int e = t; e < nr * n; e += kBT) {
+            const int i = e % n, q = e / n;
+            sh.Lc[q][i] = gb[(size_t)(rh + q) * (size_t)n + i];
+        }
+        __syncthreads();
+        for (int e = t; e < nr * n; e += kBT) {
+            const int i = e % n, q = e / n;
+            gb[(size_t)(rh + q) * (size_t)n + sh.perm[i]] = sh.Lc[q][i];
+        }
+        __syncthreads();
+    }
+    // grad_A = -grad_B X^T: thread per row i, X's rows from LDS, k = rhs order
+    for (int rh0 = 0; rh0 < nrhs; rh0 += kKC) {
+        // nrhs <= kBatchMaxRhs = kKC: a single pass
+        const int nr = (nrhs - rh0) < kKC ? (nrhs - rh0) : kKC;
+        for (int e = t; e < nr * n; e += kBT) {
+            const int j = e % n, q = e / n;
+            sh.Lc[q][j] = x[(size_t)(rh0 + q) * (size_t)n + j];
+        }
+        __syncthreads();
+        for (int i = t; i < n; i += kBT) {
+            double g[kKC];
+#pragma unroll
+            for (int q = 0; q < kKC; ++q) g[q] = gb[(size_t)(rh0 + (q < nr ? q : nr - 1)) * (size_t)n + i];
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < kKC; ++q)
+                    if (q < nr) s = __fma_rn(g[q], sh.Lc[q][j], s);
+                ga[(size_t)i + (size_t)j * (size_t)n] = 0.0 - s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBT) void batched_solve_kernel(BatchArgs p)
+{
+    __shared__ BatchShared sh;
+    const int t = threadIdx.x;
+    for (;;) {
+        if (t == 0) sh.job = (int64_t)atomicAdd(p.counter, 1u);
+        __syncthreads();
+        const int64_t job = sh.job;
+        __syncthreads();
+        if (job >= p.count) break;  // uniform: every wave leaves together
+        const int sys = p.order[job];
+        const int n = p.sizes[sys];
+        double *a = p.A + p.aoff[sys];
+        const int64_t vo = p.voff[sys];
+        double *b = p.B + (size_t)vo * (size_t)p.nrhs;
+        int32_t *ip = p.ipiv + vo;
+        if (p.mode & 1) {
+            batch_forward(sh, a, b, ip, n, p.nrhs);
+        } else {
+            // adjoint only: the row permutation from the stored interchanges
+            if (t == 0) {
+                sh.info = 0;
+                for (int i = 0; i < n; ++i) sh.perm[i] = i;
+                for (int k = 0; k < n; ++k) {
+                    const int q = ip[k];
+                    if (q != k && q >= 0 && q < n) {
+                        const int tmp = sh.perm[k];
+                        sh.perm[k] = sh.perm[q];
+                        sh.perm[q] = tmp;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (p.mode & 2)
+            batch_adjoint(sh, a, b, p.W + (size_t)vo * (size_t)p.nrhs, p.GB + (size_t)vo * (size_t)p.nrhs,
+                          p.GA + p.aoff[sys], n, p.nrhs);
+        if (t == 0) p.info[sys] = sh.info;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int launch_batched_solve(int64_t count, const int32_t *sizes, const int64_t *aoff, const int64_t *voff,
+                         const int32_t *order, double *A, int32_t *ipiv, double *B, const double *W, double *GB,
+                         double *GA, int nrhs, int mode, int64_t *info, unsigned *counter, int64_t nwg,
+                         hipStream_t st)
+{
+    if (count <= 0) return HPL_OK;
+    if (nrhs < 1 || nrhs > kBatchMaxRhs || mode < 1 || mode > 3 || nwg < 1) return HPL_ERR_INTERNAL;
+    BatchArgs p{count, sizes, aoff, voff, order, A, ipiv, B, W, GB, GA, nrhs, mode, info, counter};
+    const int64_t g = nwg < count ? nwg : count;
+    hipLaunchKernelGGL(batched_solve_kernel, dim3((unsigned)g), dim3(kBT), 0, st, p);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+}  // namespace hplx

@@ -127,6 +127,14 @@ int launch_residual(const double *A, int64_t lda, bool gen, uint64_t s0, int64_t
                     const double *X, int64_t ldx, const double *B, int64_t ldb, int64_t nrhs,
                     unsigned long long *red, hipStream_t st);
 int launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v, hipStream_t st);
+// batched small systems (one persistent launch)
+constexpr int kBatchMaxN = 512;
+constexpr int kBatchMaxRhs = 16;
+constexpr uint64_t kBatchSizeStream = 3;  // generator stream of the batch's sizes
+int launch_batched_solve(int64_t count, const int32_t *sizes, const int64_t *aoff, const int64_t *voff,
+                         const int32_t *order, double *A, int32_t *ipiv, double *B, const double *W, double *GB,
+                         double *GA, int nrhs, int mode, int64_t *info, unsigned *counter, int64_t nwg,
+                         hipStream_t st);
 
 // gemm.hip: C(m x n) -= A(m x k) * B(k x n).  variant: 0 auto, 1..4 tile shape;
 // OR kGemmTrailing for the trailing update (a separately named instance).

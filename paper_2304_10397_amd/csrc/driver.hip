@@ -20,6 +20,7 @@
 // and without look-ahead, so both give identical bits.
 #include "common.hpp"
 
+#include <algorithm>
 #include <atomic>
 #include <climits>
 #include <cmath>
@@ -70,7 +71,7 @@ static std::atomic<int64_t> opt_gemm_tile{0};
 // statistics (HPL_OPT_TIMING)
 // ---------------------------------------------------------------------------
 enum { ST_GEMM = 0, ST_PANEL = 1, ST_LASWP = 2, ST_TRSM = 3, ST_SOLVE = 4, ST_PLAN = 5, ST_MXP_GEMM = 6,
-       ST_MXP_FACT = 7, ST_GRAD_A = 8, ST_N = 9 };
+       ST_MXP_FACT = 7, ST_GRAD_A = 8, ST_BATCHED = 9, ST_N = 10 };
 static std::mutex g_st_mu;
 static int64_t g_st_launch[ST_N];
 static double g_st_ms[ST_N], g_st_flops[ST_N], g_st_bytes[ST_N];
@@ -131,6 +132,8 @@ struct Device {
     size_t mxp_cap = 0;
     double *mxp_vec = nullptr;            // refinement vectors r, d (2 n doubles)
     int64_t mxp_vec_cap = 0;
+    void *bat_ws = nullptr;               // batched systems: sizes, offsets, order, info, queue counter
+    size_t bat_cap = 0;
 };
 
 static std::mutex g_dev_mu;
@@ -1034,6 +1037,93 @@ int hpl_mfma_peak(int64_t iters, double *out, void *hip_stream)
     return HPL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batched small systems
+// ---------------------------------------------------------------------------
+int hpl_batched_sizes(uint64_t seed, int64_t count, int32_t nmin, int32_t nmax, int32_t *sizes)
+{
+    if (count < 0) return -2;
+    if (nmin < 1) return -3;
+    if (nmax < nmin) return -4;
+    if (count > 0 && sizes == nullptr) return -5;
+    const uint64_t s0 = stream_state(seed, kBatchSizeStream);
+    const int64_t range = (int64_t)nmax - (int64_t)nmin + 1;
+    for (int64_t i = 0; i < count; ++i) {
+        const double u = gen_value(s0, (uint64_t)i) + 0.5;  // exact, in [0, 1)
+        int64_t k = (int64_t)floor(u * (double)range);
+        if (k > range - 1) k = range - 1;
+        sizes[i] = (int32_t)(nmin + k);
+    }
+    return HPL_OK;
+}
+
+int hpl_batched_solve(int64_t count, const int32_t *sizes, int64_t nrhs, double *A, int32_t *ipiv, double *B,
+                      const double *W, double *GB, double *GA, int mode, int64_t *info, void *hip_stream)
+{
+    if (count < 0) return -1;
+    if (count > 0 && sizes == nullptr) return -2;
+    if (nrhs < 1 || nrhs > kBatchMaxRhs) return -3;
+    if (mode < 1 || mode > 3) return -10;
+    if (count > 0 && info == nullptr) return -11;
+    for (int64_t i = 0; i < count; ++i)
+        if (sizes[i] < 1 || sizes[i] > kBatchMaxN) return -2;
+    if (count > 0 && (A == nullptr || ipiv == nullptr || B == nullptr)) return A == nullptr ? -4 : (ipiv == nullptr ? -5 : -6);
+    if ((mode & 2) && count > 0 && (W == nullptr || GB == nullptr || GA == nullptr))
+        return W == nullptr ? -7 : (GB == nullptr ? -8 : -9);
+    if (count == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    hipStream_t st = (hipStream_t)hip_stream;
+    // host plan: packed offsets and the largest-first order
+    std::vector<int64_t> aoff((size_t)count), voff((size_t)count);
+    std::vector<int32_t> order((size_t)count);
+    int64_t a_acc = 0, v_acc = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        aoff[(size_t)i] = a_acc;
+        voff[(size_t)i] = v_acc;
+        a_acc += (int64_t)sizes[i] * sizes[i];
+        v_acc += sizes[i];
+        order[(size_t)i] = (int32_t)i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return sizes[x] > sizes[y]; });
+    // device copies: sizes | aoff | voff | order | info | counter (256-byte aligned pieces)
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_sizes = 0, o_aoff = up(4 * (size_t)count), o_voff = o_aoff + up(8 * (size_t)count);
+    const size_t o_order = o_voff + up(8 * (size_t)count), o_info = o_order + up(4 * (size_t)count);
+    const size_t o_cnt = o_info + up(8 * (size_t)count), total = o_cnt + 256;
+    if (d->bat_cap < total) {
+        if (d->bat_ws) HPLX_TRY(hipFree(d->bat_ws));
+        d->bat_ws = nullptr;
+        d->bat_cap = 0;
+        if (hipMalloc(&d->bat_ws, total) != hipSuccess) HPLX_FAIL(HPL_ERR_NOMEM, "batched workspace allocation failed");
+        d->bat_cap = total;
+    }
+    char *ws = (char *)d->bat_ws;
+    HPLX_TRY(hipMemcpyAsync(ws + o_sizes, sizes, 4 * (size_t)count, hipMemcpyHostToDevice, st));
+    HPLX_TRY(hipMemcpyAsync(ws + o_aoff, aoff.data(), 8 * (size_t)count, hipMemcpyHostToDevice, st));
+    HPLX_TRY(hipMemcpyAsync(ws + o_voff, voff.data(), 8 * (size_t)count, hipMemcpyHostToDevice, st));
+    HPLX_TRY(hipMemcpyAsync(ws + o_order, order.data(), 4 * (size_t)count, hipMemcpyHostToDevice, st));
+    HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)(ws + o_cnt), 1, 0ull, st));
+    int cus = 0;
+    HPLX_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d->id));
+    Timer tm(d, opt_timing.load() != 0);
+    const int id = tm.begin(ST_BATCHED, st);
+    HPLX_PROPAGATE(launch_batched_solve(count, (const int32_t *)(ws + o_sizes), (const int64_t *)(ws + o_aoff),
+                                        (const int64_t *)(ws + o_voff), (const int32_t *)(ws + o_order), A, ipiv, B,
+                                        W, GB, GA, (int)nrhs, mode, (int64_t *)(ws + o_info),
+                                        (unsigned *)(ws + o_cnt), (int64_t)cus, st));
+    double fl = 0.0;
+    for (int64_t i = 0; i < count; ++i) {
+        const double n = (double)sizes[i];
+        if (mode & 1) fl += 2.0 * n * n * n / 3.0 + 2.0 * n * n * (double)nrhs;
+        if (mode & 2) fl += 2.0 * n * n * (double)nrhs + 2.0 * n * n * (double)nrhs;
+    }
+    HPLX_PROPAGATE(tm.end(id, st, fl, 8.0 * (double)a_acc * ((mode & 2) ? 3.0 : 2.0)));
+    HPLX_TRY(hipMemcpyAsync(info, ws + o_info, 8 * (size_t)count, hipMemcpyDeviceToHost, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    return tm.collect();
+}
+
 int hpl_release(void)
 {
     std::lock_guard<std::mutex> lk(g_dev_mu);
@@ -1058,6 +1148,7 @@ int hpl_release(void)
         if (d.splans) (void)hipFree(d.splans);
         if (d.mxp_ws) (void)hipFree(d.mxp_ws);
         if (d.mxp_vec) (void)hipFree(d.mxp_vec);
+        if (d.bat_ws) (void)hipFree(d.bat_ws);
         if (d.hbuf) (void)hipHostFree(d.hbuf);
         (void)hipFree(d.ws);
         d = Device();

@@ -29,7 +29,7 @@ HPL_OPT_PROGRESS = 5
 HPL_OPT_SERIALIZE = 6
 HPL_OPT_GEMM_TILE = 7
 
-STAT_CLASSES = ("gemm", "panel", "laswp", "trsm", "solve", "plan", "mxp_gemm", "mxp_fact", "grad_a")
+STAT_CLASSES = ("gemm", "panel", "laswp", "trsm", "solve", "plan", "mxp_gemm", "mxp_fact", "grad_a", "batched")
 
 
 class HplError(RuntimeError):
@@ -70,6 +70,8 @@ def _load():
         "hpl_mxp_generate": (i32, [u64, P, i64, i64, P]),
         "hpl_mxp_factor": (i32, [P, i64, i64, i64, i32, P, i64, P, P]),
         "hpl_mxp_solve": (i32, [P, i64, P, i64, i64, P, P, i64, P, P]),
+        "hpl_batched_sizes": (i32, [u64, i64, ctypes.c_int32, ctypes.c_int32, P]),
+        "hpl_batched_solve": (i32, [i64, P, i64, P, P, P, P, P, P, i32, P, P]),
         "hpl_release": (i32, []),
         "hpl_strerror": (ctypes.c_char_p, [i32]),
         "hpl_last_error_detail": (ctypes.c_char_p, []),
@@ -85,7 +87,7 @@ _lib = _load()
 EXPORTED = ("hpl_factor", "hpl_solve", "hpl_residual", "hpl_residual_gen", "hpl_generate",
             "hpl_set_option", "hpl_get_option", "hpl_get_stats", "hpl_reset_stats",
             "hpl_mfma_peak", "hpl_solve_grad_a", "hpl_generate_normal", "hpl_add_diagonal",
-            "hpl_mxp_generate", "hpl_mxp_factor", "hpl_mxp_solve",
+            "hpl_mxp_generate", "hpl_mxp_factor", "hpl_mxp_solve", "hpl_batched_sizes", "hpl_batched_solve",
             "hpl_release", "hpl_strerror", "hpl_last_error_detail")
 
 
@@ -289,6 +291,55 @@ def hpl_mxp_solve(A, LU, b, x=None, max_iter=50, stream=None):
                                                 int(max_iter), out.ctypes.data_as(ctypes.c_void_p),
                                                 _stream(stream)))
     return x, out
+
+
+BATCH_FORWARD, BATCH_ADJOINT, BATCH_BOTH = 1, 2, 3
+
+
+def hpl_batched_sizes(seed, count, nmin=32, nmax=512):
+    """Seeded system sizes of a batch (host computation); numpy int32 array."""
+    sizes = np.zeros(max(int(count), 1), dtype=np.int32)
+    _check("hpl_batched_sizes", _lib.hpl_batched_sizes(int(seed), int(count), int(nmin), int(nmax),
+                                                        sizes.ctypes.data_as(ctypes.c_void_p)))
+    return sizes[:int(count)]
+
+
+def batch_layout(sizes, nrhs):
+    """Packed offsets: (aoff, voff, total A elements, total B elements), numpy int64."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    aoff = np.concatenate([[0], np.cumsum(sizes * sizes)[:-1]]) if sizes.size else np.zeros(0, np.int64)
+    voff = np.concatenate([[0], np.cumsum(sizes)[:-1]]) if sizes.size else np.zeros(0, np.int64)
+    return aoff, voff, int(np.sum(sizes * sizes)), int(np.sum(sizes)) * int(nrhs)
+
+
+def hpl_batched_solve(sizes, A, ipiv, B, nrhs, W=None, GB=None, GA=None, mode=BATCH_FORWARD, stream=None):
+    """One launch over the packed batch (see hpl.h); returns the info array (numpy int64)."""
+    torch = _torch()
+    sizes = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    count = sizes.size
+    _, _, na, nb_ = batch_layout(sizes, nrhs)
+
+    def dev(name, T, n, dtype, need):
+        if T is None:
+            if need:
+                raise ValueError(f"{name} is required for mode {mode}")
+            return None
+        if not T.is_cuda or T.dtype != dtype or not T.is_contiguous() or T.numel() < n:
+            raise TypeError(f"{name} must be a contiguous CUDA {dtype} tensor of at least {n} elements")
+        return ctypes.c_void_p(T.data_ptr())
+
+    adj = bool(mode & 2)
+    pA = dev("A", A, na, torch.float64, True)
+    pI = dev("ipiv", ipiv, int(np.sum(sizes)), torch.int32, True)
+    pB = dev("B", B, nb_, torch.float64, True)
+    pW = dev("W", W, nb_, torch.float64, adj)
+    pGB = dev("GB", GB, nb_, torch.float64, adj)
+    pGA = dev("GA", GA, na, torch.float64, adj)
+    info = np.zeros(max(count, 1), dtype=np.int64)
+    _check("hpl_batched_solve", _lib.hpl_batched_solve(count, sizes.ctypes.data_as(ctypes.c_void_p), int(nrhs), pA,
+                                                        pI, pB, pW, pGB, pGA, int(mode),
+                                                        info.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return info[:count]
 
 
 def _colmajor_copy(T):

@@ -139,3 +139,35 @@ def test_stats_interface():
     st = h.hpl_get_stats()
     assert set(st) >= {"gemm", "panel", "laswp", "trsm", "solve"}
     assert all(v["launches"] == 0 for v in st.values())
+
+
+def test_batched_argument_errors_and_sizes():
+    import numpy as np
+    import oracle
+    L = h.lib()
+    info = (ctypes.c_int64 * 4)()
+    sz = (ctypes.c_int32 * 2)(4, 513)
+    ok = (ctypes.c_int32 * 2)(4, 5)
+    assert L.hpl_batched_solve(-1, ok, 1, FAKE, FAKE, FAKE, None, None, None, 1, info, None) == -1
+    assert L.hpl_batched_solve(2, None, 1, FAKE, FAKE, FAKE, None, None, None, 1, info, None) == -2
+    assert L.hpl_batched_solve(2, sz, 1, FAKE, FAKE, FAKE, None, None, None, 1, info, None) == -2
+    assert L.hpl_batched_solve(2, ok, 0, FAKE, FAKE, FAKE, None, None, None, 1, info, None) == -3
+    assert L.hpl_batched_solve(2, ok, 17, FAKE, FAKE, FAKE, None, None, None, 1, info, None) == -3
+    assert L.hpl_batched_solve(2, ok, 1, None, FAKE, FAKE, None, None, None, 1, info, None) == -4
+    assert L.hpl_batched_solve(2, ok, 1, FAKE, None, FAKE, None, None, None, 1, info, None) == -5
+    assert L.hpl_batched_solve(2, ok, 1, FAKE, FAKE, None, None, None, None, 1, info, None) == -6
+    assert L.hpl_batched_solve(2, ok, 1, FAKE, FAKE, FAKE, None, FAKE, FAKE, 3, info, None) == -7
+    assert L.hpl_batched_solve(2, ok, 1, FAKE, FAKE, FAKE, FAKE, None, FAKE, 2, info, None) == -8
+    assert L.hpl_batched_solve(2, ok, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None, 2, info, None) == -9
+    assert L.hpl_batched_solve(2, ok, 1, FAKE, FAKE, FAKE, None, None, None, 0, info, None) == -10
+    assert L.hpl_batched_solve(2, ok, 1, FAKE, FAKE, FAKE, None, None, None, 4, info, None) == -10
+    assert L.hpl_batched_solve(2, ok, 1, FAKE, FAKE, FAKE, None, None, None, 1, None, None) == -11
+    assert L.hpl_batched_solve(0, None, 1, None, None, None, None, None, None, 1, None, None) == 0
+    assert L.hpl_batched_sizes(1, -1, 1, 2, info) == -2
+    assert L.hpl_batched_sizes(1, 2, 0, 2, info) == -3
+    assert L.hpl_batched_sizes(1, 2, 5, 4, info) == -4
+    assert L.hpl_batched_sizes(1, 2, 1, 4, None) == -5
+    # the library's host-side sizes equal the oracle's, bit for bit
+    for seed, cnt, lo, hi in ((2304, 4096, 32, 512), (7, 1000, 1, 100), (1, 10, 5, 5)):
+        got = h.hpl_batched_sizes(seed, cnt, lo, hi)
+        assert np.array_equal(got, oracle.batched_sizes(seed, cnt, lo, hi))
