@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 METRIC = "HPL TFLOP/s (2N³/3+2N²) & % FP64 MFMA peak; MxP+IR speed-up at FP64 residual"
 PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X datasheet, dense FP64 matrix
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X, FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
 
 # HBM bytes per trailing-GEMM launch measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 2048 MiB copy: x2.000 and x1.000) at the default
@@ -265,6 +266,107 @@ def bench_mxp(args, torch, h):
     print(json.dumps(out), flush=True)
 
 
+def bench_batched(args, torch, h):
+    """Batched uneven solves: 4096 systems, n ~ U{32..512} (stream 3), A and B uniform,
+    4 right-hand sides, W standard normal; one persistent launch for factor + solve
+    (the metric) and one for factor + solve + adjoint, against one launch per system
+    (timed on every 8th system)."""
+    import numpy as np
+    count, nrhs = 4096, 4
+    sizes = h.hpl_batched_sizes(args.seed, count, 32, 512)
+    _, _, na, nb = h.batch_layout(sizes, nrhs)
+    A0 = torch.empty(na, dtype=torch.float64, device="cuda")
+    B0 = torch.empty(nb, dtype=torch.float64, device="cuda")
+    W = torch.empty(nb, dtype=torch.float64, device="cuda")
+    h.hpl_generate(args.seed, 0, A0)
+    h.hpl_generate(args.seed, 1, B0)
+    h.hpl_generate_normal(args.seed, 2, W)
+    A, B = torch.empty_like(A0), torch.empty_like(B0)
+    GB, GA = torch.empty_like(B0), torch.empty_like(A0)
+    ipiv = torch.empty(int(np.sum(sizes)), dtype=torch.int32, device="cuda")
+    n3 = sizes.astype(np.float64)
+    f_fwd = float(np.sum(2.0 * n3 ** 3 / 3.0 + 2.0 * n3 ** 2 * nrhs))
+
+    def run(mode, reps, label):
+        wall, dev = [], []
+        for step in range(args.warmup + reps):
+            A.copy_(A0)
+            B.copy_(B0)
+            torch.cuda.synchronize()
+            h.hpl_reset_stats()
+            h.hpl_set_option(h.HPL_OPT_TIMING, 1)
+            t0 = time.perf_counter()
+            info = h.hpl_batched_solve(sizes, A, ipiv, B, nrhs, W=W, GB=GB, GA=GA, mode=mode)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            h.hpl_set_option(h.HPL_OPT_TIMING, 0)
+            st = h.hpl_get_stats()["batched"]
+            if int(np.count_nonzero(info)):
+                raise RuntimeError(f"{label}: singular system in the batch")
+            log(f"{label} step {step}: {1e3 * dt:.3f} ms wall, kernel {st['ms']:.3f} ms")
+            if step >= args.warmup:
+                wall.append(dt)
+                dev.append(st["ms"] * 1e-3)
+        return sum(wall) / len(wall), sum(dev) / len(dev)
+
+    t_fwd, k_fwd = run(h.BATCH_FORWARD, args.steps, "factor+solve")
+    t_both, k_both = run(h.BATCH_BOTH, args.steps, "factor+solve+adjoint")
+    # one launch per system, every 8th system of the batch
+    sample = np.arange(0, count, 8)
+    _, voff_all, _, _ = h.batch_layout(sizes, nrhs)
+    aoff_all = h.batch_layout(sizes, nrhs)[0]
+    A.copy_(A0)
+    B.copy_(B0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in sample:
+        n = int(sizes[i])
+        a0, v0 = int(aoff_all[i]), int(voff_all[i])
+        h.hpl_batched_solve(sizes[i:i + 1], A[a0:a0 + n * n], ipiv[v0:v0 + n], B[nrhs * v0:nrhs * v0 + n * nrhs],
+                            nrhs, mode=h.BATCH_FORWARD)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    loop_rate = sample.size / t_loop
+    out = {
+        "metric": "batched uneven FP64 solves (LU with partial pivoting + solve), one persistent launch",
+        "value": round(count / t_fwd, 1),
+        "unit": "systems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_fwd, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{count} systems, n ~ U{{32..512}} (seed {args.seed}, stream 3), A_i, B_i ~ U[-0.5,0.5), "
+                        f"{nrhs} right-hand sides, W ~ N(0,1) for the adjoint",
+            "systems": count, "nrhs": nrhs, "sum_n": int(np.sum(sizes)),
+            "factor_solve_tflops": round(f_fwd / t_fwd / 1e12, 3),
+            "factor_solve_adjoint_ms": round(1e3 * t_both, 3),
+            "factor_solve_adjoint_systems_per_s": round(count / t_both, 1),
+            "adjoint_ms": round(1e3 * (t_both - t_fwd), 3),
+            "per_system_launch_loop_systems_per_s": round(loop_rate, 1),
+            "speedup_vs_per_system_loop": round((count / t_fwd) / loop_rate, 2),
+            "per_system_loop_sample": f"every 8th system ({sample.size} launches, sizes as in the batch)",
+        },
+        "roofline": {
+            "kernel": "batched_solve_kernel (factor + solve; FP64 FMA on the VALU)",
+            "bound": "alu",
+            "achieved": round(f_fwd / k_fwd / 1e12, 3),
+            "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(f_fwd / k_fwd / 1e12 / PEAK_FP64_VALU_TFLOPS, 4),
+            "avg_launch_ms": round(1e3 * k_fwd, 4),
+            "algorithmic_flops_per_launch": f_fwd,
+            "traffic": None,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,7 +380,7 @@ def main():
     ap.add_argument("--pad", type=int, default=0, help="lda = n + pad")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="N of the oracle sample (0: skip)")
     ap.add_argument("--progress", type=int, default=32, help="progress line every k panels (stderr)")
-    ap.add_argument("--workload", choices=["hpl", "diffsolve", "mxp"], default="hpl",
+    ap.add_argument("--workload", choices=["hpl", "diffsolve", "mxp", "batched"], default="hpl",
                     help="hpl: the HPL factor + solve (default); diffsolve: the differentiable FP64 "
                          "solve, N=8192 NB=256 16 right-hand sides, forward + backward; mxp: mixed-precision "
                          "LU + FP64 refinement at N=65536 against the FP64 path on the same matrix")
@@ -310,6 +412,8 @@ def main():
         return bench_diffsolve(args, torch, h)
     if args.workload == "mxp":
         return bench_mxp(args, torch, h)
+    if args.workload == "batched":
+        return bench_batched(args, torch, h)
     n, nb = args.n, args.nb
     log(f"device {torch.cuda.get_device_name(dev)}; N={n} NB={nb} look-ahead={args.lookahead}")
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, args.lookahead)

@@ -19,16 +19,19 @@
 //      barrier: each wave publishes its best candidate (|a|, row) and that
 //      row's values in LDS (double-buffered by column parity), the diagonal
 //      row is published too, and every thread then knows the pivot row and
-//      performs the interchange and the rank-1 update of its own row.
+//      performs the interchange and the rank-1 update of its own row.  The
+//      column loop is rolled (the register row rotates by one column per step).
 //   2. The 32 interchanges are composed (by thread 0, during FACT) into one
 //      permutation of the <= 64 rows they touch; every other column (left:
 //      LAPACK-form L; right: U12 and the trailing columns; the right-hand
 //      sides, carried as extra columns so that B becomes L^{-1} P B as in
-//      HPL's augmented system) is permuted with one burst of loads, and the
-//      right columns' top 32 rows are solved with the unit-lower L11 (LDS).
+//      HPL's augmented system) goes through LDS in chunks of 64 columns:
+//      gathered with lane = slot (the panel rows of a column are consecutive,
+//      so the reads coalesce), the right columns' top 32 rows solved with the
+//      unit-lower L11, and scattered to the destination rows.
 //   3. Trailing update C -= L21 U12 over rows [k0+32, n) and columns
 //      [k0+32, n+nrhs): 8 x 4 register tiles, L21 and U12 staged through LDS
-//      16 k at a time; the product is accumulated from zero in k order and
+//      8 k at a time; the product is accumulated from zero in k order and
 //      then subtracted from C.  FP64 FMA on the VALU: on this chip the FP64
 //      vector and matrix peaks are equal, and the VALU form needs no
 //      16-alignment at these small, ragged sizes.
@@ -46,10 +49,12 @@ namespace {
 constexpr int kBT = 512;               // threads per workgroup
 constexpr int kBW = kBT / 64;          // waves
 constexpr int kPB = 32;                // panel width
-constexpr int kKC = 16;                // k per LDS stage of the trailing update
+constexpr int kKC = 8;                 // k per LDS stage of the trailing update
 constexpr int kTM = 8, kTN = 4;        // register tile of the trailing update (rows x columns)
 constexpr int kMaxColGroups = 64;      // <= 256 columns per update chunk
 constexpr int kMaxSlots = 2 * kPB;     // rows touched by one panel's interchanges
+constexpr int kGc = 64;                // columns per chunk of the interchange pass
+static_assert(kBT % kMaxSlots == 0 && kGc % (kBT / kMaxSlots) == 0, "interchange pass shape");
 
 struct BatchArgs {
     int64_t count;
@@ -73,6 +78,7 @@ struct BatchShared {
     double Lc[kKC][kBatchMaxN];            // L21 stage [k][row]; also the right-hand-side stage
     double Uc[kKC][kTN * kMaxColGroups];   // U12 stage [k][column]
     double T[kPB][kPB + 1];                // diagonal block (L11, or a block of U / L for the solves)
+    double G[kGc][kMaxSlots + 1];          // interchange pass: [column][slot]
     double prow[2][kBW][kPB];              // per-wave candidate rows
     double drow[2][kPB];                   // the diagonal row
     double pv[2][kBW];                     // per-wave candidate |a|
@@ -81,274 +87,357 @@ struct BatchShared {
     int perm[kBatchMaxN];                  // row permutation: row i of P A is row perm[i] of A
     int slot_row[kMaxSlots];               // interchange composition: destination rows ...
     int slot_src[kMaxSlots];               // ... and the original row each receives
+    int slotmap[kBatchMaxN];               // row -> its slot for rows below the panel (-1: none)
     int nslots;
     int64_t info;
     int64_t job;
 };
 
-__device__ __forceinline__ double *col_ptr(double *a, double *b, int n, int c)
+// global-memory pointers for the phase functions (a plain pointer argument of a
+// non-inlined function is generic, and generic accesses share the LDS wait
+// counter)
+typedef __attribute__((address_space(1))) double gf64;
+typedef __attribute__((address_space(1))) const double gcf64;
+typedef __attribute__((address_space(1))) int32_t gi32;
+
+// the workgroup's shared state (one workgroup per CU; file scope, so that the
+// phase functions below address it as LDS without a pointer argument)
+__shared__ BatchShared sh;
+
+__device__ __forceinline__ gf64 *col_ptr(gf64 *a, gf64 *b, int n, int c)
 {
     return c < n ? a + (size_t)c * (size_t)n : b + (size_t)(c - n) * (size_t)n;
 }
 
-// slot of row r in the composition list (appending it if new); thread 0 only
-__device__ __forceinline__ int slot_of(BatchShared &sh, int k0, int r)
-{
-    if (r < k0 + kPB) return r - k0;
-    for (int s = kPB; s < sh.nslots; ++s)
-        if (sh.slot_row[s] == r) return s;
-    const int s = sh.nslots++;
-    sh.slot_row[s] = r;
-    sh.slot_src[s] = r;
-    return s;
-}
 
-// ---------------------------------------------------------------------------
-// forward: LU with partial pivoting of the augmented [A | B], then U X = Y
-// ---------------------------------------------------------------------------
-__device__ void batch_forward(BatchShared &sh, double *a, double *b, int32_t *ip, int n, int nrhs)
+// FACT of the panel [k0, k0+w) (rows k0..n-1 in registers), its interchanges
+// recorded in ip, the permutation and the slot lists; L11 left in sh.T.
+// The column loop is not unrolled (the unrolled body overflows the
+// instruction cache): the register row rotates by one column per step, so the
+// current column is always v[0] and every register index is a constant.
+__device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, int k0)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int ncol = n + nrhs;
-    for (int i = t; i < n; i += kBT) sh.perm[i] = i;
-    if (t == 0) sh.info = 0;
-    __syncthreads();
-
-    for (int k0 = 0; k0 < n; k0 += kPB) {
-        const int w = (n - k0) < kPB ? (n - k0) : kPB;
-        const int r = k0 + t;
-        const bool own = r < n;
-        if (t == 0) {
-            // slots 0..w-1 are the panel's rows; pivot rows below the panel
-            // are appended (only when w == kPB: otherwise every row is in it)
-            sh.nslots = w;
-            for (int s = 0; s < w; ++s) {
-                sh.slot_row[s] = k0 + s;
-                sh.slot_src[s] = k0 + s;
-            }
+    const int w = (n - k0) < kPB ? (n - k0) : kPB;
+    const int r = k0 + t;
+    const bool own = r < n;
+    for (int i = t; i < n; i += kBT) sh.slotmap[i] = -1;
+    if (t == 0) {
+        // slots 0..w-1 are the panel's rows; pivot rows below the panel
+        // are appended (only when w == kPB: otherwise every row is in it)
+        sh.nslots = w;
+        for (int q = 0; q < w; ++q) {
+            sh.slot_row[q] = k0 + q;
+            sh.slot_src[q] = k0 + q;
         }
-        // ---- 1. FACT of columns [k0, k0+w): row k0+t in registers
-        double v[kPB];
-        {
-            const int rr = own ? r : n - 1;
+    }
+    double v[kPB];
+    {
+        const int rr = own ? r : n - 1;
 #pragma unroll
-            for (int j = 0; j < kPB; ++j) {
-                const int cj = (k0 + j) < n ? (k0 + j) : (n - 1);
-                const double x = a[(size_t)rr + (size_t)cj * (size_t)n];
-                v[j] = (own && j < w) ? x : 0.0;
-            }
+        for (int q = 0; q < kPB; ++q) {
+            const int cq = (k0 + q) < n ? (k0 + q) : (n - 1);
+            const double x = a[(size_t)rr + (size_t)cq * (size_t)n];
+            v[q] = (own && q < w) ? x : 0.0;
         }
-        __syncthreads();  // slot lists initialised
-#pragma unroll
-        for (int j = 0; j < kPB; ++j) {
-            if (j < w) {
-                const int par = j & 1;
-                // wave argmax of |v[j]| over rows >= k0+j (ties: lowest row)
-                double cv = (own && t >= j) ? fabs(v[j]) : -1.0;
-                int cr = (own && t >= j) ? r : 0x7fffffff;
-                for (int o = 32; o > 0; o >>= 1) {
-                    const double ov = __shfl_xor(cv, o, 64);
-                    const int orr = __shfl_xor(cr, o, 64);
-                    if (ov > cv || (ov == cv && orr < cr)) {
-                        cv = ov;
-                        cr = orr;
-                    }
-                }
-                if (lane == 0) {
-                    sh.pv[par][wave] = cv;
-                    sh.pr[par][wave] = cv >= 0.0 ? cr : -1;
-                }
-                if (own && r == cr && cv >= 0.0) {
-#pragma unroll
-                    for (int q = 0; q < kPB; ++q) sh.prow[par][wave][q] = v[q];
-                }
-                if (r == k0 + j) {
-#pragma unroll
-                    for (int q = 0; q < kPB; ++q) sh.drow[par][q] = v[q];
-                }
-                __syncthreads();
-                double gv = -1.0;
-                int gp = 0x7fffffff, gw = 0;
-#pragma unroll
-                for (int q = 0; q < kBW; ++q) {
-                    const double qv = sh.pv[par][q];
-                    const int qr = sh.pr[par][q];
-                    if (qr >= 0 && (qv > gv || (qv == gv && qr < gp))) {
-                        gv = qv;
-                        gp = qr;
-                        gw = q;
-                    }
-                }
-                // no valid candidate (a NaN column): keep the diagonal row, so
-                // every row index stays inside the system
-                if (gp == 0x7fffffff) gp = k0 + j;
-                const double *u = (gp == k0 + j) ? sh.drow[par] : sh.prow[par][gw];
-                if (gp != k0 + j) {
-                    if (r == k0 + j) {
-#pragma unroll
-                        for (int q = 0; q < kPB; ++q) v[q] = u[q];
-                    } else if (r == gp) {
-#pragma unroll
-                        for (int q = 0; q < kPB; ++q) v[q] = sh.drow[par][q];
-                    }
-                }
-                if (t == 0) {
-                    ip[k0 + j] = gp;
-                    if (gp != k0 + j) {
-                        const int pk = sh.perm[k0 + j];
-                        sh.perm[k0 + j] = sh.perm[gp];
-                        sh.perm[gp] = pk;
-                        const int s1 = j, s2 = slot_of(sh, k0, gp);
-                        const int tmp = sh.slot_src[s1];
-                        sh.slot_src[s1] = sh.slot_src[s2];
-                        sh.slot_src[s2] = tmp;
-                    }
-                }
-                const double piv = u[j];
-                if (piv == 0.0) {
-                    if (t == 0 && sh.info == 0) sh.info = k0 + j + 1;  // column left unscaled
-                } else if (own && r > k0 + j) {
-                    const double l = v[j] / piv;
-                    v[j] = l;
-#pragma unroll
-                    for (int q = j + 1; q < kPB; ++q) v[q] = __fma_rn(-l, u[q], v[q]);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);  // one column's LDS traffic at a time
+    }
+    __syncthreads();  // slot lists and map initialised
+    for (int j = 0; j < w; ++j) {
+        const int par = j & 1;
+        // wave argmax of |v[0]| over rows >= k0+j; ties: the lowest row (lane)
+        const bool cand = own && t >= j;
+        const double cv = cand ? fabs(v[0]) : -1.0;
+        double vm = cv;
+        for (int o = 32; o > 0; o >>= 1) vm = fmax(vm, __shfl_xor(vm, o, 64));
+        const unsigned long long hit = __ballot(cand && cv == vm);
+        const int wl = hit ? (int)__builtin_ctzll(hit) : -1;
+        if (lane == 0) {
+            sh.pv[par][wave] = vm;
+            sh.pr[par][wave] = wl >= 0 ? k0 + 64 * wave + wl : -1;
         }
-        // write the factored panel back; L11 to LDS
-        if (own) {
+        if (lane == wl) {
 #pragma unroll
-            for (int j = 0; j < kPB; ++j)
-                if (j < w) a[(size_t)r + (size_t)(k0 + j) * (size_t)n] = v[j];
+            for (int q = 0; q < kPB; ++q) sh.prow[par][wave][q] = v[q];
         }
-        if (t < w) {
+        if (r == k0 + j) {
 #pragma unroll
-            for (int j = 0; j < kPB; ++j) sh.T[t][j] = v[j];
+            for (int q = 0; q < kPB; ++q) sh.drow[par][q] = v[q];
         }
         __syncthreads();
+        double gv = -1.0;
+        int gp = 0x7fffffff, gw = 0;
+#pragma unroll
+        for (int q = 0; q < kBW; ++q) {
+            const double qv = sh.pv[par][q];
+            const int qr = sh.pr[par][q];
+            if (qr >= 0 && (qv > gv || (qv == gv && qr < gp))) {
+                gv = qv;
+                gp = qr;
+                gw = q;
+            }
+        }
+        // no valid candidate (a NaN column): keep the diagonal row, so
+        // every row index stays inside the system
+        if (gp == 0x7fffffff) gp = k0 + j;
+        const double *u = (gp == k0 + j) ? sh.drow[par] : sh.prow[par][gw];
+        if (gp != k0 + j) {
+            if (r == k0 + j) {
+#pragma unroll
+                for (int q = 0; q < kPB; ++q) v[q] = u[q];
+            } else if (r == gp) {
+#pragma unroll
+                for (int q = 0; q < kPB; ++q) v[q] = sh.drow[par][q];
+            }
+        }
+        if (t == 0) {
+            ip[k0 + j] = gp;
+            if (gp != k0 + j) {
+                const int pk = sh.perm[k0 + j];
+                sh.perm[k0 + j] = sh.perm[gp];
+                sh.perm[gp] = pk;
+                int s2;
+                if (gp < k0 + kPB) {
+                    s2 = gp - k0;
+                } else if (sh.slotmap[gp] >= 0) {
+                    s2 = sh.slotmap[gp];
+                } else {
+                    s2 = sh.nslots++;
+                    sh.slotmap[gp] = s2;
+                    sh.slot_row[s2] = gp;
+                    sh.slot_src[s2] = gp;
+                }
+                const int tmp = sh.slot_src[j];
+                sh.slot_src[j] = sh.slot_src[s2];
+                sh.slot_src[s2] = tmp;
+            }
+        }
+        const double piv = u[0];
+        if (piv == 0.0) {
+            if (t == 0 && sh.info == 0) sh.info = k0 + j + 1;  // column left unscaled
+        } else if (own && r > k0 + j) {
+            const double l = v[0] / piv;
+            v[0] = l;
+            // the panel's remaining columns sit at 1 .. w-1-j
+#pragma unroll
+            for (int q = 1; q < kPB; ++q)
+                if (q < w - j) v[q] = __fma_rn(-l, u[q], v[q]);
+        }
+        // rotate: the next column moves to v[0], this one to the end
+        const double c0 = v[0];
+#pragma unroll
+        for (int q = 0; q < kPB - 1; ++q) v[q] = v[q + 1];
+        v[kPB - 1] = c0;
+    }
+    // w rotations so far: complete the turn, column q back at v[q]
+    for (int j = w; j < kPB; ++j) {
+        const double c0 = v[0];
+#pragma unroll
+        for (int q = 0; q < kPB - 1; ++q) v[q] = v[q + 1];
+        v[kPB - 1] = c0;
+    }
+    // write the factored panel back; L11 to LDS
+    if (own) {
+#pragma unroll
+        for (int q = 0; q < kPB; ++q)
+            if (q < w) a[(size_t)r + (size_t)(k0 + q) * (size_t)n] = v[q];
+    }
+    if (t < w) {
+#pragma unroll
+        for (int q = 0; q < kPB; ++q) sh.T[t][q] = v[q];
+    }
+    __syncthreads();
+}
 
-        // ---- 2. interchanges on every other column; U12 = L11^{-1} A12 on the right
+__device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int n, int ncol, int k0, int w)
+{
+    const int t = threadIdx.x;
+    // ---- 2. interchanges on every other column; U12 = L11^{-1} A12 on the right.
+    //      Chunks of kGc columns through LDS: gather (lane = slot, so the
+    //      panel rows of a column are read coalesced), the unit-lower solve
+    //      of the right columns' top rows (one thread per column), scatter.
+    {
         const int nslots = sh.nslots;
         const int nother = ncol - w;
-        for (int e = t; e < nother; e += kBT) {
-            const int c = e < k0 ? e : e + w;
-            double *cp = col_ptr(a, b, n, c);
-            // all sources are read before any row is written (a row may be
-            // both a source and a destination)
-            double x[kPB], xe[kPB];
+        const int slot = t & (kMaxSlots - 1), cq = t / kMaxSlots;  // kBT / kMaxSlots columns per pass
+        const int src = sh.slot_src[slot < nslots ? slot : nslots - 1];
+        const int dst = sh.slot_row[slot < nslots ? slot : nslots - 1];
+        for (int e0 = 0; e0 < nother; e0 += kGc) {
+            const int ce = (nother - e0) < kGc ? (nother - e0) : kGc;
+            double gq[kGc * kMaxSlots / kBT];
 #pragma unroll
-            for (int s = 0; s < kPB; ++s) {
-                const int ss = s < nslots ? s : nslots - 1;
-                x[s] = cp[sh.slot_src[ss]];
-                const int se = kPB + s < nslots ? kPB + s : nslots - 1;
-                xe[s] = cp[sh.slot_src[se]];
+            for (int q = 0; q < kGc * kMaxSlots / kBT; ++q) {
+                const int cl = cq + q * (kBT / kMaxSlots);
+                const int e = e0 + (cl < ce ? cl : ce - 1);
+                const int c = e < k0 ? e : e + w;
+                gq[q] = col_ptr(a, b, n, c)[src];
             }
 #pragma unroll
-            for (int s = 0; s < kPB; ++s)
-                if (kPB + s < nslots) cp[sh.slot_row[kPB + s]] = xe[s];
-            if (c >= k0 + w) {
-#pragma unroll
-                for (int i = 1; i < kPB; ++i) {
-                    if (i < w) {
-                        double acc = x[i];
-#pragma unroll
-                        for (int k = 0; k < i; ++k) acc = __fma_rn(-sh.T[i][k], x[k], acc);
-                        x[i] = acc;
-                    }
-                    __builtin_amdgcn_sched_barrier(0);  // keep each row's LDS reads next to their use
-                }
+            for (int q = 0; q < kGc * kMaxSlots / kBT; ++q) {
+                const int cl = cq + q * (kBT / kMaxSlots);
+                sh.G[cl][slot] = gq[q];
             }
+            __syncthreads();
+            if (t < ce) {
+                const int c = (e0 + t) < k0 ? (e0 + t) : (e0 + t + w);
+                if (c >= k0 + w) {
+                    double x[kPB];
 #pragma unroll
-            for (int s = 0; s < kPB; ++s)
-                if (s < nslots) cp[sh.slot_row[s]] = x[s];
-        }
-        __syncthreads();
-
-        // ---- 3. trailing update C -= L21 U12
-        const int m = n - k0 - w, nc = ncol - k0 - w;
-        if (m > 0 && nc > 0) {
-            const int R = (m + kTM - 1) / kTM;
-            int G = kBT / R;
-            if (G > kMaxColGroups) G = kMaxColGroups;
-            const int CW = kTN * G;
-            const int tr = t / G, tc = t - (t / G) * G;
-            const bool act = tr < R;
-            for (int cc0 = 0; cc0 < nc; cc0 += CW) {
-                double acc[kTM][kTN];
+                    for (int i = 0; i < kPB; ++i) x[i] = sh.G[t][i];
 #pragma unroll
-                for (int i = 0; i < kTM; ++i)
+                    for (int i = 1; i < kPB; ++i) {
+                        if (i < w) {
+                            double acc = x[i];
 #pragma unroll
-                    for (int jj = 0; jj < kTN; ++jj) acc[i][jj] = 0.0;
-                for (int kc = 0; kc < w; kc += kKC) {
-                    const int kw = (w - kc) < kKC ? (w - kc) : kKC;
-                    // stage L21[:, kc..kc+kw) as Lc[k][i] and U12[kc.., cc0..cc0+CW) as Uc[k][j]
-                    for (int e = t; e < kKC * m; e += kBT) {
-                        const int i = e % m, k = e / m;
-                        const int kk = k < kw ? k : kw - 1;
-                        const double x = a[(size_t)(k0 + w + i) + (size_t)(k0 + kc + kk) * (size_t)n];
-                        sh.Lc[k][i] = k < kw ? x : 0.0;
-                    }
-                    for (int e = t; e < kKC * CW; e += kBT) {
-                        const int k = e % kKC, j = e / kKC;
-                        const int kk = k < kw ? k : kw - 1;
-                        const int jc = (cc0 + j) < nc ? (cc0 + j) : (nc - 1);
-                        const double x = col_ptr(a, b, n, k0 + w + jc)[k0 + kc + kk];
-                        sh.Uc[k][j] = (k < kw && cc0 + j < nc) ? x : 0.0;
-                    }
-                    __syncthreads();
-                    if (act) {
-                        const int i0 = kTM * tr;
-#pragma unroll 4
-                        for (int k = 0; k < kKC; ++k) {
-                            double lv[kTM], uv[kTN];
-#pragma unroll
-                            for (int i = 0; i < kTM; ++i) lv[i] = sh.Lc[k][(i0 + i) < m ? (i0 + i) : (m - 1)];
-#pragma unroll
-                            for (int jj = 0; jj < kTN; ++jj) uv[jj] = sh.Uc[k][kTN * tc + jj];
-#pragma unroll
-                            for (int i = 0; i < kTM; ++i)
-#pragma unroll
-                                for (int jj = 0; jj < kTN; ++jj) acc[i][jj] = __fma_rn(lv[i], uv[jj], acc[i][jj]);
+                            for (int k = 0; k < i; ++k) acc = __fma_rn(-sh.T[i][k], x[k], acc);
+                            x[i] = acc;
                         }
+                        __builtin_amdgcn_sched_barrier(0);  // keep each row's LDS reads next to their use
                     }
-                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < kPB; ++i) sh.G[t][i] = x[i];
                 }
-                if (act) {
+            }
+            __syncthreads();
+            if (slot < nslots) {
 #pragma unroll
-                    for (int jj = 0; jj < kTN; ++jj) {
-                        const int j = cc0 + kTN * tc + jj;
-                        if (j < nc) {
-                            double *cp = col_ptr(a, b, n, k0 + w + j) + (k0 + w);
-                            double cv[kTM];
-#pragma unroll
-                            for (int i = 0; i < kTM; ++i) {
-                                const int ii = kTM * tr + i;
-                                cv[i] = cp[ii < m ? ii : m - 1];
-                            }
-#pragma unroll
-                            for (int i = 0; i < kTM; ++i)
-                                if (kTM * tr + i < m) cp[kTM * tr + i] = cv[i] - acc[i][jj];
-                        }
+                for (int q = 0; q < kGc * kMaxSlots / kBT; ++q) {
+                    const int cl = cq + q * (kBT / kMaxSlots);
+                    if (cl < ce) {
+                        const int e = e0 + cl;
+                        const int c = e < k0 ? e : e + w;
+                        col_ptr(a, b, n, c)[dst] = sh.G[cl][slot];
                     }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
-    // ---- U X = Y, 32-row blocks from the bottom (Y = L^{-1} P B is in b)
+}
+
+__device__ __attribute__((noinline)) void bat_update(gf64 *a, gf64 *b, int n, int ncol, int k0, int w)
+{
+    const int t = threadIdx.x;
+    // ---- 3. trailing update C -= L21 U12
+    const int m = n - k0 - w, nc = ncol - k0 - w;
+    if (m > 0 && nc > 0) {
+        const int R = (m + kTM - 1) / kTM;
+        int G = kBT / R;
+        if (G > kMaxColGroups) G = kMaxColGroups;
+        const int CW = kTN * G;
+        const int tr = t / G, tc = t - (t / G) * G;
+        const bool act = tr < R;
+        for (int cc0 = 0; cc0 < nc; cc0 += CW) {
+            double acc[kTM][kTN];
+#pragma unroll
+            for (int i = 0; i < kTM; ++i)
+#pragma unroll
+                for (int jj = 0; jj < kTN; ++jj) acc[i][jj] = 0.0;
+            for (int kc = 0; kc < w; kc += kKC) {
+                const int kw = (w - kc) < kKC ? (w - kc) : kKC;
+                // stage L21[:, kc..kc+kw) as Lc[k][i] and U12[kc.., cc0..cc0+CW) as Uc[k][j]
+                // every staging load is issued before the first LDS store
+                // (one memory round trip per stage, not one per element)
+                constexpr int kLq = kKC * kBatchMaxN / kBT, kUq = kKC * kTN * kMaxColGroups / kBT;
+                double lq[kLq], uq[kUq];
+#pragma unroll
+                for (int q = 0; q < kLq; ++q) {
+                    const int e = t + q * kBT;
+                    const int ec = e < kKC * m ? e : kKC * m - 1;
+                    const int i = ec % m, k = ec / m;
+                    const int kk = k < kw ? k : kw - 1;
+                    lq[q] = a[(size_t)(k0 + w + i) + (size_t)(k0 + kc + kk) * (size_t)n];
+                }
+#pragma unroll
+                for (int q = 0; q < kUq; ++q) {
+                    const int e = t + q * kBT;
+                    const int ec = e < kKC * CW ? e : kKC * CW - 1;
+                    const int k = ec % kKC, j = ec / kKC;
+                    const int kk = k < kw ? k : kw - 1;
+                    const int jc = (cc0 + j) < nc ? (cc0 + j) : (nc - 1);
+                    uq[q] = col_ptr(a, b, n, k0 + w + jc)[k0 + kc + kk];
+                }
+#pragma unroll
+                for (int q = 0; q < kLq; ++q) {
+                    const int e = t + q * kBT;
+                    if (e < kKC * m) {
+                        const int i = e % m, k = e / m;
+                        sh.Lc[k][i] = k < kw ? lq[q] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kUq; ++q) {
+                    const int e = t + q * kBT;
+                    if (e < kKC * CW) {
+                        const int k = e % kKC, j = e / kKC;
+                        sh.Uc[k][j] = (k < kw && cc0 + j < nc) ? uq[q] : 0.0;
+                    }
+                }
+                __syncthreads();
+                if (act) {
+                    const int i0 = kTM * tr;
+#pragma unroll 4
+                    for (int k = 0; k < kKC; ++k) {
+                        double lv[kTM], uv[kTN];
+#pragma unroll
+                        for (int i = 0; i < kTM; ++i) lv[i] = sh.Lc[k][(i0 + i) < m ? (i0 + i) : (m - 1)];
+#pragma unroll
+                        for (int jj = 0; jj < kTN; ++jj) uv[jj] = sh.Uc[k][kTN * tc + jj];
+#pragma unroll
+                        for (int i = 0; i < kTM; ++i)
+#pragma unroll
+                            for (int jj = 0; jj < kTN; ++jj) acc[i][jj] = __fma_rn(lv[i], uv[jj], acc[i][jj]);
+                    }
+                }
+                __syncthreads();
+            }
+            if (act) {
+#pragma unroll
+                for (int jj = 0; jj < kTN; ++jj) {
+                    const int j = cc0 + kTN * tc + jj;
+                    if (j < nc) {
+                        gf64 *cp = col_ptr(a, b, n, k0 + w + j) + (k0 + w);
+                        double cv[kTM];
+#pragma unroll
+                        for (int i = 0; i < kTM; ++i) {
+                            const int ii = kTM * tr + i;
+                            cv[i] = cp[ii < m ? ii : m - 1];
+                        }
+#pragma unroll
+                        for (int i = 0; i < kTM; ++i)
+                            if (kTM * tr + i < m) cp[kTM * tr + i] = cv[i] - acc[i][jj];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// U X = Y, 32-row blocks from the bottom (Y = L^{-1} P B is in b)
+__device__ __attribute__((noinline)) void bat_usolve(gcf64 *a, gf64 *b, int n, int nrhs)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nb0 = (n - 1) / kPB * kPB;
     for (int r0 = nb0; r0 >= 0; r0 -= kPB) {
         const int bw = (n - r0) < kPB ? (n - r0) : kPB;
-        for (int e = t; e < kPB * kPB; e += kBT) {
-            const int i = e % kPB, k = e / kPB;
-            const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
-            sh.T[i][k] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
+        {
+            double tq[kPB * kPB / kBT];
+#pragma unroll
+            for (int q = 0; q < kPB * kPB / kBT; ++q) {
+                const int e = t + q * kBT, i = e % kPB, k = e / kPB;
+                const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
+                tq[q] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
+            }
+#pragma unroll
+            for (int q = 0; q < kPB * kPB / kBT; ++q) {
+                const int e = t + q * kBT;
+                sh.T[e % kPB][e / kPB] = tq[q];
+            }
         }
         __syncthreads();
         for (int rh = wave; rh < nrhs; rh += kBW) {
-            double *bp = b + (size_t)rh * (size_t)n;
+            gf64 *bp = b + (size_t)rh * (size_t)n;
             double y = bp[r0 + (lane < bw ? lane : bw - 1)];
             for (int s = bw - 1; s >= 0; --s) {
                 const double xs = read_lane(y, s) / sh.T[s][s];
@@ -373,7 +462,7 @@ __device__ void batch_forward(BatchShared &sh, double *a, double *b, int32_t *ip
 #pragma unroll
                 for (int k = 0; k < kPB; ++k)
                     if (k < bw) acc = __fma_rn(u[k], sh.Ys[rh][k], acc);
-                double *bp = b + (size_t)rh * (size_t)n;
+                gf64 *bp = b + (size_t)rh * (size_t)n;
                 bp[i] = bp[i] - acc;
             }
         }
@@ -382,25 +471,62 @@ __device__ void batch_forward(BatchShared &sh, double *a, double *b, int32_t *ip
 }
 
 // ---------------------------------------------------------------------------
+// forward: LU with partial pivoting of the augmented [A | B], then U X = Y
+// ---------------------------------------------------------------------------
+__device__ void batch_forward(double *a, double *b, int32_t *ip, int n, int nrhs)
+{
+    const int t = threadIdx.x;
+    const int ncol = n + nrhs;
+    for (int i = t; i < n; i += kBT) sh.perm[i] = i;
+    if (t == 0) sh.info = 0;
+    __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += kPB) {
+        const int w = (n - k0) < kPB ? (n - k0) : kPB;
+        bat_panel((gf64 *)a, (gi32 *)ip, n, k0);
+        bat_interchange((gf64 *)a, (gf64 *)b, n, ncol, k0, w);
+        bat_update((gf64 *)a, (gf64 *)b, n, ncol, k0, w);
+    }
+    bat_usolve((gcf64 *)a, (gf64 *)b, n, nrhs);
+}
+
+// ---------------------------------------------------------------------------
 // adjoint: grad_B = A^{-T} W = P^T L^{-T} U^{-T} W, grad_A = -grad_B X^T
 // ---------------------------------------------------------------------------
-__device__ void batch_adjoint(BatchShared &sh, const double *a, const double *x, const double *wv, double *gb,
-                              double *ga, int n, int nrhs)
+__device__ __attribute__((noinline)) void batch_adjoint(gcf64 *a, gcf64 *x, gcf64 *wv, gf64 *gb,
+                              gf64 *ga, int n, int nrhs)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int e = t; e < n * nrhs; e += kBT) gb[e] = wv[e];
+    {
+        constexpr int kQ = kBatchMaxN * kBatchMaxRhs / kBT;
+        double wq[kQ];
+        const int tot = n * nrhs;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) wq[q] = wv[(t + q * kBT) < tot ? (t + q * kBT) : tot - 1];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+            if (t + q * kBT < tot) gb[t + q * kBT] = wq[q];
+    }
     __syncthreads();
     // U^T z = W: lower with diagonal u_ii, blocks from the top
     for (int r0 = 0; r0 < n; r0 += kPB) {
         const int bw = (n - r0) < kPB ? (n - r0) : kPB;
-        for (int e = t; e < kPB * kPB; e += kBT) {
-            const int i = e % kPB, k = e / kPB;
-            const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
-            sh.T[i][k] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
+        {
+            double tq[kPB * kPB / kBT];
+#pragma unroll
+            for (int q = 0; q < kPB * kPB / kBT; ++q) {
+                const int e = t + q * kBT, i = e % kPB, k = e / kPB;
+                const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
+                tq[q] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
+            }
+#pragma unroll
+            for (int q = 0; q < kPB * kPB / kBT; ++q) {
+                const int e = t + q * kBT;
+                sh.T[e % kPB][e / kPB] = tq[q];
+            }
         }
         __syncthreads();
         for (int rh = wave; rh < nrhs; rh += kBW) {
-            double *zp = gb + (size_t)rh * (size_t)n;
+            gf64 *zp = gb + (size_t)rh * (size_t)n;
             double y = zp[r0 + (lane < bw ? lane : bw - 1)];
             for (int s = 0; s < bw; ++s) {
                 const double xs = read_lane(y, s) / sh.T[s][s];
@@ -422,7 +548,7 @@ __device__ void batch_adjoint(BatchShared &sh, const double *a, const double *x,
 #pragma unroll
                 for (int k = 0; k < kPB; ++k)
                     if (k < bw) acc = __fma_rn(u[k], sh.Ys[rh][k], acc);
-                double *zp = gb + (size_t)rh * (size_t)n;
+                gf64 *zp = gb + (size_t)rh * (size_t)n;
                 zp[i] = zp[i] - acc;
             }
         }
@@ -432,14 +558,23 @@ __device__ void batch_adjoint(BatchShared &sh, const double *a, const double *x,
     const int nb0 = (n - 1) / kPB * kPB;
     for (int r0 = nb0; r0 >= 0; r0 -= kPB) {
         const int bw = (n - r0) < kPB ? (n - r0) : kPB;
-        for (int e = t; e < kPB * kPB; e += kBT) {
-            const int i = e % kPB, k = e / kPB;
-            const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
-            sh.T[i][k] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
+        {
+            double tq[kPB * kPB / kBT];
+#pragma unroll
+            for (int q = 0; q < kPB * kPB / kBT; ++q) {
+                const int e = t + q * kBT, i = e % kPB, k = e / kPB;
+                const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
+                tq[q] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
+            }
+#pragma unroll
+            for (int q = 0; q < kPB * kPB / kBT; ++q) {
+                const int e = t + q * kBT;
+                sh.T[e % kPB][e / kPB] = tq[q];
+            }
         }
         __syncthreads();
         for (int rh = wave; rh < nrhs; rh += kBW) {
-            double *zp = gb + (size_t)rh * (size_t)n;
+            gf64 *zp = gb + (size_t)rh * (size_t)n;
             double y = zp[r0 + (lane < bw ? lane : bw - 1)];
             for (int s = bw - 1; s >= 0; --s) {
                 const double xs = read_lane(y, s);
@@ -460,7 +595,7 @@ __device__ void batch_adjoint(BatchShared &sh, const double *a, const double *x,
 #pragma unroll
                 for (int k = 0; k < kPB; ++k)
                     if (k < bw) acc = __fma_rn(l[k], sh.Ys[rh][k], acc);
-                double *zp = gb + (size_t)rh * (size_t)n;
+                gf64 *zp = gb + (size_t)rh * (size_t)n;
                 zp[i] = zp[i] - acc;
             }
         }
@@ -469,9 +604,20 @@ __device__ void batch_adjoint(BatchShared &sh, const double *a, const double *x,
     // grad_B = P^T v: entry perm[i] receives v_i (staged through LDS)
     for (int rh = 0; rh < nrhs; rh += kKC) {
         const int nr = (nrhs - rh) < kKC ? (nrhs - rh) : kKC;
-        for (int e = t; e < nr * n; e += kBT) {
-            const int i = e % n, q = e / n;
-            sh.Lc[q][i] = gb[(size_t)(rh + q) * (size_t)n + i];
+        {
+            constexpr int kQ = kKC * kBatchMaxN / kBT;
+            double vq[kQ];
+            const int tot = nr * n;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int e = (t + q * kBT) < tot ? (t + q * kBT) : tot - 1;
+                vq[q] = gb[(size_t)(rh + e / n) * (size_t)n + e % n];
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int e = t + q * kBT;
+                if (e < tot) sh.Lc[e / n][e % n] = vq[q];
+            }
         }
         __syncthreads();
         for (int e = t; e < nr * n; e += kBT) {
@@ -480,13 +626,24 @@ __device__ void batch_adjoint(BatchShared &sh, const double *a, const double *x,
         }
         __syncthreads();
     }
-    // grad_A = -grad_B X^T: thread per row i, X's rows from LDS, k = rhs order
+    // grad_A = -grad_B X^T: thread per row i, X's rows from LDS, the sum over
+    // right-hand sides in order, kKC of them per pass
     for (int rh0 = 0; rh0 < nrhs; rh0 += kKC) {
-        // nrhs <= kBatchMaxRhs = kKC: a single pass
         const int nr = (nrhs - rh0) < kKC ? (nrhs - rh0) : kKC;
-        for (int e = t; e < nr * n; e += kBT) {
-            const int j = e % n, q = e / n;
-            sh.Lc[q][j] = x[(size_t)(rh0 + q) * (size_t)n + j];
+        {
+            constexpr int kQ = kKC * kBatchMaxN / kBT;
+            double xq[kQ];
+            const int tot = nr * n;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int e = (t + q * kBT) < tot ? (t + q * kBT) : tot - 1;
+                xq[q] = x[(size_t)(rh0 + e / n) * (size_t)n + e % n];
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int e = t + q * kBT;
+                if (e < tot) sh.Lc[e / n][e % n] = xq[q];
+            }
         }
         __syncthreads();
         for (int i = t; i < n; i += kBT) {
@@ -498,7 +655,8 @@ __device__ void batch_adjoint(BatchShared &sh, const double *a, const double *x,
 #pragma unroll
                 for (int q = 0; q < kKC; ++q)
                     if (q < nr) s = __fma_rn(g[q], sh.Lc[q][j], s);
-                ga[(size_t)i + (size_t)j * (size_t)n] = 0.0 - s;
+                gf64 *gp = ga + (size_t)i + (size_t)j * (size_t)n;
+                *gp = (rh0 == 0 ? 0.0 : *gp) - s;
             }
         }
         __syncthreads();
@@ -507,7 +665,6 @@ __device__ void batch_adjoint(BatchShared &sh, const double *a, const double *x,
 
 __global__ __launch_bounds__(kBT) void batched_solve_kernel(BatchArgs p)
 {
-    __shared__ BatchShared sh;
     const int t = threadIdx.x;
     for (;;) {
         if (t == 0) sh.job = (int64_t)atomicAdd(p.counter, 1u);
@@ -522,7 +679,7 @@ __global__ __launch_bounds__(kBT) void batched_solve_kernel(BatchArgs p)
         double *b = p.B + (size_t)vo * (size_t)p.nrhs;
         int32_t *ip = p.ipiv + vo;
         if (p.mode & 1) {
-            batch_forward(sh, a, b, ip, n, p.nrhs);
+            batch_forward(a, b, ip, n, p.nrhs);
         } else {
             // adjoint only: the row permutation from the stored interchanges
             if (t == 0) {
@@ -540,8 +697,8 @@ __global__ __launch_bounds__(kBT) void batched_solve_kernel(BatchArgs p)
             __syncthreads();
         }
         if (p.mode & 2)
-            batch_adjoint(sh, a, b, p.W + (size_t)vo * (size_t)p.nrhs, p.GB + (size_t)vo * (size_t)p.nrhs,
-                          p.GA + p.aoff[sys], n, p.nrhs);
+            batch_adjoint((gcf64 *)a, (gcf64 *)b, (gcf64 *)(p.W + (size_t)vo * (size_t)p.nrhs),
+                          (gf64 *)(p.GB + (size_t)vo * (size_t)p.nrhs), (gf64 *)(p.GA + p.aoff[sys]), n, p.nrhs);
         if (t == 0) p.info[sys] = sh.info;
         __syncthreads();
     }
