@@ -30,11 +30,8 @@
 //      so the reads coalesce), the right columns' top 32 rows solved with the
 //      unit-lower L11, and scattered to the destination rows.
 //   3. Trailing update C -= L21 U12 over rows [k0+32, n) and columns
-//      [k0+32, n+nrhs): 8 x 4 register tiles, L21 and U12 staged through LDS
-//      8 k at a time; the product is accumulated from zero in k order and
-//      then subtracted from C.  FP64 FMA on the VALU: on this chip the FP64
-//      vector and matrix peaks are equal, and the VALU form needs no
-//      16-alignment at these small, ragged sizes.
+//      [k0+32, n+nrhs) on the FP64 matrix cores (16 x 16 blocks, masked at
+//      the ragged edges), -L21 fragments in registers, U12 through LDS.
 // Then U X = Y by 32-row blocks from the bottom.  The adjoint: U^T z = W by
 // blocks from the top, L^T v = z from the bottom, grad_B = P^T v (a scatter
 // through the row permutation tracked during FACT), grad_A = -grad_B X^T.
@@ -50,8 +47,8 @@ constexpr int kBT = 512;               // threads per workgroup
 constexpr int kBW = kBT / 64;          // waves
 constexpr int kPB = 32;                // panel width
 constexpr int kKC = 8;                 // k per LDS stage of the trailing update
-constexpr int kTM = 8, kTN = 4;        // register tile of the trailing update (rows x columns)
-constexpr int kMaxColGroups = 64;      // <= 256 columns per update chunk
+constexpr int kUpdRows = 4;            // 16-row blocks per wave in the trailing update (8 waves x 4 x 16 >= 480)
+constexpr int kUpdCols = 128;          // columns of U12 staged in LDS at a time
 constexpr int kMaxSlots = 2 * kPB;     // rows touched by one panel's interchanges
 constexpr int kGc = 64;                // columns per chunk of the interchange pass
 static_assert(kBT % kMaxSlots == 0 && kGc % (kBT / kMaxSlots) == 0, "interchange pass shape");
@@ -75,10 +72,12 @@ struct BatchArgs {
 };
 
 struct BatchShared {
-    double Lc[kKC][kBatchMaxN];            // L21 stage [k][row]; also the right-hand-side stage
-    double Uc[kKC][kTN * kMaxColGroups];   // U12 stage [k][column]
+    union {
+        double Lc[kKC][kBatchMaxN];        // right-hand-side stage of the adjoint
+        double G[kGc][kMaxSlots + 1];      // interchange pass: [column][slot]
+        double Us[kPB][kUpdCols + 8];      // trailing update: U12 [k][column]
+    };
     double T[kPB][kPB + 1];                // diagonal block (L11, or a block of U / L for the solves)
-    double G[kGc][kMaxSlots + 1];          // interchange pass: [column][slot]
     double prow[2][kBW][kPB];              // per-wave candidate rows
     double drow[2][kPB];                   // the diagonal row
     double pv[2][kBW];                     // per-wave candidate |a|
@@ -315,103 +314,88 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
 
 }
 
+// Trailing update C -= L21 U12 (rows and columns from k0+32; the last panel,
+// narrower than 32, leaves no trailing matrix) on the FP64 matrix cores:
+// 16 x 16 blocks, v_mfma_f64_16x16x4_f64, K = 32 as 8 MFMAs.  Wave w owns
+// block-rows w, w+8, ..; its -L21 fragments (lane l: row 16R + l%16, k = 4s +
+// l/16) stay in registers for the whole step; U12 goes through LDS 128
+// columns at a time.  The U fragment is the MFMA's first operand, so a block
+// comes out transposed: register r of lane l is C(16R + l%16, 16G + l/16 +
+// 4r), 16 consecutive rows per access.  Accumulators start from C; the
+// products are added in k order.
 __device__ __attribute__((noinline)) void bat_update(gf64 *a, gf64 *b, int n, int ncol, int k0, int w)
 {
-    const int t = threadIdx.x;
-    // ---- 3. trailing update C -= L21 U12
-    const int m = n - k0 - w, nc = ncol - k0 - w;
-    if (m > 0 && nc > 0) {
-        const int R = (m + kTM - 1) / kTM;
-        int G = kBT / R;
-        if (G > kMaxColGroups) G = kMaxColGroups;
-        const int CW = kTN * G;
-        const int tr = t / G, tc = t - (t / G) * G;
-        const bool act = tr < R;
-        for (int cc0 = 0; cc0 < nc; cc0 += CW) {
-            double acc[kTM][kTN];
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int r0 = k0 + w;
+    const int m = n - r0, nc = ncol - r0;
+    if (m <= 0 || nc <= 0 || w != kPB) return;
+    const int nR = (m + 15) >> 4, nG = (nc + 15) >> 4;
+    double af[kUpdRows][kPB / 4];
 #pragma unroll
-            for (int i = 0; i < kTM; ++i)
+    for (int q = 0; q < kUpdRows; ++q) {
+        const int row = r0 + 16 * (wave + kBW * q) + li;
+        const bool ok = (wave + kBW * q) < nR && row < n;
+        const int rc = row < n ? row : n - 1;
 #pragma unroll
-                for (int jj = 0; jj < kTN; ++jj) acc[i][jj] = 0.0;
-            for (int kc = 0; kc < w; kc += kKC) {
-                const int kw = (w - kc) < kKC ? (w - kc) : kKC;
-                // stage L21[:, kc..kc+kw) as Lc[k][i] and U12[kc.., cc0..cc0+CW) as Uc[k][j]
-                // every staging load is issued before the first LDS store
-                // (one memory round trip per stage, not one per element)
-                constexpr int kLq = kKC * kBatchMaxN / kBT, kUq = kKC * kTN * kMaxColGroups / kBT;
-                double lq[kLq], uq[kUq];
+        for (int s4 = 0; s4 < kPB / 4; ++s4) {
+            const double x = a[(size_t)rc + (size_t)(k0 + 4 * s4 + lg) * (size_t)n];
+            af[q][s4] = ok ? -x : 0.0;
+        }
+    }
+    for (int cc0 = 0; cc0 < nc; cc0 += kUpdCols) {
+        // stage U12[:, cc0 .. cc0+128) as Us[k][j] (burst: 8 loads per thread)
+        {
+            constexpr int kQ = kPB * kUpdCols / kBT;
+            double uq[kQ];
 #pragma unroll
-                for (int q = 0; q < kLq; ++q) {
-                    const int e = t + q * kBT;
-                    const int ec = e < kKC * m ? e : kKC * m - 1;
-                    const int i = ec % m, k = ec / m;
-                    const int kk = k < kw ? k : kw - 1;
-                    lq[q] = a[(size_t)(k0 + w + i) + (size_t)(k0 + kc + kk) * (size_t)n];
-                }
-#pragma unroll
-                for (int q = 0; q < kUq; ++q) {
-                    const int e = t + q * kBT;
-                    const int ec = e < kKC * CW ? e : kKC * CW - 1;
-                    const int k = ec % kKC, j = ec / kKC;
-                    const int kk = k < kw ? k : kw - 1;
-                    const int jc = (cc0 + j) < nc ? (cc0 + j) : (nc - 1);
-                    uq[q] = col_ptr(a, b, n, k0 + w + jc)[k0 + kc + kk];
-                }
-#pragma unroll
-                for (int q = 0; q < kLq; ++q) {
-                    const int e = t + q * kBT;
-                    if (e < kKC * m) {
-                        const int i = e % m, k = e / m;
-                        sh.Lc[k][i] = k < kw ? lq[q] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kUq; ++q) {
-                    const int e = t + q * kBT;
-                    if (e < kKC * CW) {
-                        const int k = e % kKC, j = e / kKC;
-                        sh.Uc[k][j] = (k < kw && cc0 + j < nc) ? uq[q] : 0.0;
-                    }
-                }
-                __syncthreads();
-                if (act) {
-                    const int i0 = kTM * tr;
-#pragma unroll 4
-                    for (int k = 0; k < kKC; ++k) {
-                        double lv[kTM], uv[kTN];
-#pragma unroll
-                        for (int i = 0; i < kTM; ++i) lv[i] = sh.Lc[k][(i0 + i) < m ? (i0 + i) : (m - 1)];
-#pragma unroll
-                        for (int jj = 0; jj < kTN; ++jj) uv[jj] = sh.Uc[k][kTN * tc + jj];
-#pragma unroll
-                        for (int i = 0; i < kTM; ++i)
-#pragma unroll
-                            for (int jj = 0; jj < kTN; ++jj) acc[i][jj] = __fma_rn(lv[i], uv[jj], acc[i][jj]);
-                    }
-                }
-                __syncthreads();
+            for (int q = 0; q < kQ; ++q) {
+                const int e = t + q * kBT, k = e % kPB, jj = e / kPB;
+                const int jc = (cc0 + jj) < nc ? (cc0 + jj) : (nc - 1);
+                const double x = col_ptr(a, b, n, r0 + jc)[k0 + k];
+                uq[q] = (cc0 + jj) < nc ? x : 0.0;
             }
-            if (act) {
 #pragma unroll
-                for (int jj = 0; jj < kTN; ++jj) {
-                    const int j = cc0 + kTN * tc + jj;
-                    if (j < nc) {
-                        gf64 *cp = col_ptr(a, b, n, k0 + w + j) + (k0 + w);
-                        double cv[kTM];
+            for (int q = 0; q < kQ; ++q) {
+                const int e = t + q * kBT;
+                sh.Us[e % kPB][e / kPB] = uq[q];
+            }
+        }
+        __syncthreads();
+        const int g0 = cc0 >> 4;
+        const int gn = (nG - g0) < (kUpdCols / 16) ? (nG - g0) : (kUpdCols / 16);
 #pragma unroll
-                        for (int i = 0; i < kTM; ++i) {
-                            const int ii = kTM * tr + i;
-                            cv[i] = cp[ii < m ? ii : m - 1];
-                        }
+        for (int q = 0; q < kUpdRows; ++q) {
+            const int R = wave + kBW * q;
+            if (R < nR) {
+                const int row = r0 + 16 * R + li;
+                const int rc = row < n ? row : n - 1;
+                for (int g = 0; g < gn; ++g) {
+                    const int G = g0 + g;
+                    gf64 *cp[4];
+                    bool cok[4];
+                    d4 acc;
 #pragma unroll
-                        for (int i = 0; i < kTM; ++i)
-                            if (kTM * tr + i < m) cp[kTM * tr + i] = cv[i] - acc[i][jj];
+                    for (int r = 0; r < 4; ++r) {
+                        const int c = r0 + 16 * G + lg + 4 * r;
+                        cok[r] = c < ncol && row < n;
+                        cp[r] = col_ptr(a, b, n, c < ncol ? c : ncol - 1);
+                        acc[r] = cp[r][rc];
                     }
+#pragma unroll
+                    for (int s4 = 0; s4 < kPB / 4; ++s4) {
+                        const double bu = sh.Us[4 * s4 + lg][16 * g + li];
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bu, af[q][s4], acc, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (cok[r]) cp[r][row] = acc[r];
                 }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // U X = Y, 32-row blocks from the bottom (Y = L^{-1} P B is in b)
