@@ -229,14 +229,46 @@ enum hpl_option {
     HPL_OPT_TIMING = 4,      /* 1: time every kernel with HIP events (see hpl_get_stats) */
     HPL_OPT_PROGRESS = 5,    /* k > 0: print a progress line to stderr every k panels */
     HPL_OPT_SERIALIZE = 6,   /* 1: run every step on one stream (debug; bit-identical) */
-    HPL_OPT_GEMM_TILE = 7    /* GEMM kernel variant (default 0 = auto): 1..4 the 4x4x4 tiles
+    HPL_OPT_GEMM_TILE = 7,   /* GEMM kernel variant (default 0 = auto): 1..4 the 4x4x4 tiles
                                 128x128, 128x64, 64x64, 128x32; 5, 6 the streamed 16x16x4
                                 tiles 128x128, 128x64 (where their preconditions hold) */
+    HPL_OPT_HOST_PANEL = 8   /* T > 0: every panel is factored on the host by T threads
+                                (hpl_host_panel; the paper's CPU FACT, Sec. III-A), the
+                                panel copied to pinned host memory and back; with the
+                                look-ahead the whole trailing update of panel j, GEMM
+                                included, overlaps the host FACT of panel j+1.  0
+                                (default): the GPU panel.  Pinned staging: 8 n nb bytes. */
 };
 /* Returns 0, or -1 (bad key) / -2 (bad value); the option is unchanged on error. */
 int hpl_set_option(int key, int64_t value);
 /* Current value of an option, or INT64_MIN for an unknown key. */
 int64_t hpl_get_option(int key);
+
+/*
+ * hpl_host_panel -- the paper's CPU FACT (Sec. III-A): LU with partial
+ * pivoting of an m x nb panel in HOST memory by T threads, the panel split
+ * into tiles of nb rows dealt round-robin to the threads (thread 0 owns the
+ * tile with the diagonal block), recursive right-looking with two halves per
+ * level down to 16 columns.  The comparison variant of the GPU panel.
+ *   1 P       host FP64 m x nb at ldp, overwritten by L (unit, below the
+ *             diagonal) and U (on and above); the rows interchanged across
+ *             all nb columns
+ *   2 m >= 0; 3 1 <= nb <= m (m = 0: nothing to do); 4 ldp >= max(1, m)
+ *   5 ipiv    host int32[nb]: 0-based panel rows, sequential interchanges
+ *   6 threads 1 <= T <= 256
+ *   7 info    host int64*: 0, or k+1 for the first exactly-zero pivot column
+ * Runs on the calling thread plus T-1 threads of its own; no GPU call.
+ */
+int hpl_host_panel(double *P, int64_t m, int64_t nb, int64_t ldp, int32_t *ipiv, int threads, int64_t *info);
+
+/*
+ * hpl_panel_factor -- the same panel factorization on the GPU (the FACT of
+ * hpl_factor: recursive panel, register-resident leaves), for comparison.
+ *   1 A device FP64 m x nb at lda (overwritten as for hpl_host_panel)
+ *   2 m >= 0; 3 1 <= nb <= min(m, 1024); 4 lda >= max(1, m)
+ *   5 ipiv device int32[nb]; 6 info host int64*; 7 hip_stream
+ */
+int hpl_panel_factor(double *A, int64_t m, int64_t nb, int64_t lda, int32_t *ipiv, int64_t *info, void *hip_stream);
 
 /*
  * hpl_batched_sizes -- the sizes of a seeded batch of systems (host only):

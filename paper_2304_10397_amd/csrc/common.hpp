@@ -127,6 +127,10 @@ int launch_residual(const double *A, int64_t lda, bool gen, uint64_t s0, int64_t
                     const double *X, int64_t ldx, const double *B, int64_t ldb, int64_t nrhs,
                     unsigned long long *red, hipStream_t st);
 int launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v, hipStream_t st);
+// the paper's CPU FACT (host memory, T threads)
+constexpr int kHostPanelMaxThreads = 256;
+int host_panel_factor(double *P, int64_t m, int64_t nb, int64_t ld, int32_t *ipiv, int threads, int64_t *info);
+
 // batched small systems (one persistent launch)
 constexpr int kBatchMaxN = 512;
 constexpr int kBatchMaxRhs = 16;

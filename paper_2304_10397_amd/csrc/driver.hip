@@ -66,6 +66,7 @@ static std::atomic<int64_t> opt_timing{0};
 static std::atomic<int64_t> opt_progress{0};
 static std::atomic<int64_t> opt_serialize{0};
 static std::atomic<int64_t> opt_gemm_tile{0};
+static std::atomic<int64_t> opt_host_panel{0};  // threads of the host panel (0: panel on the GPU)
 
 // ---------------------------------------------------------------------------
 // statistics (HPL_OPT_TIMING)
@@ -134,6 +135,8 @@ struct Device {
     int64_t mxp_vec_cap = 0;
     void *bat_ws = nullptr;               // batched systems: sizes, offsets, order, info, queue counter
     size_t bat_cap = 0;
+    double *hp_buf = nullptr;             // host panel: pinned staging of the m x nb panel and its pivots
+    size_t hp_cap = 0;
 };
 
 static std::mutex g_dev_mu;
@@ -287,6 +290,8 @@ struct Ctx {
     int32_t *ipiv;
     int base, gmax, gemm_tile;
     Timer *tm;
+    int host_threads = 0;       // > 0: the panel is factored on the host (the paper's CPU FACT)
+    int64_t host_info = 0;      // first zero pivot (1-based) found by the host panel
 };
 
 // Interchange plans of ipiv[k0 .. k0+cnt) (cnt <= kMaxChunks*kMaxSwaps) into plans[].
@@ -370,6 +375,47 @@ static int panel_full(Ctx &x, int64_t c0, int64_t jb, SwapPlan *plans, hipStream
     return make_plans(x.ipiv + c0, c0, jb, x.n, plans, false, st, x.tm);
 }
 
+// FACT of panel (c0, jb) on the host (the paper's CPU FACT, Sec. III-A): the
+// panel goes to pinned host memory once its columns are up to date in the
+// order of stream st, T threads factor it, and the factors and pivots return
+// on st, followed by the interchange plans.  The calling thread blocks for
+// the copy out and the factorization; work queued earlier on other streams
+// keeps the GPU busy meanwhile.
+static int panel_host(Ctx &x, int64_t c0, int64_t jb, SwapPlan *plans, hipStream_t st)
+{
+    Device *d = x.d;
+    const int64_t m = x.n - c0;
+    const size_t need = sizeof(double) * (size_t)m * (size_t)jb + sizeof(int32_t) * (size_t)jb + 64;
+    if (d->hp_cap < need) {
+        if (d->hp_buf) HPLX_TRY(hipHostFree(d->hp_buf));
+        d->hp_buf = nullptr;
+        d->hp_cap = 0;
+        const size_t cap = sizeof(double) * (size_t)x.n * (size_t)jb + sizeof(int32_t) * (size_t)jb + 64;
+        if (hipHostMalloc((void **)&d->hp_buf, cap, hipHostMallocDefault) != hipSuccess)
+            HPLX_FAIL(HPL_ERR_NOMEM, "host panel staging allocation failed");
+        d->hp_cap = cap;
+    }
+    double *P = d->hp_buf;
+    int32_t *hip_piv = (int32_t *)(P + (size_t)m * (size_t)jb);
+    double *src = x.A + off(c0, c0, x.lda);
+    HPLX_TRY(hipMemcpy2DAsync(P, sizeof(double) * (size_t)m, src, sizeof(double) * (size_t)x.lda,
+                              sizeof(double) * (size_t)m, (size_t)jb, hipMemcpyDeviceToHost, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    int64_t inf = 0;
+    HPLX_PROPAGATE(host_panel_factor(P, m, jb, m, hip_piv, x.host_threads, &inf));
+    if (inf > 0 && (x.host_info == 0 || c0 + inf < x.host_info)) x.host_info = c0 + inf;
+    for (int64_t k = 0; k < jb; ++k) hip_piv[k] += (int32_t)c0;
+    HPLX_TRY(hipMemcpy2DAsync(src, sizeof(double) * (size_t)x.lda, P, sizeof(double) * (size_t)m,
+                              sizeof(double) * (size_t)m, (size_t)jb, hipMemcpyHostToDevice, st));
+    HPLX_TRY(hipMemcpyAsync(x.ipiv + c0, hip_piv, sizeof(int32_t) * (size_t)jb, hipMemcpyHostToDevice, st));
+    return make_plans(x.ipiv + c0, c0, jb, x.n, plans, false, st, x.tm);
+}
+
+static int panel_any(Ctx &x, int64_t c0, int64_t jb, SwapPlan *plans, hipStream_t st)
+{
+    return x.host_threads > 0 ? panel_host(x, c0, jb, plans, st) : panel_full(x, c0, jb, plans, st);
+}
+
 // Trailing GEMM of panel (c0, jb) on columns [col, col+ncols): A22 -= L21 U12.
 static int update_gemm(Ctx &x, int64_t c0, int64_t jb, int64_t col, int64_t ncols, hipStream_t st)
 {
@@ -417,6 +463,7 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
 {
     Timer tm(d, opt_timing.load() != 0);
     Ctx x{d, A, n, lda, ipiv, (int)opt_panel_base.load(), (int)opt_panel_wgs.load(), (int)opt_gemm_tile.load(), &tm};
+    x.host_threads = (int)opt_host_panel.load();
     const int64_t progress = opt_progress.load();
     const int64_t la_mode = opt_lookahead.load();
     const bool la = la_mode != 0 && opt_serialize.load() == 0 && n > nb;
@@ -429,7 +476,7 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
         HPLX_TRY(hipEventRecord(d->ev_start, su));
         HPLX_TRY(hipStreamWaitEvent(sp, d->ev_start, 0));
     }
-    HPLX_PROPAGATE(panel_full(x, 0, nb < n ? nb : n, d->ring[0], sp));
+    HPLX_PROPAGATE(panel_any(x, 0, nb < n ? nb : n, d->ring[0], sp));
     if (la) HPLX_TRY(hipEventRecord(d->ev_panel[0], sp));
 
     for (int64_t j = 0; j < np; ++j) {
@@ -442,7 +489,19 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
         if (c1 < n) {
             const int64_t jb2 = (n - c1) < nb ? (n - c1) : nb;
             SwapPlan *next_plans = d->ring[(j + 1) % kRing];
-            if (la) {
+            if (la && x.host_threads > 0) {
+                // host FACT (the paper's scheme): the whole rest of the update,
+                // GEMM included, is queued first and overlaps the host work;
+                // the next iteration waits for the panel's event
+                HPLX_PROPAGATE(update_cols(x, c0, jb, c1, jb2, plans, su, true));
+                HPLX_TRY(hipEventRecord(d->ev_la[j % kRing], su));
+                HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, n - c1 - jb2, plans, su, true));
+                HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
+                left_done = true;
+                HPLX_TRY(hipStreamWaitEvent(sp, d->ev_la[j % kRing], 0));
+                HPLX_PROPAGATE(panel_host(x, c1, jb2, next_plans, sp));
+                HPLX_TRY(hipEventRecord(d->ev_panel[(j + 1) % kRing], sp));
+            } else if (la) {
                 HPLX_PROPAGATE(update_cols(x, c0, jb, c1, jb2, plans, su, true));
                 HPLX_TRY(hipEventRecord(d->ev_la[j % kRing], su));
                 HPLX_TRY(hipStreamWaitEvent(sp, d->ev_la[j % kRing], 0));
@@ -464,7 +523,7 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
                 }
             } else {
                 HPLX_PROPAGATE(update_cols(x, c0, jb, c1, n - c1, plans, su, true));
-                HPLX_PROPAGATE(panel_full(x, c1, jb2, next_plans, su));
+                HPLX_PROPAGATE(panel_any(x, c1, jb2, next_plans, su));
             }
         }
         // interchanges of panel j on the columns to its left (L in LAPACK form)
@@ -496,7 +555,9 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
         HPLX_FAIL(HPL_ERR_INTERNAL, "panel barrier timed out");
     }
     const unsigned long long iv = d->hbuf[0];
-    *info = (iv == ULLONG_MAX) ? 0 : (int64_t)iv;
+    int64_t inf = (iv == ULLONG_MAX) ? 0 : (int64_t)iv;
+    if (x.host_info > 0 && (inf == 0 || x.host_info < inf)) inf = x.host_info;
+    *info = inf;
     return HPL_OK;
 }
 
@@ -958,6 +1019,10 @@ int hpl_set_option(int key, int64_t value)
         if (value < 0 || value > 6) return -2;
         opt_gemm_tile = value;
         return 0;
+    case HPL_OPT_HOST_PANEL:
+        if (value < 0 || value > kHostPanelMaxThreads) return -2;
+        opt_host_panel = value;
+        return 0;
     default: return -1;
     }
 }
@@ -972,6 +1037,7 @@ int64_t hpl_get_option(int key)
     case HPL_OPT_PROGRESS: return opt_progress;
     case HPL_OPT_SERIALIZE: return opt_serialize;
     case HPL_OPT_GEMM_TILE: return opt_gemm_tile;
+    case HPL_OPT_HOST_PANEL: return opt_host_panel;
     default: return INT64_MIN;
     }
 }
@@ -1124,6 +1190,43 @@ int hpl_batched_solve(int64_t count, const int32_t *sizes, int64_t nrhs, double 
     return tm.collect();
 }
 
+int hpl_host_panel(double *P, int64_t m, int64_t nb, int64_t ldp, int32_t *ipiv, int threads, int64_t *info)
+{
+    if (m < 0) return -2;
+    if (nb < 1 || nb > m) return m == 0 ? (info ? (*info = 0, 0) : -7) : -3;
+    if (m > 0 && P == nullptr) return -1;
+    if (ldp < (m > 1 ? m : 1)) return -4;
+    if (ipiv == nullptr) return -5;
+    if (threads < 1 || threads > kHostPanelMaxThreads) return -6;
+    if (info == nullptr) return -7;
+    return host_panel_factor(P, m, nb, ldp, ipiv, threads, info);
+}
+
+int hpl_panel_factor(double *A, int64_t m, int64_t nb, int64_t lda, int32_t *ipiv, int64_t *info, void *hip_stream)
+{
+    if (m < 0) return -2;
+    if (nb < 1 || nb > 1024 || nb > m) return m == 0 ? (info ? (*info = 0, 0) : -6) : -3;
+    if (A == nullptr) return -1;
+    if (lda < (m > 1 ? m : 1)) return -4;
+    if (ipiv == nullptr) return -5;
+    if (info == nullptr) return -6;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    hipStream_t st = (hipStream_t)hip_stream;
+    Timer tm(d, opt_timing.load() != 0);
+    Ctx x{d, A, m, lda, ipiv, (int)opt_panel_base.load(), (int)opt_panel_wgs.load(), (int)opt_gemm_tile.load(), &tm};
+    HPLX_PROPAGATE(launch_fill_u64(d->sync.info, 1, ULLONG_MAX, st));
+    HPLX_PROPAGATE(panel_full(x, 0, nb, d->ring[0], st));
+    HPLX_TRY(hipMemcpyAsync(d->hbuf, d->sync.info, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HPLX_TRY(hipMemcpyAsync(d->hbuf + 1, d->sync.abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HPLX_TRY(hipStreamSynchronize(st));
+    HPLX_PROPAGATE(tm.collect());
+    if (*(int *)(d->hbuf + 1)) HPLX_FAIL(HPL_ERR_INTERNAL, "panel barrier timed out");
+    const unsigned long long iv = d->hbuf[0];
+    *info = (iv == ULLONG_MAX) ? 0 : (int64_t)iv;
+    return HPL_OK;
+}
+
 int hpl_release(void)
 {
     std::lock_guard<std::mutex> lk(g_dev_mu);
@@ -1149,6 +1252,7 @@ int hpl_release(void)
         if (d.mxp_ws) (void)hipFree(d.mxp_ws);
         if (d.mxp_vec) (void)hipFree(d.mxp_vec);
         if (d.bat_ws) (void)hipFree(d.bat_ws);
+        if (d.hp_buf) (void)hipHostFree(d.hp_buf);
         if (d.hbuf) (void)hipHostFree(d.hbuf);
         (void)hipFree(d.ws);
         d = Device();

@@ -28,6 +28,7 @@ HPL_OPT_TIMING = 4
 HPL_OPT_PROGRESS = 5
 HPL_OPT_SERIALIZE = 6
 HPL_OPT_GEMM_TILE = 7
+HPL_OPT_HOST_PANEL = 8
 
 STAT_CLASSES = ("gemm", "panel", "laswp", "trsm", "solve", "plan", "mxp_gemm", "mxp_fact", "grad_a", "batched")
 
@@ -71,6 +72,8 @@ def _load():
         "hpl_mxp_factor": (i32, [P, i64, i64, i64, i32, P, i64, P, P]),
         "hpl_mxp_solve": (i32, [P, i64, P, i64, i64, P, P, i64, P, P]),
         "hpl_batched_sizes": (i32, [u64, i64, ctypes.c_int32, ctypes.c_int32, P]),
+        "hpl_host_panel": (i32, [P, i64, i64, i64, P, i32, P]),
+        "hpl_panel_factor": (i32, [P, i64, i64, i64, P, P, P]),
         "hpl_batched_solve": (i32, [i64, P, i64, P, P, P, P, P, P, i32, P, P]),
         "hpl_release": (i32, []),
         "hpl_strerror": (ctypes.c_char_p, [i32]),
@@ -88,6 +91,7 @@ EXPORTED = ("hpl_factor", "hpl_solve", "hpl_residual", "hpl_residual_gen", "hpl_
             "hpl_set_option", "hpl_get_option", "hpl_get_stats", "hpl_reset_stats",
             "hpl_mfma_peak", "hpl_solve_grad_a", "hpl_generate_normal", "hpl_add_diagonal",
             "hpl_mxp_generate", "hpl_mxp_factor", "hpl_mxp_solve", "hpl_batched_sizes", "hpl_batched_solve",
+            "hpl_host_panel", "hpl_panel_factor",
             "hpl_release", "hpl_strerror", "hpl_last_error_detail")
 
 
@@ -291,6 +295,35 @@ def hpl_mxp_solve(A, LU, b, x=None, max_iter=50, stream=None):
                                                 int(max_iter), out.ctypes.data_as(ctypes.c_void_p),
                                                 _stream(stream)))
     return x, out
+
+
+def hpl_host_panel(P, threads, ipiv=None):
+    """The paper's CPU FACT of the m x nb panel P (numpy float64, Fortran order, in place)
+    with T threads; returns (ipiv int32[nb] 0-based, info)."""
+    if not (isinstance(P, np.ndarray) and P.dtype == np.float64 and P.ndim == 2):
+        raise TypeError("P must be a 2-D float64 numpy array")
+    if P.shape[0] > 1 and P.strides[0] != 8:
+        raise TypeError("P must be column-major (Fortran order)")
+    m, nb = P.shape
+    ldp = max(1, P.strides[1] // 8 if nb > 1 else m, m)
+    ipiv = np.zeros(max(nb, 1), dtype=np.int32) if ipiv is None else ipiv
+    info = ctypes.c_int64(0)
+    _check("hpl_host_panel", _lib.hpl_host_panel(P.ctypes.data_as(ctypes.c_void_p), m, nb, ldp,
+                                                  ipiv.ctypes.data_as(ctypes.c_void_p), int(threads),
+                                                  ctypes.byref(info)))
+    return ipiv[:nb], int(info.value)
+
+
+def hpl_panel_factor(A, ipiv=None, stream=None):
+    """GPU FACT of the m x nb column-major CUDA panel A (in place); returns (ipiv, info)."""
+    torch = _torch()
+    pA, m, nb, lda = _matrix("A", A)
+    if ipiv is None:
+        ipiv = torch.empty(max(nb, 1), dtype=torch.int32, device=A.device)
+    info = ctypes.c_int64(0)
+    _check("hpl_panel_factor", _lib.hpl_panel_factor(pA, m, nb, lda, ctypes.c_void_p(ipiv.data_ptr()),
+                                                      ctypes.byref(info), _stream(stream)))
+    return ipiv[:nb], int(info.value)
 
 
 BATCH_FORWARD, BATCH_ADJOINT, BATCH_BOTH = 1, 2, 3
