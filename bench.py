@@ -367,6 +367,98 @@ def bench_batched(args, torch, h):
     print(json.dumps(out), flush=True)
 
 
+def bench_hostpanel(args, torch, h):
+    """The paper's host FACT (T threads over NB-row tiles) against the GPU panel:
+    (1) FACT of an M x 512 panel for M = 512 .. 32768 (the tail of a run has the
+    small M); (2) factor + solve at N = 32768, NB = 512, once with each FACT,
+    the host one overlapping the trailing update as in the paper."""
+    import numpy as np
+    nb = 512
+    threads = [1, 4, 16]
+    Ms = [512, 1024, 2048, 4096, 8192, 16384, 32768]
+    rows = []
+    last = {}
+    for M in Ms:
+        G = h.colmajor(M, nb)
+        h.hpl_generate(args.seed, 0, G)
+        P0 = np.asfortranarray(G.cpu().numpy())
+        flops = M * nb * nb - nb ** 3 / 3.0
+        row = {"M": M}
+        for T in threads:
+            if T in last and last[T] * 2.2 > 5.0:   # keep the host part of the run short
+                row[f"host_T{T}_gflops"] = None
+                continue
+            P = P0.copy(order="F")
+            t0 = time.perf_counter()
+            h.hpl_host_panel(P, T)
+            dt = time.perf_counter() - t0
+            last[T] = dt
+            row[f"host_T{T}_gflops"] = round(flops / dt / 1e9, 2)
+        best = 1e30
+        for _ in range(3):
+            A = G.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.hpl_panel_factor(A)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        row["gpu_gflops"] = round(flops / best / 1e9, 2)
+        rows.append(row)
+        log(f"FACT M={M}: {row}")
+    n = 32768
+    runs = {}
+    for label, T in (("gpu_panel", 0), ("host_panel_T16", 16)):
+        h.hpl_set_option(h.HPL_OPT_HOST_PANEL, T)
+        A = h.colmajor(n, n)
+        h.hpl_generate(args.seed, 0, A)
+        b = h.colmajor(n, 1)
+        h.hpl_generate(args.seed, 1, b)
+        torch.cuda.synchronize()
+        h.hpl_reset_stats()
+        h.hpl_set_option(h.HPL_OPT_TIMING, 1)
+        t0 = time.perf_counter()
+        ipiv, info = h.hpl_factor(A, nb)
+        h.hpl_solve(A, ipiv, b)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h.hpl_set_option(h.HPL_OPT_TIMING, 0)
+        st = h.hpl_get_stats()
+        A0 = h.colmajor(n, n)
+        h.hpl_generate(args.seed, 0, A0)
+        b0 = h.colmajor(n, 1)
+        h.hpl_generate(args.seed, 1, b0)
+        res = h.hpl_residual(A0, b, b0)
+        del A0, A
+        runs[label] = {"seconds": round(dt, 4), "tflops": round(hpl_flops(n) / dt / 1e12, 3),
+                       "fact_ms_total": round(st["panel"]["ms"], 2), "fact_launches": st["panel"]["launches"],
+                       "gemm_ms": round(st["gemm"]["ms"], 2), "scaled_residual": float(res[0]), "info": int(info)}
+        log(f"{label}: {runs[label]}")
+    h.hpl_set_option(h.HPL_OPT_HOST_PANEL, 0)
+    g = runs["host_panel_T16"]
+    out = {
+        "metric": "HPL with the paper's host FACT (16 threads, NB-row tiles): TFLOP/s at N=32768, against the GPU panel",
+        "value": g["tflops"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(1e3 * g["seconds"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"HPL FP64 LU+solve, N={n}, NB={nb}, look-ahead 1, A,b ~ U[-0.5,0.5) seed {args.seed}; "
+                        "FACT of M x 512 panels on the host (T threads) and on the GPU",
+            "n": n, "nb": nb, "runs": runs, "fact_gflops_by_M": rows,
+            "host_threads_note": "the host FACT runs on the box's CPU share (16 cores)",
+        },
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -380,7 +472,7 @@ def main():
     ap.add_argument("--pad", type=int, default=0, help="lda = n + pad")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="N of the oracle sample (0: skip)")
     ap.add_argument("--progress", type=int, default=32, help="progress line every k panels (stderr)")
-    ap.add_argument("--workload", choices=["hpl", "diffsolve", "mxp", "batched"], default="hpl",
+    ap.add_argument("--workload", choices=["hpl", "diffsolve", "mxp", "batched", "hostpanel"], default="hpl",
                     help="hpl: the HPL factor + solve (default); diffsolve: the differentiable FP64 "
                          "solve, N=8192 NB=256 16 right-hand sides, forward + backward; mxp: mixed-precision "
                          "LU + FP64 refinement at N=65536 against the FP64 path on the same matrix")
@@ -414,6 +506,8 @@ def main():
         return bench_mxp(args, torch, h)
     if args.workload == "batched":
         return bench_batched(args, torch, h)
+    if args.workload == "hostpanel":
+        return bench_hostpanel(args, torch, h)
     n, nb = args.n, args.nb
     log(f"device {torch.cuda.get_device_name(dev)}; N={n} NB={nb} look-ahead={args.lookahead}")
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, args.lookahead)

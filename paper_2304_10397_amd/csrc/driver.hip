@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -400,9 +401,19 @@ static int panel_host(Ctx &x, int64_t c0, int64_t jb, SwapPlan *plans, hipStream
     double *src = x.A + off(c0, c0, x.lda);
     HPLX_TRY(hipMemcpy2DAsync(P, sizeof(double) * (size_t)m, src, sizeof(double) * (size_t)x.lda,
                               sizeof(double) * (size_t)m, (size_t)jb, hipMemcpyDeviceToHost, st));
+    const auto th0 = std::chrono::steady_clock::now();
     HPLX_TRY(hipStreamSynchronize(st));
     int64_t inf = 0;
     HPLX_PROPAGATE(host_panel_factor(P, m, jb, m, hip_piv, x.host_threads, &inf));
+    if (opt_timing.load()) {  // the panel class: copy out + host FACT, wall time
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
+        const double mm = (double)m, w = (double)jb;
+        std::lock_guard<std::mutex> lk(g_st_mu);
+        g_st_launch[ST_PANEL] += 1;
+        g_st_ms[ST_PANEL] += ms;
+        g_st_flops[ST_PANEL] += mm * w * w - w * w * w / 3.0;
+        g_st_bytes[ST_PANEL] += 16.0 * mm * w;
+    }
     if (inf > 0 && (x.host_info == 0 || c0 + inf < x.host_info)) x.host_info = c0 + inf;
     for (int64_t k = 0; k < jb; ++k) hip_piv[k] += (int32_t)c0;
     HPLX_TRY(hipMemcpy2DAsync(src, sizeof(double) * (size_t)x.lda, P, sizeof(double) * (size_t)m,

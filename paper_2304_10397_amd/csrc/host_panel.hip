@@ -70,14 +70,14 @@ struct HostPanel {
     }
     double &at(int64_t i, int64_t j) { return P[i + j * ld]; }
 
-    // rows [lo, m) owned by thread tid, visited tile by tile
-    template <typename F> void own_rows(int tid, int64_t lo, F &&f)
+    // row ranges [r0, r1) within [lo, m) owned by thread tid, tile by tile
+    template <typename F> void own_ranges(int tid, int64_t lo, F &&f)
     {
         const int64_t ntiles = (m + nb - 1) / nb;
         for (int64_t tile = tid; tile < ntiles; tile += T) {
             int64_t r0 = tile * nb, r1 = r0 + nb < m ? r0 + nb : m;
             if (r0 < lo) r0 = lo;
-            for (int64_t i = r0; i < r1; ++i) f(i);
+            if (r0 < r1) f(r0, r1);
         }
     }
 
@@ -86,11 +86,14 @@ struct HostPanel {
         for (int64_t k = c; k < c + w; ++k) {
             double best = -1.0;
             int64_t brow = -1;
-            own_rows(tid, k, [&](int64_t i) {
-                const double v = std::fabs(at(i, k));
-                if (v > best) {  // rows visited in increasing order: the first maximum is the lowest row
-                    best = v;
-                    brow = i;
+            own_ranges(tid, k, [&](int64_t r0, int64_t r1) {
+                const double *col = &at(0, k);
+                for (int64_t i = r0; i < r1; ++i) {
+                    const double v = std::fabs(col[i]);
+                    if (v > best) {  // rows visited in increasing order: the first maximum is the lowest row
+                        best = v;
+                        brow = i;
+                    }
                 }
             });
             cval[tid] = best;
@@ -118,10 +121,15 @@ struct HostPanel {
             bar.wait();
             const double pv = piv;
             if (pv != 0.0) {
-                own_rows(tid, k + 1, [&](int64_t i) {
-                    const double l = at(i, k) / pv;
-                    at(i, k) = l;
-                    for (int64_t j = k + 1; j < c + w; ++j) at(i, j) = at(i, j) - l * at(k, j);
+                // l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj column by column
+                own_ranges(tid, k + 1, [&](int64_t r0, int64_t r1) {
+                    double *lk = &at(0, k);
+                    for (int64_t i = r0; i < r1; ++i) lk[i] = lk[i] / pv;
+                    for (int64_t j = k + 1; j < c + w; ++j) {
+                        const double u = at(k, j);
+                        double *cj = &at(0, j);
+                        for (int64_t i = r0; i < r1; ++i) cj[i] = cj[i] - lk[i] * u;
+                    }
                 });
             }
         }
@@ -147,12 +155,16 @@ struct HostPanel {
                     at(i, j) = s;
                 }
         bar.wait();
-        // A22 -= L21 U12 on every thread's rows below the first half
-        own_rows(tid, c + w1, [&](int64_t i) {
+        // A22 -= L21 U12 on every thread's rows below the first half: each
+        // element takes its products in k order, a column axpy per k
+        own_ranges(tid, c + w1, [&](int64_t r0, int64_t r1) {
             for (int64_t j = c + w1; j < c + w; ++j) {
-                double s = at(i, j);
-                for (int64_t k = c; k < c + w1; ++k) s = s - at(i, k) * at(k, j);
-                at(i, j) = s;
+                double *cj = &at(0, j);
+                for (int64_t k = c; k < c + w1; ++k) {
+                    const double u = at(k, j);
+                    const double *lk = &at(0, k);
+                    for (int64_t i = r0; i < r1; ++i) cj[i] = cj[i] - lk[i] * u;
+                }
             }
         });
         bar.wait();
