@@ -86,7 +86,7 @@ struct BatchShared {
     int perm[kBatchMaxN];                  // row permutation: row i of P A is row perm[i] of A
     int slot_row[kMaxSlots];               // interchange composition: destination rows ...
     int slot_src[kMaxSlots];               // ... and the original row each receives
-    int slotmap[kBatchMaxN];               // row -> its slot for rows below the panel (-1: none)
+    int pivs[kPB];                         // the panel's pivot rows, in column order
     int nslots;
     int64_t info;
     int64_t job;
@@ -120,16 +120,6 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
     const int w = (n - k0) < kPB ? (n - k0) : kPB;
     const int r = k0 + t;
     const bool own = r < n;
-    for (int i = t; i < n; i += kBT) sh.slotmap[i] = -1;
-    if (t == 0) {
-        // slots 0..w-1 are the panel's rows; pivot rows below the panel
-        // are appended (only when w == kPB: otherwise every row is in it)
-        sh.nslots = w;
-        for (int q = 0; q < w; ++q) {
-            sh.slot_row[q] = k0 + q;
-            sh.slot_src[q] = k0 + q;
-        }
-    }
     double v[kPB];
     {
         const int rr = own ? r : n - 1;
@@ -140,7 +130,7 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
             v[q] = (own && q < w) ? x : 0.0;
         }
     }
-    __syncthreads();  // slot lists and map initialised
+    __syncthreads();
     for (int j = 0; j < w; ++j) {
         const int par = j & 1;
         // wave argmax of |v[0]| over rows >= k0+j; ties: the lowest row (lane)
@@ -188,28 +178,7 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
                 for (int q = 0; q < kPB; ++q) v[q] = sh.drow[par][q];
             }
         }
-        if (t == 0) {
-            ip[k0 + j] = gp;
-            if (gp != k0 + j) {
-                const int pk = sh.perm[k0 + j];
-                sh.perm[k0 + j] = sh.perm[gp];
-                sh.perm[gp] = pk;
-                int s2;
-                if (gp < k0 + kPB) {
-                    s2 = gp - k0;
-                } else if (sh.slotmap[gp] >= 0) {
-                    s2 = sh.slotmap[gp];
-                } else {
-                    s2 = sh.nslots++;
-                    sh.slotmap[gp] = s2;
-                    sh.slot_row[s2] = gp;
-                    sh.slot_src[s2] = gp;
-                }
-                const int tmp = sh.slot_src[j];
-                sh.slot_src[j] = sh.slot_src[s2];
-                sh.slot_src[s2] = tmp;
-            }
-        }
+        if (t == 0) sh.pivs[j] = gp;  // composed after the loop (off the per-column path)
         const double piv = u[0];
         if (piv == 0.0) {
             if (t == 0 && sh.info == 0) sh.info = k0 + j + 1;  // column left unscaled
@@ -233,6 +202,55 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
 #pragma unroll
         for (int q = 0; q < kPB - 1; ++q) v[q] = v[q + 1];
         v[kPB - 1] = c0;
+    }
+    // the panel's interchanges composed by wave 0: lane j follows destination
+    // row k0+j (and, if it is the first occurrence of a pivot row below the
+    // panel, that row) back through the transpositions, last first, to the
+    // original row it receives; the row permutation and the slot lists of the
+    // interchange pass follow, and ipiv is written
+    __syncthreads();
+    if (wave == 0) {
+        int g[kPB];
+#pragma unroll
+        for (int q = 0; q < kPB; ++q) g[q] = q < w ? sh.pivs[q] : -1;
+        const int j = lane;
+        int gj = -1;
+#pragma unroll
+        for (int q = 0; q < kPB; ++q)
+            if (q == j) gj = g[q];
+        bool isx = j < w && gj >= k0 + w;
+#pragma unroll
+        for (int q = 0; q < kPB; ++q)
+            if (q < j && g[q] == gj) isx = false;
+        const unsigned long long bx = __ballot(isx);
+        const int nx = __popcll(bx);
+        const int xi = __popcll(bx & ((1ull << j) - 1ull));
+        auto sigma = [&](int d) {
+#pragma unroll
+            for (int q = kPB - 1; q >= 0; --q)
+                if (q < w) {
+                    if (d == k0 + q)
+                        d = g[q];
+                    else if (d == g[q])
+                        d = k0 + q;
+                }
+            return d;
+        };
+        const int d0 = k0 + (j < w ? j : 0), s0 = sigma(d0);
+        const int dx = isx ? gj : d0, sx = sigma(dx);
+        const int p0 = sh.perm[s0], px = sh.perm[sx];  // every read before any write
+        if (j < w) {
+            sh.slot_row[j] = d0;
+            sh.slot_src[j] = s0;
+            ip[k0 + j] = gj;
+        }
+        if (isx) {
+            sh.slot_row[w + xi] = dx;
+            sh.slot_src[w + xi] = sx;
+        }
+        if (j == 0) sh.nslots = w + nx;
+        if (j < w) sh.perm[d0] = p0;
+        if (isx) sh.perm[dx] = px;
     }
     // write the factored panel back; L11 to LDS
     if (own) {
