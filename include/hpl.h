@@ -196,6 +196,9 @@ int hpl_mxp_generate(uint64_t seed, double *A, int64_t n, int64_t lda, void *hip
  *   7 ldlu >= max(1, n)
  *   8 info host int64*: 0, or k+1 for the first exactly-zero diagonal of U
  *   9 hip_stream
+ * With HPL_OPT_LOOKAHEAD non-zero the update of the next panel's columns runs
+ * first and that panel's FACT overlaps the rest of the update on a second
+ * stream; the factors are bitwise those of the plain schedule.
  * Workspace: 4 n nb bytes (the FP16/BF16 copies of L21 and U12), kept per device.
  */
 int hpl_mxp_factor(const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU,
@@ -223,7 +226,9 @@ int hpl_mxp_solve(const double *A, int64_t lda, const float *LU, int64_t ldlu, i
 enum hpl_option {
     HPL_OPT_LOOKAHEAD = 1,   /* 0: none.  1 (default): panel j+1 is factored while the
                                 RS/TRSM of panel j finish; the trailing GEMM starts when
-                                the panel is done.  2: the panel also overlaps the GEMM. */
+                                the panel is done.  2: the panel also overlaps the GEMM.
+                                hpl_mxp_factor: 1 and 2 both overlap the next FACT with
+                                the trailing update (it has no RS to overlap). */
     HPL_OPT_PANEL_BASE = 2,  /* leaf width of the recursive panel: 8, 16, 32 or 64 (default 32) */
     HPL_OPT_PANEL_WGS = 3,   /* max workgroups of the panel leaf kernel, 1..256 (default 256) */
     HPL_OPT_TIMING = 4,      /* 1: time every kernel with HIP events (see hpl_get_stats) */

@@ -667,6 +667,13 @@ static int mxp_panel(float *A, int64_t lda, int64_t n, int64_t c, int64_t w, uns
     return mxp_panel(A, lda, n, c + w1, w2, info, st);
 }
 
+// One step of the mixed-precision factorization is FACT of the panel (FP32),
+// U12 = L11^{-1} A12 (FP32), the scaling and conversion of -L21 and U12 to
+// FP16/BF16, and A22 += (-L21) U12 on the matrix cores.  With look-ahead
+// (Sec. III) the update of the next panel's columns goes first; the panel
+// stream then factors that panel while the main stream updates the remaining
+// columns, and the next U12 waits for both.  Every element takes the same
+// operations in the same order either way, so the factors are bitwise equal.
 static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU,
                            int64_t ldlu, int64_t *info, hipStream_t st)
 {
@@ -679,29 +686,58 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
     unsigned *mx = (unsigned *)(ws + sc_off);
     int *sexp = (int *)(ws + sc_off + 16);
     unsigned long long *dinfo = (unsigned long long *)(ws + sc_off + 32);
+    const bool la = opt_lookahead.load() != 0 && opt_serialize.load() == 0 && n > nb;
+    hipStream_t sp = la ? d->sp : st;
     Timer tm(d, opt_timing.load() != 0);
+    // FACT of the panel at c (width w), on stream s
+    auto fact = [&](int64_t c, int64_t w, hipStream_t s) -> int {
+        const int id = tm.begin(ST_MXP_FACT, s);
+        HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c, w, dinfo, s));
+        return tm.end(id, s, (double)(n - c) * (double)w * (double)w, 4.0 * (double)(n - c) * (double)w * 2.0);
+    };
+    // U12 of the panel at c and the low-precision copies of -L21 and U12
+    auto prep = [&](int64_t c, int64_t w) -> int {
+        const int64_t c1 = c + w, m = n - c1;
+        const int id = tm.begin(ST_MXP_FACT, st);
+        HPLX_PROPAGATE(mxp_trsm(LU + off(c, c, ldlu), ldlu, w, LU + off(c, c1, ldlu), ldlu, m, st));
+        HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)w, mx,
+                                        sexp, st));
+        HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)w,
+                                          sexp, A16, B16, st));
+        return tm.end(id, st, (double)w * (double)w * (double)m, 4.0 * (double)w * (double)m * 2.0);
+    };
+    // A22 columns [c1 + j0, c1 + j0 + nc) += (-L21) U12 of the panel at c0 (width w)
+    auto update = [&](int64_t c1, int64_t w, int64_t j0, int64_t nc) -> int {
+        const int64_t m = n - c1;
+        const int id = tm.begin(ST_MXP_GEMM, st);
+        HPLX_PROPAGATE(launch_hgemm_update(fmt, m, nc, w, A16, (const uint16_t *)B16 + (size_t)j0 * (size_t)w,
+                                           LU + off(c1, c1 + j0, ldlu), ldlu, st));
+        return tm.end(id, st, 2.0 * (double)m * (double)nc * (double)w,
+                      8.0 * (double)m * (double)nc + 2.0 * (double)w * (double)(m + nc));
+    };
     HPLX_PROPAGATE(launch_fill_u64(dinfo, 1, ULLONG_MAX, st));
     HPLX_PROPAGATE(launch_cvt_f64_f32(A, lda, LU, ldlu, n, n, st));
+    HPLX_PROPAGATE(fact(0, nb < n ? nb : n, st));
     for (int64_t c0 = 0; c0 < n; c0 += nb) {
         const int64_t w = (n - c0) < nb ? (n - c0) : nb;
         const int64_t c1 = c0 + w;
-        const int64_t m = n - c1;
-        int id = tm.begin(ST_MXP_FACT, st);
-        HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c0, w, dinfo, st));
-        if (c1 < n) {
-            HPLX_PROPAGATE(mxp_trsm(LU + off(c0, c0, ldlu), ldlu, w, LU + off(c0, c1, ldlu), ldlu, m, st));
-            HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c0, ldlu), ldlu, m, LU + off(c0, c1, ldlu), ldlu, m, (int)w,
-                                            mx, sexp, st));
-            HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c0, ldlu), ldlu, m, LU + off(c0, c1, ldlu), ldlu, m,
-                                              (int)w, sexp, A16, B16, st));
-        }
-        HPLX_PROPAGATE(tm.end(id, st, (double)(n - c0) * (double)w * (double)w + (double)w * (double)w * (double)m,
-                              4.0 * (double)(n - c0) * (double)w * 2.0 + 4.0 * (double)w * (double)m * 2.0));
         if (c1 >= n) break;
-        id = tm.begin(ST_MXP_GEMM, st);
-        HPLX_PROPAGATE(launch_hgemm_update(fmt, m, m, w, A16, B16, LU + off(c1, c1, ldlu), ldlu, st));
-        HPLX_PROPAGATE(tm.end(id, st, 2.0 * (double)m * (double)m * (double)w,
-                              8.0 * (double)m * (double)m + 4.0 * (double)w * (double)m));
+        const int64_t m = n - c1;
+        const int64_t w2 = m < nb ? m : nb;  // width of the next panel
+        HPLX_PROPAGATE(prep(c0, w));
+        const int r = (int)((c0 / nb) % kRing);
+        if (la) {
+            HPLX_PROPAGATE(update(c1, w, 0, w2));
+            HPLX_TRY(hipEventRecord(d->ev_la[r], st));
+            HPLX_TRY(hipStreamWaitEvent(sp, d->ev_la[r], 0));
+            HPLX_PROPAGATE(fact(c1, w2, sp));
+            HPLX_TRY(hipEventRecord(d->ev_panel[r], sp));
+            if (m > w2) HPLX_PROPAGATE(update(c1, w, w2, m - w2));
+            HPLX_TRY(hipStreamWaitEvent(st, d->ev_panel[r], 0));
+        } else {
+            HPLX_PROPAGATE(update(c1, w, 0, m));
+            HPLX_PROPAGATE(fact(c1, w2, st));
+        }
     }
     unsigned long long hinfo = 0;
     HPLX_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof hinfo, hipMemcpyDeviceToHost, st));

@@ -46,6 +46,25 @@ def test_mxp_factor_dyadic_exact(n, nb, fmt):
     assert np.array_equal(np.triu(LUh), U)
 
 
+@pytest.mark.parametrize("n,nb", [(64, 64), (130, 64), (1000, 128), (3000, 512), (4160, 1024)])
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_mxp_factor_lookahead_bitwise(n, nb, fmt):
+    """The look-ahead schedule (next panel's columns first, its FACT on the panel
+    stream beside the rest of the update) gives the bits of the plain schedule."""
+    h = hpl()
+    A, _ = gpu_mxp_system(n, 9)
+    old = h.hpl_get_option(h.HPL_OPT_LOOKAHEAD)
+    try:
+        h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 0)
+        LU0, info0 = h.hpl_mxp_factor(A, nb=nb, fmt=fmt)
+        h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 1)
+        LU1, info1 = h.hpl_mxp_factor(A, nb=nb, fmt=fmt)
+    finally:
+        h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, old)
+    assert info0 == info1 == 0
+    assert np.array_equal(LU0.cpu().numpy().view(np.int32), LU1.cpu().numpy().view(np.int32))
+
+
 @pytest.mark.parametrize("n,nb", [(256, 64), (1000, 128), (1536, 512)])
 @pytest.mark.parametrize("fmt", [0, 1])
 def test_mxp_factor_vs_oracle(n, nb, fmt):
