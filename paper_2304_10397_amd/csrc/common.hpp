@@ -231,7 +231,7 @@ int launch_mxp_diag(double *A, int64_t n, int64_t lda, hipStream_t st);
 int launch_cvt_f64_f32(const double *A, int64_t lda, float *B, int64_t ldb, int64_t rows, int64_t cols,
                        hipStream_t st);
 int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsigned long long *info,
-                        hipStream_t st);
+                        unsigned *done, hipStream_t st);
 int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st);
 int launch_sgemm32(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B, int64_t ldb,
                    float *C, int64_t ldc, hipStream_t st);

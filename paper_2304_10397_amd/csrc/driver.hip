@@ -654,17 +654,18 @@ static int mxp_trsm(const float *L, int64_t ldl, int64_t nbk, float *B, int64_t 
 }
 
 // FACT of columns [c, c+w), rows [c, n), no pivoting, FP32: recursive halves.
-static int mxp_panel(float *A, int64_t lda, int64_t n, int64_t c, int64_t w, unsigned long long *info, hipStream_t st)
+static int mxp_panel(float *A, int64_t lda, int64_t n, int64_t c, int64_t w, unsigned long long *info, unsigned *done,
+                     hipStream_t st)
 {
-    if (w <= 32) return launch_panel32_leaf(A, lda, c, n, (int)w, info, st);
+    if (w <= 32) return launch_panel32_leaf(A, lda, c, n, (int)w, info, done, st);
     int64_t w1 = ((w / 2 + 31) / 32) * 32;
     if (w1 >= w) w1 = w - 1;
     const int64_t w2 = w - w1;
-    HPLX_PROPAGATE(mxp_panel(A, lda, n, c, w1, info, st));
+    HPLX_PROPAGATE(mxp_panel(A, lda, n, c, w1, info, done, st));
     HPLX_PROPAGATE(mxp_trsm(A + off(c, c, lda), lda, w1, A + off(c, c + w1, lda), lda, w2, st));
     HPLX_PROPAGATE(launch_sgemm32(n - c - w1, w2, w1, A + off(c + w1, c, lda), lda, A + off(c, c + w1, lda), lda,
                                   A + off(c + w1, c + w1, lda), lda, st));
-    return mxp_panel(A, lda, n, c + w1, w2, info, st);
+    return mxp_panel(A, lda, n, c + w1, w2, info, done, st);
 }
 
 // One step of the mixed-precision factorization is FACT of the panel (FP32),
@@ -686,13 +687,14 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
     unsigned *mx = (unsigned *)(ws + sc_off);
     int *sexp = (int *)(ws + sc_off + 16);
     unsigned long long *dinfo = (unsigned long long *)(ws + sc_off + 32);
+    unsigned *leaf_done = (unsigned *)(ws + sc_off + 64);  // panel leaf's workgroup count (returns to zero)
     const bool la = opt_lookahead.load() != 0 && opt_serialize.load() == 0 && n > nb;
     hipStream_t sp = la ? d->sp : st;
     Timer tm(d, opt_timing.load() != 0);
     // FACT of the panel at c (width w), on stream s
     auto fact = [&](int64_t c, int64_t w, hipStream_t s) -> int {
         const int id = tm.begin(ST_MXP_FACT, s);
-        HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c, w, dinfo, s));
+        HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c, w, dinfo, leaf_done, s));
         return tm.end(id, s, (double)(n - c) * (double)w * (double)w, 4.0 * (double)(n - c) * (double)w * 2.0);
     };
     // U12 of the panel at c and the low-precision copies of -L21 and U12
@@ -716,6 +718,7 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
                       8.0 * (double)m * (double)nc + 2.0 * (double)w * (double)(m + nc));
     };
     HPLX_PROPAGATE(launch_fill_u64(dinfo, 1, ULLONG_MAX, st));
+    HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)leaf_done, 1, 0ull, st));
     HPLX_PROPAGATE(launch_cvt_f64_f32(A, lda, LU, ldlu, n, n, st));
     HPLX_PROPAGATE(fact(0, nb < n ? nb : n, st));
     for (int64_t c0 = 0; c0 < n; c0 += nb) {

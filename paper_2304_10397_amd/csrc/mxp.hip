@@ -44,72 +44,68 @@ __global__ __launch_bounds__(256) void cvt_f64_f32_kernel(const double *__restri
 }
 
 // ---------------------------------------------------------------------------
-// FP32 panel leaf (w <= 32 columns, rows [c, n)): every workgroup factors the
-// w x w diagonal block in LDS without pivoting (row t owned by thread t; step
-// k divides column k and updates the rows below), then each thread solves one
-// row below the block: x U11 = a, x_j = (a_j - sum_{k<j} x_k u_kj) / u_jj with
-// the sum taken as successive subtractions in k order.  Workgroup 0 writes the
-// factored block back; info records the first zero diagonal.
+// FP32 panel leaf (w <= 32 columns, rows [c, n)), no pivoting.  Every row takes
+// the same right-looking steps: at step k a row i > k divides its entry k by
+// u_kk and subtracts that multiple of the pivot row from its entries q > k (a
+// zero u_kk leaves the column as is; info reports it).  Each thread holds one
+// row in registers: in every workgroup, threads 0..31 hold the rows of the
+// w x w diagonal block (recomputed by each workgroup) and threads 32..255 the
+// rows below it, 224 per workgroup.  At step k thread k publishes its row (the
+// final row k of U) to a double-buffered LDS row, so one barrier per step
+// suffices.  Every workgroup reads the diagonal block as input, so it is
+// written back only by the last workgroup to finish (counted on *done, which
+// wraps to zero at the end of each launch).
 // ---------------------------------------------------------------------------
-constexpr int kLw = 32;
+constexpr int kLw = 32, kLeafRows = 256 - kLw;
 
 __global__ __launch_bounds__(256) void panel32_leaf_kernel(float *__restrict__ A, int64_t lda, int64_t c,
-                                                           int64_t n, int w, unsigned long long *__restrict__ info)
+                                                           int64_t n, int w, unsigned long long *__restrict__ info,
+                                                           unsigned *__restrict__ done)
 {
-    __shared__ float D[kLw][kLw + 1];
+    __shared__ float P[2][kLw];
+    __shared__ int last;
     const int t = threadIdx.x;
-    static_assert(kLw * kLw % 256 == 0, "staging must divide evenly");
-    float sv[kLw * kLw / 256];  // all loads in flight before the first LDS store
-#pragma unroll
-    for (int q = 0; q < kLw * kLw / 256; ++q) {
-        const int e = t + 256 * q, r = e % kLw, cc = e / kLw;
-        sv[q] = (r < w && cc < w) ? A[off(c + r, c + cc, lda)] : (r == cc ? 1.0f : 0.0f);
-    }
-#pragma unroll
-    for (int q = 0; q < kLw * kLw / 256; ++q) {
-        const int e = t + 256 * q;
-        D[e % kLw][e / kLw] = sv[q];
-    }
-    __syncthreads();
-    for (int k = 0; k < w; ++k) {
-        const float piv = D[k][k];
-        if (t > k && t < w && piv != 0.0f) {
-            const float l = D[t][k] / piv;
-            D[t][k] = l;
-            for (int j = k + 1; j < w; ++j) D[t][j] = D[t][j] - l * D[k][j];
-        }
-        __syncthreads();
-    }
-    if (blockIdx.x == 0) {
-        for (int e = t; e < w * w; e += 256) {
-            const int r = e % w, q = e / w;
-            A[off(c + r, c + q, lda)] = D[r][q];
-        }
-        if (t == 0)
-            for (int k = 0; k < w; ++k)
-                if (D[k][k] == 0.0f) {
-                    atomicMin(info, (unsigned long long)(c + k + 1));
-                    break;
-                }
-    }
-    const int64_t i = c + w + (int64_t)blockIdx.x * 256 + t;
-    if (i >= n) return;
+    const bool diag = t < kLw;
+    // row of this thread: the diagonal block's row t, or a row below the block
+    const int64_t i = diag ? c + t : c + w + (int64_t)blockIdx.x * kLeafRows + (t - kLw);
+    const bool live = diag ? t < w : i < n;
+    const int64_t ir = live ? i : c;  // loads from a valid row when idle
     float x[kLw];
 #pragma unroll
-    for (int j = 0; j < kLw; ++j) x[j] = (j < w) ? A[off(i, c + j, lda)] : 0.0f;
+    for (int j = 0; j < kLw; ++j) x[j] = A[off(ir, c + (j < w ? j : 0), lda)];
+    unsigned first_zero = 0;
 #pragma unroll
-    for (int j = 0; j < kLw; ++j) {
-        const float ujj = D[j][j];
-        if (j < w && ujj != 0.0f) {  // a zero pivot leaves its column as is (info reports it)
-            x[j] = x[j] / ujj;
+    for (int k = 0; k < kLw; ++k) {
+        if (k < w) {  // uniform; the loop stays unrolled so x[] stays in registers
+            if (t == k) {
 #pragma unroll
-            for (int q = j + 1; q < kLw; ++q)
-                if (q < w) x[q] = x[q] - x[j] * D[j][q];
+                for (int q = k; q < kLw; ++q) P[k & 1][q] = x[q];
+            }
+            __syncthreads();
+            const float ukk = P[k & 1][k];
+            if (t == 0 && ukk == 0.0f && first_zero == 0) first_zero = (unsigned)k + 1;
+            // rows below k: the diagonal block's rows t > k and every row below it
+            if ((!diag || t > k) && ukk != 0.0f) {
+                x[k] = x[k] / ukk;
+#pragma unroll
+                for (int q = k + 1; q < kLw; ++q)
+                    if (q < w) x[q] = x[q] - x[k] * P[k & 1][q];
+            }
         }
     }
+    // every thread's loads were consumed by the steps above
+    __syncthreads();
+    if (t == 0) {
+        __threadfence();
+        last = atomicInc(done, gridDim.x - 1) == gridDim.x - 1;
+        if (last && first_zero != 0) atomicMin(info, (unsigned long long)(c + first_zero));
+    }
+    __syncthreads();
+    if (live && (!diag || last)) {
 #pragma unroll
-    for (int j = 0; j < kLw; ++j)
-        if (j < w) A[off(i, c + j, lda)] = x[j];
+        for (int j = 0; j < kLw; ++j)
+            if (j < w) A[off(i, c + j, lda)] = x[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -506,12 +502,13 @@ int launch_cvt_f64_f32(const double *A, int64_t lda, float *B, int64_t ldb, int6
 }
 
 int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsigned long long *info,
-                        hipStream_t st)
+                        unsigned *done, hipStream_t st)
 {
     if (w <= 0 || w > kLw) return HPL_ERR_INTERNAL;
     const int64_t below = n - c - w;
-    const int64_t g = below > 0 ? blocks_of(below, 256) : 1;
-    hipLaunchKernelGGL(panel32_leaf_kernel, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info);
+    const int64_t g = below > 0 ? blocks_of(below, kLeafRows) : 1;
+    if (g > 0xffffffffll) return HPL_ERR_INTERNAL;
+    hipLaunchKernelGGL(panel32_leaf_kernel, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info, done);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
