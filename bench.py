@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 METRIC = "HPL TFLOP/s (2N³/3+2N²) & % FP64 MFMA peak; MxP+IR speed-up at FP64 residual"
 PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X datasheet, dense FP64 matrix
 PEAK_HBM_GBS = 8000.0
-PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X, FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz)
+PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X, FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz); FP64 MFMA is rated the same
 
 # HBM bytes per trailing-GEMM launch measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 2048 MiB copy: x2.000 and x1.000) at the default
@@ -353,8 +353,9 @@ def bench_batched(args, torch, h):
             "per_system_loop_sample": f"every 8th system ({sample.size} launches, sizes as in the batch)",
         },
         "roofline": {
-            "kernel": "batched_solve_kernel (factor + solve; FP64 FMA on the VALU)",
-            "bound": "alu",
+            "kernel": "batched_solve_kernel (factor + solve; trailing updates on the FP64 matrix cores, "
+                      "panels and solves on the VALU, both rated 78.6 TFLOP/s)",
+            "bound": "mfma",
             "achieved": round(f_fwd / k_fwd / 1e12, 3),
             "peak": PEAK_FP64_VALU_TFLOPS,
             "unit": "TFLOP/s",
