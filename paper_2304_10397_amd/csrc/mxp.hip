@@ -110,56 +110,98 @@ __global__ __launch_bounds__(256) void panel32_leaf_kernel(float *__restrict__ A
 
 // ---------------------------------------------------------------------------
 // FP32 triangular-solve leaf: B (nbk x ncols, nbk <= 32) <- L^{-1} B with L
-// unit lower (staged in LDS); one column per thread, forward substitution.
+// unit lower.  A workgroup of 128 threads takes 128 columns: the 32 x 128 block
+// moves between B and LDS with coalesced accesses (16-byte vectors when every
+// column starts 16-byte aligned, else 32 lanes per column), then each thread
+// solves its column in registers, right-looking: at step k every row i > k
+// subtracts l_ik x_k, so each element takes its subtractions in k order.  L is
+// staged transposed so that step k reads one contiguous column of L.
 // ---------------------------------------------------------------------------
-constexpr int kTl = 32;
+constexpr int kTl = 32, kTlCols = 128, kTlPad = 4;
 
-template <bool FULL>
-__global__ __launch_bounds__(256) void trsm32_leaf_kernel(const float *__restrict__ L, int64_t ldl,
-                                                          float *__restrict__ B, int64_t ldb, int nbk,
-                                                          int64_t ncols)
+template <bool VEC>
+__global__ __launch_bounds__(kTlCols) void trsm32_leaf_kernel(const float *__restrict__ L, int64_t ldl,
+                                                              float *__restrict__ B, int64_t ldb, int nbk,
+                                                              int64_t ncols)
 {
-    __shared__ float Ls[kTl][kTl + 1];
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) float Lt[kTl][kTl + kTlPad];            // Lt[k][i] = l_ik
+    __shared__ __attribute__((aligned(16))) float Xs[kTlCols][kTl + kTlPad];        // Xs[c][i] = b_i of column c
     const int t = threadIdx.x;
-    static_assert(kTl * kTl % 256 == 0, "staging must divide evenly");
-    float sv[kTl * kTl / 256];  // all loads in flight before the first LDS store
+    const int64_t j0 = (int64_t)blockIdx.x * kTlCols;
+    constexpr int kLq = kTl * kTl / kTlCols;
+    float sv[kLq];  // all loads in flight before the first LDS store
 #pragma unroll
-    for (int q = 0; q < kTl * kTl / 256; ++q) {
-        const int e = t + 256 * q, r = e % kTl, cc = e / kTl;
-        sv[q] = (r < nbk && cc < nbk) ? L[off(r, cc, ldl)] : 0.0f;
+    for (int q = 0; q < kLq; ++q) {
+        const int e = t + kTlCols * q, r = e % kTl, cc = e / kTl;
+        sv[q] = load_or(r < nbk && cc < nbk, L + off(r, cc, ldl), L, 0.0f);
+    }
+    if (VEC) {
+        // unit u: column u / 8, rows 4 (u % 8) .. + 3 (nbk == 32)
+        f4 vv[kTl * kTlCols / 4 / kTlCols];
+#pragma unroll
+        for (int q = 0; q < kTl / 4; ++q) {
+            const int u = t + kTlCols * q, c = u >> 3, r4 = (u & 7) * 4;
+            const int64_t jj = j0 + c;
+            const f4 v = *(const f4 *)(B + (size_t)(jj < ncols ? jj : ncols - 1) * (size_t)ldb + r4);
+            vv[q] = jj < ncols ? v : (f4){0.0f, 0.0f, 0.0f, 0.0f};
+        }
+#pragma unroll
+        for (int q = 0; q < kTl / 4; ++q) {
+            const int u = t + kTlCols * q;
+            *(f4 *)&Xs[u >> 3][(u & 7) * 4] = vv[q];
+        }
+    } else {
+        float xv[kTl];
+#pragma unroll
+        for (int q = 0; q < kTl; ++q) {
+            const int e = t + kTlCols * q, c = e / kTl, r = e % kTl;
+            const int64_t jj = j0 + c;
+            const bool ok = r < nbk && jj < ncols;
+            xv[q] = load_or(ok, B + (size_t)(ok ? jj : 0) * (size_t)ldb + (ok ? r : 0), B, 0.0f);
+        }
+#pragma unroll
+        for (int q = 0; q < kTl; ++q) {
+            const int e = t + kTlCols * q;
+            Xs[e / kTl][e % kTl] = xv[q];
+        }
     }
 #pragma unroll
-    for (int q = 0; q < kTl * kTl / 256; ++q) {
-        const int e = t + 256 * q;
-        Ls[e % kTl][e / kTl] = sv[q];
+    for (int q = 0; q < kLq; ++q) {
+        const int e = t + kTlCols * q;
+        Lt[e / kTl][e % kTl] = sv[q];
     }
     __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * 256 + t;
-    if (j >= ncols) return;
     float x[kTl];
-    float *col = B + (size_t)j * (size_t)ldb;
-    if (FULL) {
 #pragma unroll
-        for (int i = 0; i < kTl; ++i) x[i] = col[i];
-    } else {
-        for (int i = 0; i < kTl; ++i) x[i] = 0.0f;
-        for (int i = 0; i < nbk; ++i) x[i] = col[i];
+    for (int i4 = 0; i4 < kTl; i4 += 4) {
+        const f4 v = *(const f4 *)&Xs[t][i4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[i4 + r] = v[r];
     }
-    // row by row: x_i = b_i - sum_{k<i} l_ik x_k (successive subtractions in k
-    // order); the barrier keeps each row's LDS reads next to their use
 #pragma unroll
-    for (int i = 1; i < kTl; ++i) {
-        float acc = x[i];
+    for (int k = 0; k < kTl - 1; ++k) {
+        const float xk = x[k];
 #pragma unroll
-        for (int k = 0; k < i; ++k) acc = acc - Ls[i][k] * x[k];
-        x[i] = acc;
-        __builtin_amdgcn_sched_barrier(0);
+        for (int i = k + 1; i < kTl; ++i) x[i] = x[i] - Lt[k][i] * xk;
     }
-    if (FULL) {
 #pragma unroll
-        for (int i = 0; i < kTl; ++i) col[i] = x[i];
+    for (int i4 = 0; i4 < kTl; i4 += 4) *(f4 *)&Xs[t][i4] = (f4){x[i4], x[i4 + 1], x[i4 + 2], x[i4 + 3]};
+    __syncthreads();
+    if (VEC) {
+#pragma unroll
+        for (int q = 0; q < kTl / 4; ++q) {
+            const int u = t + kTlCols * q, c = u >> 3, r4 = (u & 7) * 4;
+            const int64_t jj = j0 + c;
+            if (jj < ncols) *(f4 *)(B + (size_t)jj * (size_t)ldb + r4) = *(const f4 *)&Xs[c][r4];
+        }
     } else {
-        for (int i = 0; i < nbk; ++i) col[i] = x[i];
+#pragma unroll
+        for (int q = 0; q < kTl; ++q) {
+            const int e = t + kTlCols * q, c = e / kTl, r = e % kTl;
+            const int64_t jj = j0 + c;
+            if (r < nbk && jj < ncols) B[(size_t)jj * (size_t)ldb + r] = Xs[c][r];
+        }
     }
 }
 
@@ -517,12 +559,15 @@ int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int n
 {
     if (ncols <= 0 || nbk <= 0) return HPL_OK;
     if (nbk > kTl) return HPL_ERR_INTERNAL;
-    if (nbk == kTl)
-        hipLaunchKernelGGL(trsm32_leaf_kernel<true>, dim3((unsigned)blocks_of(ncols, 256)), dim3(256), 0, st, L, ldl, B,
-                           ldb, nbk, ncols);
+    const int64_t g = blocks_of(ncols, kTlCols);
+    if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    // 16-byte vectors need every column start 16-byte aligned and all 32 rows present
+    const bool vec = nbk == kTl && ((uintptr_t)B % 16) == 0 && (ldb % 4) == 0;
+    if (vec)
+        hipLaunchKernelGGL(trsm32_leaf_kernel<true>, dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B, ldb, nbk, ncols);
     else
-        hipLaunchKernelGGL(trsm32_leaf_kernel<false>, dim3((unsigned)blocks_of(ncols, 256)), dim3(256), 0, st, L, ldl,
-                           B, ldb, nbk, ncols);
+        hipLaunchKernelGGL(trsm32_leaf_kernel<false>, dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B, ldb, nbk,
+                           ncols);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
