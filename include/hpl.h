@@ -196,10 +196,12 @@ int hpl_mxp_generate(uint64_t seed, double *A, int64_t n, int64_t lda, void *hip
  *   7 ldlu >= max(1, n)
  *   8 info host int64*: 0, or k+1 for the first exactly-zero diagonal of U
  *   9 hip_stream
- * With HPL_OPT_LOOKAHEAD non-zero the update of the next panel's columns runs
- * first and that panel's FACT overlaps the rest of the update on a second
- * stream; the factors are bitwise those of the plain schedule.
- * Workspace: 4 n nb bytes (the FP16/BF16 copies of L21 and U12), kept per device.
+ * With HPL_OPT_LOOKAHEAD non-zero each update does the next panel's columns
+ * first, then its rows, then the rest; that panel's FACT, its U12 and its
+ * FP16/BF16 copies run on a second stream beside the rest of the update; the
+ * factors are bitwise those of the plain schedule.
+ * Workspace: 4 n nb bytes (the FP16/BF16 copies of L21 and U12), twice that
+ * with look-ahead (two sets), kept per device.
  */
 int hpl_mxp_factor(const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU,
                    int64_t ldlu, int64_t *info, void *hip_stream);

@@ -671,24 +671,32 @@ static int mxp_panel(float *A, int64_t lda, int64_t n, int64_t c, int64_t w, uns
 // One step of the mixed-precision factorization is FACT of the panel (FP32),
 // U12 = L11^{-1} A12 (FP32), the scaling and conversion of -L21 and U12 to
 // FP16/BF16, and A22 += (-L21) U12 on the matrix cores.  With look-ahead
-// (Sec. III) the update of the next panel's columns goes first; the panel
-// stream then factors that panel while the main stream updates the remaining
-// columns, and the next U12 waits for both.  Every element takes the same
-// operations in the same order either way, so the factors are bitwise equal.
+// (Sec. III) the update of step j first does the next panel's columns, then the
+// next panel's rows, then the rest.  The panel stream factors the next panel
+// as soon as its columns are updated, and computes its U12 and low-precision
+// copies (into the second of two buffers) as soon as its rows are, both beside
+// the bulk of the update; step j+1 starts when both streams are done.  Every
+// element takes the same operations in the same order either way, so the
+// factors are bitwise equal.
 static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU,
                            int64_t ldlu, int64_t *info, hipStream_t st)
 {
-    const size_t half_bytes = sizeof(uint16_t) * (size_t)n * (size_t)nb;
-    const size_t a16_off = 0, b16_off = (half_bytes + 255) / 256 * 256;
-    const size_t sc_off = b16_off + (half_bytes + 255) / 256 * 256;
+    const bool la = opt_lookahead.load() != 0 && opt_serialize.load() == 0 && n > nb;
+    const size_t half_bytes = (sizeof(uint16_t) * (size_t)n * (size_t)nb + 255) / 256 * 256;
+    const int nbuf = la ? 2 : 1;
+    const size_t sc_off = 2 * (size_t)nbuf * half_bytes;
     HPLX_PROPAGATE(ensure_mxp_ws(d, sc_off + 256));
     char *ws = (char *)d->mxp_ws;
-    void *A16 = ws + a16_off, *B16 = ws + b16_off;
+    void *A16[2], *B16[2];
+    for (int q = 0; q < 2; ++q) {
+        const int qq = q < nbuf ? q : 0;
+        A16[q] = ws + 2 * (size_t)qq * half_bytes;
+        B16[q] = ws + (2 * (size_t)qq + 1) * half_bytes;
+    }
     unsigned *mx = (unsigned *)(ws + sc_off);
     int *sexp = (int *)(ws + sc_off + 16);
     unsigned long long *dinfo = (unsigned long long *)(ws + sc_off + 32);
     unsigned *leaf_done = (unsigned *)(ws + sc_off + 64);  // panel leaf's workgroup count (returns to zero)
-    const bool la = opt_lookahead.load() != 0 && opt_serialize.load() == 0 && n > nb;
     hipStream_t sp = la ? d->sp : st;
     Timer tm(d, opt_timing.load() != 0);
     // FACT of the panel at c (width w), on stream s
@@ -697,50 +705,60 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c, w, dinfo, leaf_done, s));
         return tm.end(id, s, (double)(n - c) * (double)w * (double)w, 4.0 * (double)(n - c) * (double)w * 2.0);
     };
-    // U12 of the panel at c and the low-precision copies of -L21 and U12
-    auto prep = [&](int64_t c, int64_t w) -> int {
+    // U12 of the panel at c and the low-precision copies of -L21 and U12 into buffer q, on stream s
+    auto prep = [&](int64_t c, int64_t w, int q, hipStream_t s) -> int {
         const int64_t c1 = c + w, m = n - c1;
-        const int id = tm.begin(ST_MXP_FACT, st);
-        HPLX_PROPAGATE(mxp_trsm(LU + off(c, c, ldlu), ldlu, w, LU + off(c, c1, ldlu), ldlu, m, st));
+        const int id = tm.begin(ST_MXP_FACT, s);
+        HPLX_PROPAGATE(mxp_trsm(LU + off(c, c, ldlu), ldlu, w, LU + off(c, c1, ldlu), ldlu, m, s));
         HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)w, mx,
-                                        sexp, st));
+                                        sexp, s));
         HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)w,
-                                          sexp, A16, B16, st));
-        return tm.end(id, st, (double)w * (double)w * (double)m, 4.0 * (double)w * (double)m * 2.0);
+                                          sexp, A16[q], B16[q], s));
+        return tm.end(id, s, (double)w * (double)w * (double)m, 4.0 * (double)w * (double)m * 2.0);
     };
-    // A22 columns [c1 + j0, c1 + j0 + nc) += (-L21) U12 of the panel at c0 (width w)
-    auto update = [&](int64_t c1, int64_t w, int64_t j0, int64_t nc) -> int {
-        const int64_t m = n - c1;
+    // A22 rows [c1 + i0, c1 + i0 + ni) x columns [c1 + j0, c1 + j0 + nc) += (-L21) U12 of the
+    // panel ending at c1 (width w), from buffer q, on the main stream
+    auto update = [&](int64_t c1, int64_t w, int q, int64_t i0, int64_t ni, int64_t j0, int64_t nc) -> int {
         const int id = tm.begin(ST_MXP_GEMM, st);
-        HPLX_PROPAGATE(launch_hgemm_update(fmt, m, nc, w, A16, (const uint16_t *)B16 + (size_t)j0 * (size_t)w,
-                                           LU + off(c1, c1 + j0, ldlu), ldlu, st));
-        return tm.end(id, st, 2.0 * (double)m * (double)nc * (double)w,
-                      8.0 * (double)m * (double)nc + 2.0 * (double)w * (double)(m + nc));
+        HPLX_PROPAGATE(launch_hgemm_update(fmt, ni, nc, w, (const uint16_t *)A16[q] + (size_t)i0 * (size_t)w,
+                                           (const uint16_t *)B16[q] + (size_t)j0 * (size_t)w,
+                                           LU + off(c1 + i0, c1 + j0, ldlu), ldlu, st));
+        return tm.end(id, st, 2.0 * (double)ni * (double)nc * (double)w,
+                      8.0 * (double)ni * (double)nc + 2.0 * (double)w * (double)(ni + nc));
     };
     HPLX_PROPAGATE(launch_fill_u64(dinfo, 1, ULLONG_MAX, st));
     HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)leaf_done, 1, 0ull, st));
     HPLX_PROPAGATE(launch_cvt_f64_f32(A, lda, LU, ldlu, n, n, st));
     HPLX_PROPAGATE(fact(0, nb < n ? nb : n, st));
+    int cur = 0;
+    if (nb < n) HPLX_PROPAGATE(prep(0, nb, cur, st));
     for (int64_t c0 = 0; c0 < n; c0 += nb) {
         const int64_t w = (n - c0) < nb ? (n - c0) : nb;
         const int64_t c1 = c0 + w;
         if (c1 >= n) break;
         const int64_t m = n - c1;
         const int64_t w2 = m < nb ? m : nb;  // width of the next panel
-        HPLX_PROPAGATE(prep(c0, w));
         const int r = (int)((c0 / nb) % kRing);
         if (la) {
-            HPLX_PROPAGATE(update(c1, w, 0, w2));
+            HPLX_PROPAGATE(update(c1, w, cur, 0, m, 0, w2));
             HPLX_TRY(hipEventRecord(d->ev_la[r], st));
             HPLX_TRY(hipStreamWaitEvent(sp, d->ev_la[r], 0));
             HPLX_PROPAGATE(fact(c1, w2, sp));
+            if (m > w2) {
+                HPLX_PROPAGATE(update(c1, w, cur, 0, w2, w2, m - w2));
+                HPLX_TRY(hipEventRecord(d->ev_iter[r], st));
+                HPLX_TRY(hipStreamWaitEvent(sp, d->ev_iter[r], 0));
+                HPLX_PROPAGATE(prep(c1, w2, cur ^ 1, sp));
+                HPLX_PROPAGATE(update(c1, w, cur, w2, m - w2, w2, m - w2));
+            }
             HPLX_TRY(hipEventRecord(d->ev_panel[r], sp));
-            if (m > w2) HPLX_PROPAGATE(update(c1, w, w2, m - w2));
             HPLX_TRY(hipStreamWaitEvent(st, d->ev_panel[r], 0));
         } else {
-            HPLX_PROPAGATE(update(c1, w, 0, m));
+            HPLX_PROPAGATE(update(c1, w, cur, 0, m, 0, m));
             HPLX_PROPAGATE(fact(c1, w2, st));
+            if (m > w2) HPLX_PROPAGATE(prep(c1, w2, cur ^ 1, st));
         }
+        cur ^= 1;
     }
     unsigned long long hinfo = 0;
     HPLX_TRY(hipMemcpyAsync(&hinfo, dinfo, sizeof hinfo, hipMemcpyDeviceToHost, st));
