@@ -585,7 +585,8 @@ def main():
         "config": {
             "workload": f"HPL FP64 LU+solve, N={n}, NB={nb}, look-ahead {args.lookahead}, "
                         f"A,b ~ U[-0.5,0.5) seed {args.seed}",
-            "n": n, "nb": nb, "lda": n + args.pad, "lookahead": args.lookahead, "seed": args.seed,
+            "n": n, "nb": nb, "lda": n + args.pad, "lookahead": args.lookahead,
+            "interchange_workgroups": h.hpl_get_option(h.HPL_OPT_LASWP_WGS), "seed": args.seed,
             "scaled_residual": float(res[0]), "residual_pass": bool(res[0] < 16.0), "info": info,
             "phase_ms_last_step": phases,
         },

@@ -239,12 +239,16 @@ enum hpl_option {
     HPL_OPT_GEMM_TILE = 7,   /* GEMM kernel variant (default 0 = auto): 1..4 the 4x4x4 tiles
                                 128x128, 128x64, 64x64, 128x32; 5, 6 the streamed 16x16x4
                                 tiles 128x128, 128x64 (where their preconditions hold) */
-    HPL_OPT_HOST_PANEL = 8   /* T > 0: every panel is factored on the host by T threads
+    HPL_OPT_HOST_PANEL = 8,  /* T > 0: every panel is factored on the host by T threads
                                 (hpl_host_panel; the paper's CPU FACT, Sec. III-A), the
                                 panel copied to pinned host memory and back; with the
                                 look-ahead the whole trailing update of panel j, GEMM
                                 included, overlaps the host FACT of panel j+1.  0
                                 (default): the GPU panel.  Pinned staging: 8 n nb bytes. */
+    HPL_OPT_LASWP_WGS = 9    /* g > 0: the row interchanges of the trailing columns run on at
+                                most g workgroups (each loops over 8-column groups), leaving
+                                the other CUs to the panel on the other stream (default 96);
+                                0: one workgroup per 8 columns.  Results do not depend on it. */
 };
 /* Returns 0, or -1 (bad key) / -2 (bad value); the option is unchanged on error. */
 int hpl_set_option(int key, int64_t value);

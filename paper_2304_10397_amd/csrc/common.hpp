@@ -172,7 +172,7 @@ constexpr int kPlanStride = 4 * kMaxSwaps + 64;
 int launch_swap_plans_all(const int32_t *ipiv, int64_t total, int64_t r0, int64_t nrows, bool reverse,
                           int32_t *plans, int *err, hipStream_t st);
 // Applies a plan to columns [col0, col0+ncols) of A.
-int launch_laswp(double *A, int64_t lda, int64_t col0, int64_t ncols, SwapPlan plan,
+int launch_laswp(double *A, int64_t lda, int64_t col0, int64_t ncols, SwapPlan plan, int64_t max_wgs,
                  hipStream_t st);
 
 // panel.hip: leaf of the recursive panel factorization.

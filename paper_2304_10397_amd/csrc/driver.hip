@@ -67,6 +67,7 @@ static std::atomic<int64_t> opt_timing{0};
 static std::atomic<int64_t> opt_progress{0};
 static std::atomic<int64_t> opt_serialize{0};
 static std::atomic<int64_t> opt_gemm_tile{0};
+static std::atomic<int64_t> opt_laswp_wgs{96};
 static std::atomic<int64_t> opt_host_panel{0};  // threads of the host panel (0: panel on the GPU)
 
 // ---------------------------------------------------------------------------
@@ -313,7 +314,9 @@ static int apply_plans(double *A, int64_t lda, int64_t col0, int64_t ncols, int6
 {
     if (ncols <= 0 || cnt <= 0) return HPL_OK;
     int id = tm->begin(ST_LASWP, st);
-    for (int64_t q = 0; q * kMaxSwaps < cnt; ++q) HPLX_PROPAGATE(launch_laswp(A, lda, col0, ncols, plans[q], st));
+    const int64_t max_wgs = opt_laswp_wgs.load();
+    for (int64_t q = 0; q * kMaxSwaps < cnt; ++q)
+        HPLX_PROPAGATE(launch_laswp(A, lda, col0, ncols, plans[q], max_wgs, st));
     return tm->end(id, st, 0, 32.0 * (double)cnt * (double)ncols);
 }
 
@@ -355,14 +358,14 @@ static int panel_rec(Ctx &x, int64_t c, int64_t w, hipStream_t st)
     const int64_t w2 = w - w1;
     HPLX_PROPAGATE(panel_rec(x, c, w1, st));
     HPLX_PROPAGATE(launch_swap_plan(x.ipiv + c, (int)w1, c, x.n, false, d->pint, st));
-    HPLX_PROPAGATE(launch_laswp(x.A, x.lda, c + w1, w2, d->pint, st));
+    HPLX_PROPAGATE(launch_laswp(x.A, x.lda, c + w1, w2, d->pint, 0, st));
     HPLX_PROPAGATE(launch_trsm_llnu(x.A + off(c, c, x.lda), x.lda, x.A + off(c, c + w1, x.lda), x.lda, w1, w2, st));
     HPLX_PROPAGATE(launch_gemm_sub(x.n - c - w1, w2, w1, x.A + off(c + w1, c, x.lda), x.lda,
                                    x.A + off(c, c + w1, x.lda), x.lda, x.A + off(c + w1, c + w1, x.lda), x.lda, 0,
                                    st));
     HPLX_PROPAGATE(panel_rec(x, c + w1, w2, st));
     HPLX_PROPAGATE(launch_swap_plan(x.ipiv + c + w1, (int)w2, c + w1, x.n, false, d->pint, st));
-    return launch_laswp(x.A, x.lda, c, w1, d->pint, st);
+    return launch_laswp(x.A, x.lda, c, w1, d->pint, 0, st);
 }
 
 static int panel_full(Ctx &x, int64_t c0, int64_t jb, SwapPlan *plans, hipStream_t st)
@@ -1091,6 +1094,10 @@ int hpl_set_option(int key, int64_t value)
         if (value < 0 || value > kHostPanelMaxThreads) return -2;
         opt_host_panel = value;
         return 0;
+    case HPL_OPT_LASWP_WGS:
+        if (value < 0 || value > 65536) return -2;
+        opt_laswp_wgs = value;
+        return 0;
     default: return -1;
     }
 }
@@ -1106,6 +1113,7 @@ int64_t hpl_get_option(int key)
     case HPL_OPT_SERIALIZE: return opt_serialize;
     case HPL_OPT_GEMM_TILE: return opt_gemm_tile;
     case HPL_OPT_HOST_PANEL: return opt_host_panel;
+    case HPL_OPT_LASWP_WGS: return opt_laswp_wgs;
     default: return INT64_MIN;
     }
 }

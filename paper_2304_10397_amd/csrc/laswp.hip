@@ -120,25 +120,31 @@ __global__ __launch_bounds__(kLwThreads) void laswp_kernel(double *__restrict__ 
                                                            const int32_t *__restrict__ srcslot,
                                                            const int32_t *__restrict__ nslots_p)
 {
+    // column groups of kLwCols, taken grid-stride (the grid may be smaller than
+    // the number of groups, so that the interchange leaves CUs to other work)
     __shared__ double vals[2 * kMaxSwaps][kLwCols];
     const int ns = *nslots_p;
-    const int64_t cb = col0 + (int64_t)blockIdx.x * kLwCols;
-    const int64_t left = col0 + ncols - cb;
-    const int nc = left < kLwCols ? (int)left : kLwCols;
-    for (int s = threadIdx.x; s < ns; s += kLwThreads) {
-        const int64_t r = rows[s];
+    const int64_t ngroups = (ncols + kLwCols - 1) / kLwCols;
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int64_t cb = col0 + grp * kLwCols;
+        const int64_t left = col0 + ncols - cb;
+        const int nc = left < kLwCols ? (int)left : kLwCols;
+        for (int s = threadIdx.x; s < ns; s += kLwThreads) {
+            const int64_t r = rows[s];
 #pragma unroll
-        for (int c = 0; c < kLwCols; ++c)  // entries past nc are never written back
-            vals[s][c] = load_or(c < nc, A + off(r, cb + c, lda), A + off(r, cb, lda), 0.0);
-    }
-    __syncthreads();
-    for (int s = threadIdx.x; s < ns; s += kLwThreads) {
-        const int ss = srcslot[s];
-        if (ss == s) continue;
-        const int64_t r = rows[s];
+            for (int c = 0; c < kLwCols; ++c)  // entries past nc are never written back
+                vals[s][c] = load_or(c < nc, A + off(r, cb + c, lda), A + off(r, cb, lda), 0.0);
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < ns; s += kLwThreads) {
+            const int ss = srcslot[s];
+            if (ss == s) continue;
+            const int64_t r = rows[s];
 #pragma unroll
-        for (int c = 0; c < kLwCols; ++c)
-            if (c < nc) A[off(r, cb + c, lda)] = vals[ss][c];
+            for (int c = 0; c < kLwCols; ++c)
+                if (c < nc) A[off(r, cb + c, lda)] = vals[ss][c];
+        }
+        __syncthreads();  // vals is refilled by the next group
     }
 }
 
@@ -167,10 +173,12 @@ int launch_swap_plans_all(const int32_t *ipiv, int64_t total, int64_t r0, int64_
     return HPL_OK;
 }
 
-int launch_laswp(double *A, int64_t lda, int64_t col0, int64_t ncols, SwapPlan plan, hipStream_t st)
+int launch_laswp(double *A, int64_t lda, int64_t col0, int64_t ncols, SwapPlan plan, int64_t max_wgs,
+                 hipStream_t st)
 {
     if (ncols <= 0) return HPL_OK;
-    const int64_t g = (ncols + kLwCols - 1) / kLwCols;
+    int64_t g = (ncols + kLwCols - 1) / kLwCols;
+    if (max_wgs > 0 && g > max_wgs) g = max_wgs;
     if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
     hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)g), dim3(kLwThreads), 0, st, A, lda, col0, ncols, plan.rows,
                        plan.srcslot, plan.nslots);

@@ -29,6 +29,7 @@ HPL_OPT_PROGRESS = 5
 HPL_OPT_SERIALIZE = 6
 HPL_OPT_GEMM_TILE = 7
 HPL_OPT_HOST_PANEL = 8
+HPL_OPT_LASWP_WGS = 9
 
 STAT_CLASSES = ("gemm", "panel", "laswp", "trsm", "solve", "plan", "mxp_gemm", "mxp_fact", "grad_a", "batched")
 

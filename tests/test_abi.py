@@ -125,6 +125,13 @@ def test_options_roundtrip_and_rejects():
     with pytest.raises(ValueError):
         h.hpl_set_option(999, 1)
     assert h.hpl_get_option(999) == -(2**63)
+    assert h.hpl_get_option(h.HPL_OPT_LASWP_WGS) == 96
+    h.hpl_set_option(h.HPL_OPT_LASWP_WGS, 0)
+    assert h.hpl_get_option(h.HPL_OPT_LASWP_WGS) == 0
+    with pytest.raises(ValueError):
+        h.hpl_set_option(h.HPL_OPT_LASWP_WGS, -1)
+    assert h.hpl_get_option(h.HPL_OPT_LASWP_WGS) == 0
+    h.hpl_set_option(h.HPL_OPT_LASWP_WGS, 96)
 
 
 def test_strerror():
