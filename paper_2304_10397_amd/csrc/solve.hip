@@ -5,9 +5,10 @@
 // rows depend on each other, so it is organized as a sweep over diagonal blocks
 // of kBs = 64 rows with ONE launch per block:
 //   * every workgroup of the launch first finishes the diagonal block itself:
-//     one wave per right-hand side, lane r holds x_r, and x_k reaches the other
-//     lanes by shuffle -- no barrier, no second launch (workgroup 0 also
-//     stores the finished rows);
+//     each wave takes up to 4 right-hand sides at a time (their recurrences
+//     interleaved), lane r holds x_r, and x_k reaches the other lanes by
+//     shuffle -- no barrier, no second launch (workgroup 0 also stores the
+//     finished rows);
 //   * then the workgroup subtracts the block's contribution from its share of
 //     the rows not yet solved, one row per thread (a skinny GEMV: for L and U
 //     the row's values are read coalesced across lanes; for the transposed
@@ -27,6 +28,7 @@ namespace {
 
 constexpr int kBs = 64;          // diagonal block rows (one per lane)
 constexpr int kSvThreads = 256;  // 4 waves
+constexpr int kSvChain = 4;      // right-hand sides per wave in the diagonal block
 
 template <int mode, typename TT>
 __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const TT *__restrict__ T, int64_t ldt,
@@ -60,22 +62,35 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const TT *__res
         Td[e % kBs][e / kBs] = sv[q];
     }
     __syncthreads();
-    for (int64_t c = wid; c < nrhs; c += kSvThreads / 64) {
-        double x = (lane < bs) ? B[off(r0 + lane, c, ldb)] : 0.0;
-#pragma unroll 8
+    // each wave carries kSvChain consecutive right-hand sides through the same
+    // step loop (independent recurrences, interleaved)
+    for (int64_t c0 = (int64_t)wid * kSvChain; c0 < nrhs; c0 += (int64_t)kSvChain * (kSvThreads / 64)) {
+        double x[kSvChain];
+#pragma unroll
+        for (int j = 0; j < kSvChain; ++j) {
+            const bool ok = lane < bs && c0 + j < nrhs;
+            x[j] = load_or(ok, B + off(r0 + lane, c0 + j, ldb), B + off(r0, c0, ldb), 0.0);
+        }
+#pragma unroll 4
         for (int s = 0; s < kBs; ++s) {
             const int k = lower ? s : kBs - 1 - s;
-            double xk = read_lane(x, k);
-            if (!unit) xk = xk / Td[k][k];
-            if (lane == k) x = xk;
             const bool below = lower ? (lane > k) : (lane < k);
             const double a = tr ? Td[k][lane] : Td[lane][k];  // T_op(lane, k)
-            if (below) x = __fma_rn(-a, xk, x);
+            const double dkk = Td[k][k];
+#pragma unroll
+            for (int j = 0; j < kSvChain; ++j) {
+                double xk = read_lane(x[j], k);
+                if (!unit) xk = xk / dkk;
+                if (lane == k) x[j] = xk;
+                if (below) x[j] = __fma_rn(-a, xk, x[j]);
+            }
         }
-        if (lane < bs) {
-            Y[c * kBs + lane] = x;
-            if (blockIdx.x == 0) B[off(r0 + lane, c, ldb)] = x;
-        }
+#pragma unroll
+        for (int j = 0; j < kSvChain; ++j)
+            if (lane < bs && c0 + j < nrhs) {
+                Y[(c0 + j) * kBs + lane] = x[j];
+                if (blockIdx.x == 0) B[off(r0 + lane, c0 + j, ldb)] = x[j];
+            }
     }
     __syncthreads();
     if (row_end <= row_begin) return;
