@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kTlCols) void trsm32_leaf_kernel(const float *__res
     }
     if (VEC) {
         // unit u: column u / 8, rows 4 (u % 8) .. + 3 (nbk == 32)
-        f4 vv[kTl * kTlCols / 4 / kTlCols];
+        f4 vv[kTl / 4];
 #pragma unroll
         for (int q = 0; q < kTl / 4; ++q) {
             const int u = t + kTlCols * q, c = u >> 3, r4 = (u & 7) * 4;
