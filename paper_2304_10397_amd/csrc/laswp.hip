@@ -77,18 +77,20 @@ __global__ __launch_bounds__(kPlanThreads) void swap_plan_kernel(const int32_t *
         }
         bslot[t] = b;
     }
-    for (int s = t; s < 2 * cnt; s += kPlanThreads) cur[s] = s;
     __syncthreads();
     for (int s = t; s < 2 * cnt; s += kPlanThreads)
         used[s] = (s < cnt) ? 1 : (bslot[s - cnt] == s ? 1 : 0);
-    if (t == 0) {
-        for (int kk = 0; kk < cnt; ++kk) {
+    // cur[s] = the slot whose content ends in slot s once the interchanges
+    // (k, bslot[k]) are applied in order: followed back from s through them,
+    // last applied first -- independent per slot, so every thread takes its own
+    for (int s = t; s < 2 * cnt; s += kPlanThreads) {
+        int p = s;
+        for (int kk = cnt - 1; kk >= 0; --kk) {
             const int k = reverse ? cnt - 1 - kk : kk;
             const int b = bslot[k];
-            const int ca = cur[k], cb = cur[b];
-            cur[k] = cb;
-            cur[b] = ca;
+            p = (p == k) ? b : (p == b ? k : p);
         }
+        cur[s] = p;
     }
     __syncthreads();
     // exclusive scan of used[] over 2*cnt slots: thread t owns slots 2t, 2t+1
