@@ -46,6 +46,34 @@ def test_mxp_factor_dyadic_exact(n, nb, fmt):
     assert np.array_equal(np.triu(LUh), U)
 
 
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_mxp_factor_zero_pivot_info(fmt):
+    """A = L U (dyadic) with u_kk = 0: after eliminating columns < k, column k is
+    exactly zero on and below the diagonal, so info = k + 1 whatever the
+    schedule; k = 300 lies in a leaf whose rows span two workgroups."""
+    h = hpl()
+    n, nb, k = 700, 128, 300
+    rng = np.random.default_rng(12)
+    L = np.tril(rng.integers(-4, 5, (n, n)) / 8.0, -1) + np.eye(n)
+    U = np.triu(rng.integers(-7, 8, (n, n)).astype(float), 1) + np.diag(2.0 ** rng.integers(0, 3, n))
+    U[k, k] = 0.0
+    A = np.asfortranarray(L @ U)
+    _, info_o = oracle.lu_mxp(A, nb, fmt)
+    assert info_o == k + 1
+    old = h.hpl_get_option(h.HPL_OPT_LOOKAHEAD)
+    try:
+        for la in (1, 0):
+            h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, la)
+            LU, info = h.hpl_mxp_factor(to_gpu(A), nb=nb, fmt=fmt)
+            assert info == k + 1, (la, info)
+            # the columns before k are the exact factors
+            LUh = LU.cpu().numpy().astype(np.float64)
+            assert np.array_equal(np.tril(LUh, -1)[:, :k], np.tril(L, -1)[:, :k])
+            assert np.array_equal(np.triu(LUh)[:k, :], U[:k, :])
+    finally:
+        h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, old)
+
+
 @pytest.mark.parametrize("n,nb", [(64, 64), (130, 64), (1000, 128), (3000, 512), (4160, 1024)])
 @pytest.mark.parametrize("fmt", [0, 1])
 def test_mxp_factor_lookahead_bitwise(n, nb, fmt):
