@@ -71,18 +71,37 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const TT *__res
             const bool ok = lane < bs && c0 + j < nrhs;
             x[j] = load_or(ok, B + off(r0 + lane, c0 + j, ldb), B + off(r0, c0, ldb), 0.0);
         }
+        const int64_t left = nrhs - c0;
+        // one step of the recurrence of chain value xj, k the step's row
+        auto step = [&](double &xj, int k, bool below, double a, double dkk) __attribute__((always_inline)) {
+            double xk = read_lane(xj, k);
+            if (!unit) xk = xk / dkk;
+            if (lane == k) xj = xk;
+            if (below) xj = __fma_rn(-a, xk, xj);
+        };
+        if (left >= kSvChain) {  // all chains live (uniform in the wave): interleaved
 #pragma unroll 4
-        for (int s = 0; s < kBs; ++s) {
-            const int k = lower ? s : kBs - 1 - s;
-            const bool below = lower ? (lane > k) : (lane < k);
-            const double a = tr ? Td[k][lane] : Td[lane][k];  // T_op(lane, k)
-            const double dkk = Td[k][k];
+            for (int s = 0; s < kBs; ++s) {
+                const int k = lower ? s : kBs - 1 - s;
+                const bool below = lower ? (lane > k) : (lane < k);
+                const double a = tr ? Td[k][lane] : Td[lane][k];  // T_op(lane, k)
+                const double dkk = Td[k][k];
+#pragma unroll
+                for (int j = 0; j < kSvChain; ++j) step(x[j], k, below, a, dkk);
+            }
+        } else {  // the last few right-hand sides: one chain at a time
 #pragma unroll
             for (int j = 0; j < kSvChain; ++j) {
-                double xk = read_lane(x[j], k);
-                if (!unit) xk = xk / dkk;
-                if (lane == k) x[j] = xk;
-                if (below) x[j] = __fma_rn(-a, xk, x[j]);
+                if (j >= left) break;
+                double xj = x[j];
+#pragma unroll 8
+                for (int s = 0; s < kBs; ++s) {
+                    const int k = lower ? s : kBs - 1 - s;
+                    const bool below = lower ? (lane > k) : (lane < k);
+                    const double a = tr ? Td[k][lane] : Td[lane][k];
+                    step(xj, k, below, a, Td[k][k]);
+                }
+                x[j] = xj;
             }
         }
 #pragma unroll
