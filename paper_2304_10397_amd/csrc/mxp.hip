@@ -34,13 +34,34 @@ __global__ __launch_bounds__(256) void mxp_diag_kernel(double *__restrict__ A, i
     A[off(i, i, lda)] = s;
 }
 
+// FP64 -> FP32 copy: each thread converts rows 2i, 2i+1 of kCvCols columns
+// (16-byte loads and 8-byte stores when both leading dimensions are even)
+constexpr int kCvCols = 8;
+
+template <bool VEC>
 __global__ __launch_bounds__(256) void cvt_f64_f32_kernel(const double *__restrict__ A, int64_t lda,
                                                           float *__restrict__ B, int64_t ldb, int64_t rows,
                                                           int64_t cols)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef float fl2 __attribute__((ext_vector_type(2)));
+    const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
     if (i >= rows) return;
-    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) B[off(i, j, ldb)] = (float)A[off(i, j, lda)];
+    const bool pair = i + 1 < rows;
+    for (int64_t j0 = (int64_t)blockIdx.y * kCvCols; j0 < cols; j0 += (int64_t)gridDim.y * kCvCols) {
+#pragma unroll
+        for (int c = 0; c < kCvCols; ++c) {
+            const int64_t j = j0 + c;
+            if (j >= cols) break;
+            if (VEC && pair) {
+                const d2 v = *(const d2 *)(A + off(i, j, lda));
+                *(fl2 *)(B + off(i, j, ldb)) = (fl2){(float)v[0], (float)v[1]};
+            } else {
+                B[off(i, j, ldb)] = (float)A[off(i, j, lda)];
+                if (pair) B[off(i + 1, j, ldb)] = (float)A[off(i + 1, j, lda)];
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -536,9 +557,17 @@ int launch_cvt_f64_f32(const double *A, int64_t lda, float *B, int64_t ldb, int6
                        hipStream_t st)
 {
     if (rows <= 0 || cols <= 0) return HPL_OK;
-    const unsigned gy = (unsigned)(cols < 65535 ? cols : 65535);
-    hipLaunchKernelGGL(cvt_f64_f32_kernel, dim3((unsigned)blocks_of(rows, 256), gy), dim3(256), 0, st, A, lda, B,
-                       ldb, rows, cols);
+    const int64_t gx = blocks_of(blocks_of(rows, 2), 256);
+    int64_t gy = blocks_of(cols, kCvCols);
+    if (gy > 65535) gy = 65535;  // the kernel loops over further column groups
+    if (gx > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    const bool vec = (lda % 2) == 0 && (ldb % 2) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 8) == 0;
+    if (vec)
+        hipLaunchKernelGGL(cvt_f64_f32_kernel<true>, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, A, lda, B,
+                           ldb, rows, cols);
+    else
+        hipLaunchKernelGGL(cvt_f64_f32_kernel<false>, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, A, lda, B,
+                           ldb, rows, cols);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
