@@ -226,9 +226,11 @@ int hpl_mxp_solve(const double *A, int64_t lda, const float *LU, int64_t ldlu, i
 
 /* Options (process-wide, read at the start of each call). */
 enum hpl_option {
-    HPL_OPT_LOOKAHEAD = 1,   /* 0: none.  1 (default): panel j+1 is factored while the
-                                RS/TRSM of panel j finish; the trailing GEMM starts when
-                                the panel is done.  2: the panel also overlaps the GEMM.
+    HPL_OPT_LOOKAHEAD = 1,   /* 0: none.  1: panel j+1 is factored while the RS/TRSM of
+                                panel j finish; the trailing GEMM starts when the panel
+                                is done.  2: the panel also overlaps the GEMM.  3
+                                (default): 2 for n <= 32768, 1 above (the faster of the
+                                two measured at each size).  All give the same bits.
                                 hpl_mxp_factor: 1 and 2 both overlap the next FACT with
                                 the trailing update (it has no RS to overlap). */
     HPL_OPT_PANEL_BASE = 2,  /* leaf width of the recursive panel: 8, 16, 32 or 64 (default 32) */

@@ -60,7 +60,7 @@ void note_error(const char *what, const char *file, int line)
 // ---------------------------------------------------------------------------
 // options
 // ---------------------------------------------------------------------------
-static std::atomic<int64_t> opt_lookahead{1};
+static std::atomic<int64_t> opt_lookahead{3};
 static std::atomic<int64_t> opt_panel_base{32};
 static std::atomic<int64_t> opt_panel_wgs{256};
 static std::atomic<int64_t> opt_timing{0};
@@ -479,7 +479,10 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
     Ctx x{d, A, n, lda, ipiv, (int)opt_panel_base.load(), (int)opt_panel_wgs.load(), (int)opt_gemm_tile.load(), &tm};
     x.host_threads = (int)opt_host_panel.load();
     const int64_t progress = opt_progress.load();
-    const int64_t la_mode = opt_lookahead.load();
+    // mode 3 (the default) takes 2 up to n = 32768, where the panel is the
+    // critical path and the small trailing GEMMs leave it CUs, else 1
+    const int64_t la_opt = opt_lookahead.load();
+    const int64_t la_mode = la_opt == 3 ? (n <= 32768 ? 2 : 1) : la_opt;
     const bool la = la_mode != 0 && opt_serialize.load() == 0 && n > nb;
     hipStream_t sp = la ? d->sp : su;
     const int64_t np = (n + nb - 1) / nb;
@@ -1063,7 +1066,7 @@ int hpl_set_option(int key, int64_t value)
 {
     switch (key) {
     case HPL_OPT_LOOKAHEAD:
-        if (value < 0 || value > 2) return -2;
+        if (value < 0 || value > 3) return -2;
         opt_lookahead = value;
         return 0;
     case HPL_OPT_PANEL_BASE:

@@ -116,9 +116,11 @@ def test_options_roundtrip_and_rejects():
     assert h.hpl_get_option(h.HPL_OPT_LOOKAHEAD) == 0
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 2)
     assert h.hpl_get_option(h.HPL_OPT_LOOKAHEAD) == 2
+    h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 3)
+    assert h.hpl_get_option(h.HPL_OPT_LOOKAHEAD) == 3
     with pytest.raises(ValueError):
-        h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 3)
-    assert h.hpl_get_option(h.HPL_OPT_LOOKAHEAD) == 2
+        h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 4)
+    assert h.hpl_get_option(h.HPL_OPT_LOOKAHEAD) == 3
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, old)
     with pytest.raises(ValueError):
         h.hpl_set_option(h.HPL_OPT_PANEL_BASE, 12)

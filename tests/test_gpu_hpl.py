@@ -142,8 +142,8 @@ def test_lookahead_and_serialize_bitwise(n, nb):
     h = hpl()
     results = []
     # (look-ahead, serialize, panel workgroups, interchange workgroups: 0 = one per 8 columns)
-    for la, ser, wgs, lw in [(1, 0, 128, 96), (0, 0, 128, 96), (2, 0, 128, 96), (1, 1, 128, 96), (1, 0, 5, 96),
-                             (2, 0, 1, 96), (1, 0, 128, 0), (1, 0, 128, 3), (0, 0, 128, 1)]:
+    for la, ser, wgs, lw in [(1, 0, 128, 96), (0, 0, 128, 96), (2, 0, 128, 96), (3, 0, 128, 96), (1, 1, 128, 96),
+                             (1, 0, 5, 96), (2, 0, 1, 96), (1, 0, 128, 0), (1, 0, 128, 3), (0, 0, 128, 1)]:
         h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, la)
         h.hpl_set_option(h.HPL_OPT_SERIALIZE, ser)
         h.hpl_set_option(h.HPL_OPT_PANEL_WGS, wgs)
@@ -151,7 +151,7 @@ def test_lookahead_and_serialize_bitwise(n, nb):
         A, _ = gpu_system(n, seed=7)
         ipiv, _ = h.hpl_factor(A, nb)
         results.append((to_host(A), ipiv.cpu().numpy()))
-    h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 1)
+    h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, 3)
     h.hpl_set_option(h.HPL_OPT_SERIALIZE, 0)
     h.hpl_set_option(h.HPL_OPT_PANEL_WGS, 128)
     h.hpl_set_option(h.HPL_OPT_LASWP_WGS, 96)
