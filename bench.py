@@ -7,14 +7,25 @@ The default workload is N = 163840, NB = 512, look-ahead depth 1 (A fills
 about 215 GB of HBM), seeded synthetic input.  Prints ONE JSON line on stdout;
 progress goes to stderr.
 
-    python bench.py [--gpus 1] [--steps 1] [--warmup 0] [--n 163840] [--nb 512]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--n 163840] [--nb 512]
+
+One full-size step takes about 46 s, so the number of timed steps is bounded
+by wall-clock budgets: at least one step runs; another starts only while the
+timed work stays within --timed-budget seconds and the whole process within
+--budget seconds (from its start).  The JSON line reports the steps actually
+timed and the steps requested.  Warm-up steps (--warmup) are factor + solve
+runs at N = 4096: they load the code objects and the workspace, which is all
+a full-size warm-up would add.
 """
-import argparse
-import json
-import os
-import subprocess
-import sys
 import time
+
+T_PROCESS_START = time.time()
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import os  # noqa: E402
+import subprocess  # noqa: E402
+import sys  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -39,32 +50,81 @@ def hpl_flops(n):
     return 2.0 * n ** 3 / 3.0 + 2.0 * n ** 2
 
 
-def cpu_baseline(n_sample, seed):
-    """The oracle (plain C, single thread) on a bounded sample of the same workload."""
-    import numpy as np
-    import oracle
-    A = oracle.gen(seed, 0, n_sample, n_sample).copy(order="F")
-    b = oracle.gen(seed, 1, n_sample, 1)[:, 0].copy()
-    t0 = time.perf_counter()
-    ipiv, info = oracle.lu(A)
-    oracle.solve(A, ipiv, b)
-    dt = time.perf_counter() - t0
-    res = oracle.residual_gen(seed, n_sample, b, oracle.gen(seed, 1, n_sample, 1)[:, 0].copy())
+def host_description():
+    """(CPU model, nproc) of this host."""
     try:
-        model = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
-        model = [l.split(":", 1)[1].strip() for l in model.splitlines() if l.startswith("Model name")]
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        model = [l.split(":", 1)[1].strip() for l in txt.splitlines() if l.startswith("Model name")]
         model = model[0] if model else "unknown"
     except OSError:
         model = "unknown"
-    return {
-        "value": hpl_flops(n_sample) / dt / 1e12,
+    return model, os.cpu_count()
+
+
+def host_threads():
+    """Threads for the parallel oracle: the host share the environment grants
+    (OMP_NUM_THREADS when set), else every core."""
+    v = os.environ.get("OMP_NUM_THREADS", "")
+    return int(v) if v.isdigit() and int(v) > 0 else (os.cpu_count() or 1)
+
+
+def project_n3(measured, sizes):
+    """t proportional to N^3 fitted through the largest measured point (the one
+    nearest the projected sizes' out-of-cache regime): {str(N): seconds}."""
+    n0, t0 = max(measured, key=lambda r: r[0])
+    return {str(n): round(t0 * (n / n0) ** 3, 1) for n in sizes}
+
+
+def cpu_baseline(sizes, seed, threads):
+    """The oracle (plain C: unblocked LU with partial pivoting + substitution) on
+    this host: single-threaded, then its threaded form (bitwise the same result)
+    on `threads` threads, LU + solve of the same seeded system at each N.
+    Returns (baseline dict, oracle x at the smallest N)."""
+    import numpy as np
+    import oracle
+    serial, parallel = [], []
+    x_small = None
+    used = threads
+    for n in sizes:
+        b0 = oracle.gen(seed, 1, n, 1)[:, 0].copy()
+        for form in ("serial", "parallel"):
+            A = oracle.gen(seed, 0, n, n).copy(order="F")
+            b = b0.copy()
+            t0 = time.perf_counter()
+            if form == "serial":
+                ipiv, info = oracle.lu(A)
+            else:
+                ipiv, info, used = oracle.lu_par(A, threads)
+            oracle.solve(A, ipiv, b)
+            dt = time.perf_counter() - t0
+            row = {"n": n, "seconds": round(dt, 4), "tflops": round(hpl_flops(n) / dt / 1e12, 6)}
+            (serial if form == "serial" else parallel).append(row)
+            if form == "serial" and n == min(sizes):
+                x_small = b.copy()
+            log(f"oracle {form} N={n}: {dt:.3f} s, {hpl_flops(n) / dt / 1e9:.2f} GFLOP/s")
+    model, nproc = host_description()
+    top = max(parallel, key=lambda r: r["n"])
+    proj = [8192, 65536, 163840]
+    out = {
+        "value": top["tflops"],
         "unit": "TFLOP/s",
-        "cores": 1,
+        "cores": used,
         "kind": "oracle",
-        "sample": (f"oracle LU + solve of the same seeded system at N={n_sample} "
-                   f"(single thread, {dt:.2f} s, scaled residual {res[0]:.3g}); host CPU: {model}, "
-                   f"nproc={os.cpu_count()}"),
+        "sample": (f"oracle LU + solve of the benchmark's seeded system (seed {seed}) at N = "
+                   f"{', '.join(str(n) for n in sizes)}; value = the threaded form at N={top['n']} on "
+                   f"{used} threads ({top['seconds']:.2f} s); host CPU: {model}, nproc={nproc}"),
+        "host_cpu": model,
+        "nproc": nproc,
+        "threads": used,
+        "serial": serial,
+        "parallel": parallel,
+        "projection": {
+            "note": "PROJECTION, not measured: t proportional to N^3 through the largest measured N",
+            "serial_seconds": project_n3([(r["n"], r["seconds"]) for r in serial], proj),
+            "parallel_seconds": project_n3([(r["n"], r["seconds"]) for r in parallel], proj),
+        },
     }
+    return out, x_small
 
 
 def measured_traffic(n, nb):
@@ -460,18 +520,207 @@ def bench_hostpanel(args, torch, h):
     print(json.dumps(out), flush=True)
 
 
+# The small configuration timed next to the oracle (N = 1024, NB = 64): median
+# of CONFIG1_RUNS factor + solve runs after CONFIG1_WARM warm-ups.
+CONFIG1_N, CONFIG1_NB, CONFIG1_RUNS, CONFIG1_WARM = 1024, 64, 20, 3
+RESERVE_S = 15.0   # after the last step: residual, statistics, JSON
+
+
+def may_start_step(done, requested, elapsed_s, timed_s, est_step_s, budget_s, timed_budget_s,
+                   reserve_s=RESERVE_S):
+    """Whether another full-size step may start.  The first always does (when
+    one was requested); a later one only if, at the last step's duration, the
+    timed work stays within timed_budget_s and the process, with reserve_s
+    left for the residual and the report, within budget_s."""
+    if done >= requested:
+        return False
+    if done == 0:
+        return True
+    if timed_s + est_step_s > timed_budget_s:
+        return False
+    return elapsed_s + est_step_s + reserve_s <= budget_s
+
+
+def config1_run(torch, h, seed, x_oracle):
+    """Factor + solve at N = 1024, NB = 64 on the GPU: median time, TFLOP/s,
+    scaled residual, and x against the oracle's x of the same system."""
+    import numpy as np
+    n, nb = CONFIG1_N, CONFIG1_NB
+    A0 = h.colmajor(n, n)
+    h.hpl_generate(seed, 0, A0)
+    b0 = h.colmajor(n, 1)
+    h.hpl_generate(seed, 1, b0)
+    A, x = torch.empty_like(A0), torch.empty_like(b0)
+    ts = []
+    for r in range(CONFIG1_WARM + CONFIG1_RUNS):
+        A.copy_(A0)
+        x.copy_(b0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ipiv, info = h.hpl_factor(A, nb)
+        h.hpl_solve(A, ipiv, x)
+        torch.cuda.synchronize()
+        if r >= CONFIG1_WARM:
+            ts.append(time.perf_counter() - t0)
+    res = h.hpl_residual(A0, x, b0)
+    med = float(np.median(ts))
+    out = {"n": n, "nb": nb, "runs": CONFIG1_RUNS, "gpu_median_s": round(med, 6),
+           "gpu_tflops": round(hpl_flops(n) / med / 1e12, 4), "scaled_residual": float(res[0])}
+    if x_oracle is not None:
+        xg = x.cpu().numpy()[:, 0]
+        out["x_rel_err_vs_oracle"] = float(np.max(np.abs(xg - x_oracle)) / np.max(np.abs(x_oracle)))
+    return out
+
+
+def bench_hpl(args, torch, h, dev):
+    n, nb = args.n, args.nb
+    log(f"device {torch.cuda.get_device_name(dev)}; N={n} NB={nb} look-ahead={args.lookahead}")
+    h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, args.lookahead)
+
+    # Warm-up (not timed): factor + solve at N = 4096 loads the code objects and
+    # the workspace; a full-size warm-up would add nothing else.
+    for _ in range(max(1, args.warmup)):
+        A_s = h.colmajor(4096, 4096)
+        h.hpl_generate(1, 0, A_s)
+        b_s = h.colmajor(4096, 1)
+        h.hpl_generate(1, 1, b_s)
+        piv_s, _ = h.hpl_factor(A_s, nb)
+        h.hpl_solve(A_s, piv_s, b_s)
+        del A_s, b_s, piv_s
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    peak_measured, _ = h.hpl_mfma_peak(200000)
+    log(f"measured FP64 MFMA peak (pure 16x16x4 loop): {peak_measured:.2f} TFLOP/s")
+
+    # CPU baseline (the oracle on this host's cores) and the small configuration
+    # next to it, before the full-size matrix takes the GPU memory.
+    base, x_small = None, None
+    if args.cpu_sample > 0:
+        sizes = [m for m in (1024, 2048, 4096, 8192) if m <= args.cpu_sample] or [args.cpu_sample]
+        log(f"oracle CPU baseline at N = {sizes} ...")
+        base, x_small = cpu_baseline(sizes, args.seed, host_threads())
+    cfg1 = config1_run(torch, h, args.seed, x_small if base and base["serial"][0]["n"] == CONFIG1_N else None)
+    log(f"N={CONFIG1_N} NB={CONFIG1_NB}: {cfg1}")
+    if base is not None:
+        s1 = base["serial"][0]
+        p1 = base["parallel"][0]
+        cfg1["oracle_serial_s"] = s1["seconds"]
+        cfg1["oracle_threaded_s"] = p1["seconds"]
+        cfg1["gpu_speedup_vs_oracle_serial"] = round(s1["seconds"] / cfg1["gpu_median_s"], 1)
+        base["config_n1024_nb64"] = cfg1
+
+    A = h.colmajor(n, n, ld=n + args.pad)
+    b = h.colmajor(n, 1)
+    x = h.colmajor(n, 1)
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+    log(f"allocated A: {A.stride(1) * n * 8 / 1e9:.1f} GB")
+
+    times = []
+    info = 0
+    est = 0.0
+    h.hpl_set_option(h.HPL_OPT_PROGRESS, args.progress)
+    while may_start_step(len(times), args.steps, time.time() - T_PROCESS_START, sum(times), est,
+                         args.budget, args.timed_budget):
+        step = len(times)
+        t_gen = time.perf_counter()
+        h.hpl_generate(args.seed, 0, A)
+        h.hpl_generate(args.seed, 1, b)
+        x.copy_(b)
+        torch.cuda.synchronize()
+        h.hpl_reset_stats()
+        h.hpl_set_option(h.HPL_OPT_TIMING, 1)
+        t0 = time.perf_counter()
+        _, info = h.hpl_factor(A, nb, ipiv=ipiv)
+        h.hpl_solve(A, ipiv, x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h.hpl_set_option(h.HPL_OPT_TIMING, 0)
+        times.append(dt)
+        est = time.perf_counter() - t_gen   # generation + factor + solve
+        log(f"step {step} (timed): {dt:.3f} s, {hpl_flops(n) / dt / 1e12:.2f} TFLOP/s, info={info}; "
+            f"{time.time() - T_PROCESS_START:.0f} s since start")
+    h.hpl_set_option(h.HPL_OPT_PROGRESS, 0)
+    stats = h.hpl_get_stats()  # last timed step
+
+    res = h.hpl_residual_gen(args.seed, n, x, b)
+    log(f"scaled residual {res[0]:.4g} ({'PASS' if res[0] < 16 else 'FAIL'})")
+
+    total = sum(times)
+    tflops = hpl_flops(n) * len(times) / total / 1e12
+    g = stats["gemm"]
+    gemm_tflops = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else None
+    phases = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in stats.items()}
+    out = {
+        "metric": METRIC,
+        "value": round(tflops, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": len(times),
+        "steps_requested": args.steps,
+        "warmup": args.warmup,
+        "warmup_note": "warm-up steps are factor + solve at N = 4096 (code objects, workspace)",
+        "ms_per_step": round(1e3 * total / len(times), 3),
+        "step_seconds": [round(t, 3) for t in times],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "pct_fp64_mfma_peak": round(100.0 * tflops / PEAK_FP64_MFMA_TFLOPS, 2),
+        "fp64_mfma_peak_measured": round(peak_measured, 3),
+        "pct_measured_fp64_mfma_peak": round(100.0 * tflops / peak_measured, 2) if peak_measured > 0 else None,
+        "config": {
+            "workload": f"HPL FP64 LU+solve, N={n}, NB={nb}, look-ahead {args.lookahead}, "
+                        f"A,b ~ U[-0.5,0.5) seed {args.seed}",
+            "n": n, "nb": nb, "lda": n + args.pad, "lookahead": args.lookahead,
+            "interchange_workgroups": h.hpl_get_option(h.HPL_OPT_LASWP_WGS), "seed": args.seed,
+            "scaled_residual": float(res[0]), "residual_pass": bool(res[0] < 16.0), "info": info,
+            "budget_s": args.budget, "timed_budget_s": args.timed_budget,
+            "phase_ms_last_step": phases,
+        },
+        "roofline": {
+            "kernel": "gemm_stream_kernel (trailing-update DGEMM, FP64 MFMA 16x16x4)",
+            "bound": "mfma",
+            "achieved": round(gemm_tflops, 3) if gemm_tflops else None,
+            "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(gemm_tflops / PEAK_FP64_MFMA_TFLOPS, 4) if gemm_tflops else None,
+            "launches": g["launches"],
+            "avg_launch_ms": round(g["ms"] / g["launches"], 4) if g["launches"] else None,
+            "avg_launch_gflop": round(g["flops"] / g["launches"] / 1e9, 3) if g["launches"] else None,
+            "traffic": measured_traffic(n, nb),
+            "traffic_unit": "bytes per launch (L2-miss fetch + write, rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated; includes MALL hits)",
+            "algorithmic_bytes_per_launch": round(g["bytes"] / g["launches"]) if g["launches"] else None,
+        },
+    }
+    if base is not None:
+        out["cpu_baseline"] = base
+    else:
+        out["config_n1024_nb64"] = cfg1
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="full-size steps requested (hpl: bounded by --timed-budget and --budget)")
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed warm-up steps (hpl: factor + solve at N = 4096)")
+    ap.add_argument("--timed-budget", type=float, default=100.0,
+                    help="hpl: seconds of timed full-size work after which no further step starts")
+    ap.add_argument("--budget", type=float, default=420.0,
+                    help="hpl: seconds from process start after which no further step starts")
     ap.add_argument("--n", type=int, default=163840)
     ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--mxp-nb", type=int, default=1024, help="panel width of the mixed-precision LU (--workload mxp)")
     ap.add_argument("--lookahead", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2304)
     ap.add_argument("--pad", type=int, default=0, help="lda = n + pad")
-    ap.add_argument("--cpu-sample", type=int, default=4096, help="N of the oracle sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="largest N of the oracle timings (N = 1024, 2048, ... up to it; 0: skip)")
     ap.add_argument("--progress", type=int, default=32, help="progress line every k panels (stderr)")
     ap.add_argument("--workload", choices=["hpl", "diffsolve", "mxp", "batched", "hostpanel"], default="hpl",
                     help="hpl: the HPL factor + solve (default); diffsolve: the differentiable FP64 "
@@ -509,107 +758,7 @@ def main():
         return bench_batched(args, torch, h)
     if args.workload == "hostpanel":
         return bench_hostpanel(args, torch, h)
-    n, nb = args.n, args.nb
-    log(f"device {torch.cuda.get_device_name(dev)}; N={n} NB={nb} look-ahead={args.lookahead}")
-    h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, args.lookahead)
-
-    # Priming (not a step): load the code objects and the workspace on a small system.
-    A_s = h.colmajor(4096, 4096)
-    h.hpl_generate(1, 0, A_s)
-    b_s = h.colmajor(4096, 1)
-    h.hpl_generate(1, 1, b_s)
-    piv_s, _ = h.hpl_factor(A_s, nb)
-    h.hpl_solve(A_s, piv_s, b_s)
-    del A_s, b_s, piv_s
-    torch.cuda.synchronize()
-    torch.cuda.empty_cache()
-
-    peak_measured, _ = h.hpl_mfma_peak(200000)
-    log(f"measured FP64 MFMA peak (pure 16x16x4 loop): {peak_measured:.2f} TFLOP/s")
-
-    A = h.colmajor(n, n, ld=n + args.pad)
-    b = h.colmajor(n, 1)
-    x = h.colmajor(n, 1)
-    ipiv = torch.empty(n, dtype=torch.int32, device=dev)
-    log(f"allocated A: {A.stride(1) * n * 8 / 1e9:.1f} GB")
-
-    times = []
-    info = 0
-    h.hpl_set_option(h.HPL_OPT_PROGRESS, args.progress)
-    for step in range(args.warmup + args.steps):
-        timed = step >= args.warmup
-        h.hpl_generate(args.seed, 0, A)
-        h.hpl_generate(args.seed, 1, b)
-        x.copy_(b)
-        torch.cuda.synchronize()
-        if timed:
-            h.hpl_reset_stats()
-            h.hpl_set_option(h.HPL_OPT_TIMING, 1)
-        t0 = time.perf_counter()
-        _, info = h.hpl_factor(A, nb, ipiv=ipiv)
-        h.hpl_solve(A, ipiv, x)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        h.hpl_set_option(h.HPL_OPT_TIMING, 0)
-        log(f"step {step} ({'timed' if timed else 'warmup'}): {dt:.3f} s, "
-            f"{hpl_flops(n) / dt / 1e12:.2f} TFLOP/s, info={info}")
-        if timed:
-            times.append(dt)
-    h.hpl_set_option(h.HPL_OPT_PROGRESS, 0)
-    stats = h.hpl_get_stats()  # last timed step
-
-    res = h.hpl_residual_gen(args.seed, n, x, b)
-    log(f"scaled residual {res[0]:.4g} ({'PASS' if res[0] < 16 else 'FAIL'})")
-
-    total = sum(times)
-    tflops = hpl_flops(n) * len(times) / total / 1e12
-    g = stats["gemm"]
-    gemm_tflops = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else None
-    phases = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in stats.items()}
-    out = {
-        "metric": METRIC,
-        "value": round(tflops, 4),
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * total / len(times), 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "pct_fp64_mfma_peak": round(100.0 * tflops / PEAK_FP64_MFMA_TFLOPS, 2),
-        "fp64_mfma_peak_measured": round(peak_measured, 3),
-        "pct_measured_fp64_mfma_peak": round(100.0 * tflops / peak_measured, 2) if peak_measured > 0 else None,
-        "config": {
-            "workload": f"HPL FP64 LU+solve, N={n}, NB={nb}, look-ahead {args.lookahead}, "
-                        f"A,b ~ U[-0.5,0.5) seed {args.seed}",
-            "n": n, "nb": nb, "lda": n + args.pad, "lookahead": args.lookahead,
-            "interchange_workgroups": h.hpl_get_option(h.HPL_OPT_LASWP_WGS), "seed": args.seed,
-            "scaled_residual": float(res[0]), "residual_pass": bool(res[0] < 16.0), "info": info,
-            "phase_ms_last_step": phases,
-        },
-        "roofline": {
-            "kernel": "gemm_stream_kernel (trailing-update DGEMM, FP64 MFMA 16x16x4)",
-            "bound": "mfma",
-            "achieved": round(gemm_tflops, 3) if gemm_tflops else None,
-            "peak": PEAK_FP64_MFMA_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(gemm_tflops / PEAK_FP64_MFMA_TFLOPS, 4) if gemm_tflops else None,
-            "launches": g["launches"],
-            "avg_launch_ms": round(g["ms"] / g["launches"], 4) if g["launches"] else None,
-            "avg_launch_gflop": round(g["flops"] / g["launches"] / 1e9, 3) if g["launches"] else None,
-            "traffic": measured_traffic(n, nb),
-            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "algorithmic_bytes_per_launch": round(g["bytes"] / g["launches"]) if g["launches"] else None,
-        },
-    }
-    if args.cpu_sample > 0:
-        log(f"oracle CPU baseline at N={args.cpu_sample} ...")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.seed)
-    print(json.dumps(out), flush=True)
-
+    return bench_hpl(args, torch, h, dev)
 
 if __name__ == "__main__":
     main()

@@ -36,6 +36,8 @@ def lib():
         L.oracle_gen.argtypes = [u64, u64, P, i64, i64, i64]
         L.oracle_lu.restype = None
         L.oracle_lu.argtypes = [P, i64, i64, P, P]
+        L.oracle_lu_par.restype = ctypes.c_int
+        L.oracle_lu_par.argtypes = [P, i64, i64, P, P, ctypes.c_int]
         L.oracle_solve.restype = None
         L.oracle_solve.argtypes = [P, P, P, i64, i64, i64, i64, ctypes.c_int]
         L.oracle_residual.restype = None
@@ -106,6 +108,20 @@ def lu(A: np.ndarray):
     info = ctypes.c_int64(0)
     lib().oracle_lu(_ptr(A), n, _ld(A), _ptr(ipiv), ctypes.byref(info))
     return ipiv[:n], int(info.value)
+
+
+def lu_par(A: np.ndarray, threads: int):
+    """lu() on `threads` host threads (the rank-1 update's columns split among
+    them); bitwise the same result.  Returns (ipiv, info, threads that took part)."""
+    _check(A)
+    n = A.shape[0]
+    assert A.shape[1] == n
+    ipiv = np.zeros(max(n, 1), dtype=np.int32)
+    info = ctypes.c_int64(0)
+    used = lib().oracle_lu_par(_ptr(A), n, _ld(A), _ptr(ipiv), ctypes.byref(info), int(threads))
+    if used < 1:
+        raise RuntimeError("oracle_lu_par could not start its threads")
+    return ipiv[:n], int(info.value), int(used)
 
 
 def solve(LU: np.ndarray, ipiv: np.ndarray, B: np.ndarray, trans: int = 0):

@@ -1,6 +1,6 @@
 """Build the CPU oracle (test infrastructure): oracle/liboracle.so from oracle.c.
 
-Plain gcc, -O2, no FMA contraction, no OpenMP, no GPU code.
+Plain gcc, -O2, no FMA contraction, POSIX threads for the timing-only parallel LU, no GPU code.
 """
 import os
 import subprocess
@@ -13,7 +13,7 @@ def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "oracle.c")
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
+           "-Wall", "-Wextra", "-pthread", "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)

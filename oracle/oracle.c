@@ -33,11 +33,13 @@
  * LAPACK (scipy) as an independent opinion, and the published SplitMix64
  * output sequence for the generator.
  */
+#define _POSIX_C_SOURCE 200809L /* pthread barriers under -std=c99 */
 #include <stdint.h>
 #include <stddef.h>
 #include <math.h>
 #include <string.h>
 #include <stdlib.h>
+#include <pthread.h>
 
 #define IDX(i, j, ld) ((size_t)(i) + (size_t)(j) * (size_t)(ld))
 
@@ -134,6 +136,123 @@ void oracle_lu(double *A, int64_t n, int64_t lda, int32_t *ipiv, int64_t *info)
                 A[IDX(i, j, lda)] = A[IDX(i, j, lda)] - A[IDX(i, k, lda)] * ukj;
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same factorization on T host threads (used only to time the oracle on */
+/* every core of a host).  The steps are those of oracle_lu, in the same     */
+/* order: thread 0 finds the pivot, interchanges the rows and divides the    */
+/* column; then the rank-1 update's columns j > k are split into T contiguous */
+/* ranges, one per thread, with a barrier before and after.  Every element   */
+/* receives exactly the operations of oracle_lu in the same order, so the    */
+/* result is bitwise that of oracle_lu for any T.                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double *A;
+    int64_t n, lda;
+    int32_t *ipiv;
+    int64_t *info;
+    int threads;              /* threads taking part (those that could be started) */
+    int skip;                 /* step k has an all-zero pivot column */
+    int go;                   /* start gate, set once the thread count is known */
+    pthread_mutex_t mu;
+    pthread_cond_t cv;
+    pthread_barrier_t bar;
+} par_lu_t;
+
+typedef struct {
+    par_lu_t *p;
+    int tid;
+} par_arg_t;
+
+/* Thread 0's part of step k: pivot search, row interchange, division. */
+static void par_pivot_step(par_lu_t *p, int64_t k)
+{
+    double *A = p->A;
+    const int64_t n = p->n, lda = p->lda;
+    int64_t piv_row = k;
+    double amax = fabs(A[IDX(k, k, lda)]);
+    for (int64_t i = k + 1; i < n; ++i) {
+        double v = fabs(A[IDX(i, k, lda)]);
+        if (v > amax) { amax = v; piv_row = i; }
+    }
+    p->ipiv[k] = (int32_t)piv_row;
+    p->skip = amax == 0.0;
+    if (p->skip) {
+        if (*p->info == 0) *p->info = k + 1;
+        return;
+    }
+    if (piv_row != k) {
+        for (int64_t j = 0; j < n; ++j) {
+            double t = A[IDX(k, j, lda)];
+            A[IDX(k, j, lda)] = A[IDX(piv_row, j, lda)];
+            A[IDX(piv_row, j, lda)] = t;
+        }
+    }
+    double piv = A[IDX(k, k, lda)];
+    for (int64_t i = k + 1; i < n; ++i)
+        A[IDX(i, k, lda)] = A[IDX(i, k, lda)] / piv;
+}
+
+static void *par_worker(void *arg)
+{
+    par_lu_t *p = ((par_arg_t *)arg)->p;
+    const int tid = ((par_arg_t *)arg)->tid;
+    pthread_mutex_lock(&p->mu);
+    while (!p->go) pthread_cond_wait(&p->cv, &p->mu);
+    pthread_mutex_unlock(&p->mu);
+    double *A = p->A;
+    const int64_t n = p->n, lda = p->lda, T = p->threads;
+    for (int64_t k = 0; k < n; ++k) {
+        if (tid == 0) par_pivot_step(p, k);
+        pthread_barrier_wait(&p->bar);
+        if (!p->skip) {
+            /* this thread's share of the columns of the rank-1 update */
+            const int64_t cols = n - k - 1;
+            const int64_t j0 = k + 1 + cols * tid / T, j1 = k + 1 + cols * (tid + 1) / T;
+            for (int64_t j = j0; j < j1; ++j) {
+                double ukj = A[IDX(k, j, lda)];
+                for (int64_t i = k + 1; i < n; ++i)
+                    A[IDX(i, j, lda)] = A[IDX(i, j, lda)] - A[IDX(i, k, lda)] * ukj;
+            }
+        }
+        pthread_barrier_wait(&p->bar);
+    }
+    return NULL;
+}
+
+/* threads in [1, 256]; returns the number of threads that took part (fewer  */
+/* than asked if some could not be started), or -1 if nothing was computed.  */
+int oracle_lu_par(double *A, int64_t n, int64_t lda, int32_t *ipiv, int64_t *info, int threads)
+{
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    par_lu_t p;
+    p.A = A; p.n = n; p.lda = lda; p.ipiv = ipiv; p.info = info; p.skip = 0; p.go = 0;
+    *info = 0;
+    pthread_mutex_init(&p.mu, NULL);
+    pthread_cond_init(&p.cv, NULL);
+    pthread_t th[256];
+    par_arg_t args[256];
+    for (int t = 0; t < threads; ++t) { args[t].p = &p; args[t].tid = t; }
+    int started = 1;
+    for (int t = 1; t < threads; ++t) {
+        if (pthread_create(&th[t], NULL, par_worker, &args[t]) != 0) break;
+        ++started;
+    }
+    p.threads = started;
+    int ok = pthread_barrier_init(&p.bar, NULL, (unsigned)started) == 0;
+    if (!ok) p.n = 0; /* nothing to do: every thread leaves at once */
+    pthread_mutex_lock(&p.mu);
+    p.go = 1;
+    pthread_cond_broadcast(&p.cv);
+    pthread_mutex_unlock(&p.mu);
+    par_worker(&args[0]);
+    for (int t = 1; t < started; ++t) pthread_join(th[t], NULL);
+    if (ok) pthread_barrier_destroy(&p.bar);
+    pthread_cond_destroy(&p.cv);
+    pthread_mutex_destroy(&p.mu);
+    return ok ? started : -1;
 }
 
 /* ------------------------------------------------------------------------ */

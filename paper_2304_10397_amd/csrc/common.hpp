@@ -204,10 +204,12 @@ int launch_leaf_reg(double *A, int64_t lda, int64_t c, int64_t m, int w, int32_t
 // solve.hip
 // One diagonal block [r0, r0+bs) (bs <= 64, nrhs <= 64): finish it, then update
 // rows [row_begin, row_end).  mode: 0 = L unit lower (forward), 1 = U upper
-// (backward), 2 = U^T (forward), 3 = L^T unit (backward).
+// (backward), 2 = U^T (forward), 3 = L^T unit (backward).  done: a device word
+// that is zero between launches (the launch counts its workgroups on it and
+// leaves it at zero); launches that share it must not overlap in time.
 int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs,
                        int64_t r0, int64_t bs, int64_t row_begin, int64_t row_end, int mode,
-                       hipStream_t st);
+                       unsigned *done, hipStream_t st);
 // Applies nchunks plans (kPlanStride layout) to B in order, or in reverse order.
 int launch_apply_plans_seq(double *B, int64_t ldb, int64_t nrhs, const int32_t *plans,
                            int64_t nchunks, bool reverse, hipStream_t st);
@@ -247,6 +249,6 @@ int launch_mxp_residual(const double *A, int64_t lda, const double *x, const dou
                         bool anorm, double *part, unsigned long long *red, hipStream_t st);
 int launch_axpy(double *x, const double *d, int64_t n, hipStream_t st);
 int launch_solve_block_f32(const float *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs, int64_t r0, int64_t bs,
-                           int64_t row_begin, int64_t row_end, int mode, hipStream_t st);
+                           int64_t row_begin, int64_t row_end, int mode, unsigned *done, hipStream_t st);
 
 }  // namespace hplx

@@ -128,6 +128,7 @@ struct Device {
     int64_t red_cap = 0;
     unsigned long long *hbuf = nullptr;  // pinned host staging
     int *pivot_err = nullptr;            // raised by the plan kernel on an out-of-range pivot
+    unsigned *solve_done = nullptr;      // workgroup counter of the solve's block launches (zero between them)
     int32_t *splans = nullptr;           // interchange plans of every chunk of ipiv (solve)
     int64_t splan_cap = 0;
     std::vector<hipEvent_t> ev_pool;      // timing events
@@ -215,6 +216,7 @@ static int init_device(Device &d, int id)
     const size_t o_abort = o; o += 256;
     const size_t o_info = o; o += 256;
     const size_t o_perr = o; o += 256;
+    const size_t o_sdone = o; o += 256;
     const size_t o_slots = o; o = align_up(o + sizeof(double) * 2 * kLeafMaxWGs * kLeafSlot, 256);
     const size_t o_top = o; o = align_up(o + sizeof(double) * 2 * kLeafMaxW, 256);
     const size_t o_tslots = o; o = align_up(o + sizeof(unsigned long long) * 2 * kLeafMaxWGs * kLeafSlotWords, 256);
@@ -229,6 +231,7 @@ static int init_device(Device &d, int id)
     d.sync.abort_flag = (int *)(b + o_abort);
     d.sync.info = (unsigned long long *)(b + o_info);
     d.pivot_err = (int *)(b + o_perr);
+    d.solve_done = (unsigned *)(b + o_sdone);
     d.sync.slots = (double *)(b + o_slots);
     d.sync.top = (double *)(b + o_top);
     d.sync.tslots = (unsigned long long *)(b + o_tslots);
@@ -610,10 +613,11 @@ static int solve_impl(Device *d, const double *LU, const int32_t *ipiv, double *
             const int64_t r0 = (fwd ? q : nblk - 1 - q) * bs;
             const int64_t b = (n - r0) < bs ? (n - r0) : bs;
             const int64_t rb = fwd ? r0 + b : 0, re = fwd ? n : r0;
-            HPLX_PROPAGATE(launch_solve_block(LU, lda, Bc, ldb, nr, r0, b, rb, re, mode, st));
+            HPLX_PROPAGATE(launch_solve_block(LU, lda, Bc, ldb, nr, r0, b, rb, re, mode, d->solve_done, st));
         }
         return HPL_OK;
     };
+    HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)d->solve_done, 1, 0ull, st));
     if (trans == 0) HPLX_PROPAGATE(swaps(false));
     for (int64_t c0 = 0; c0 < nrhs; c0 += rhs_chunk) {
         const int64_t nr = (nrhs - c0) < rhs_chunk ? (nrhs - c0) : rhs_chunk;
@@ -793,11 +797,11 @@ static int mxp_solve_impl(Device *d, const double *A, int64_t lda, const float *
     auto lu_solve = [&](double *v) -> int {  // v <- U^{-1} L^{-1} v with the FP32 factors
         for (int64_t q = 0; q < nblk; ++q) {
             const int64_t r0 = q * bs, bb = (n - r0) < bs ? (n - r0) : bs;
-            HPLX_PROPAGATE(launch_solve_block_f32(LU, ldlu, v, n, 1, r0, bb, r0 + bb, n, 0, st));
+            HPLX_PROPAGATE(launch_solve_block_f32(LU, ldlu, v, n, 1, r0, bb, r0 + bb, n, 0, d->solve_done, st));
         }
         for (int64_t q = nblk - 1; q >= 0; --q) {
             const int64_t r0 = q * bs, bb = (n - r0) < bs ? (n - r0) : bs;
-            HPLX_PROPAGATE(launch_solve_block_f32(LU, ldlu, v, n, 1, r0, bb, 0, r0, 1, st));
+            HPLX_PROPAGATE(launch_solve_block_f32(LU, ldlu, v, n, 1, r0, bb, 0, r0, 1, d->solve_done, st));
         }
         return HPL_OK;
     };

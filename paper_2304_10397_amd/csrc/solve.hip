@@ -7,8 +7,10 @@
 //   * every workgroup of the launch first finishes the diagonal block itself:
 //     each wave takes up to 4 right-hand sides at a time (their recurrences
 //     interleaved), lane r holds x_r, and x_k reaches the other lanes by
-//     shuffle -- no barrier, no second launch (workgroup 0 also stores the
-//     finished rows);
+//     shuffle -- no barrier, no second launch.  Every workgroup reads the
+//     block's rows of B, so the finished rows are stored only by the last
+//     workgroup to have read them (a counter that returns to zero at the end
+//     of each launch), never while another workgroup may still read them;
 //   * then the workgroup subtracts the block's contribution from its share of
 //     the rows not yet solved, one row per thread (a skinny GEMV: for L and U
 //     the row's values are read coalesced across lanes; for the transposed
@@ -34,9 +36,10 @@ template <int mode, typename TT>
 __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const TT *__restrict__ T, int64_t ldt,
                                                                  double *__restrict__ B, int64_t ldb, int64_t nrhs,
                                                                  int64_t r0, int bs, int64_t row_begin,
-                                                                 int64_t row_end)
+                                                                 int64_t row_end, unsigned *__restrict__ done)
 {
     __shared__ double Td[kBs][kBs + 1];  // Td[r][c] = T(r0 + r, r0 + c), identity-padded past bs
+    __shared__ int last;
     extern __shared__ double Y[];        // [nrhs][kBs] solved block
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     constexpr bool lower = (mode == 0 || mode == 2);
@@ -106,12 +109,26 @@ __global__ __launch_bounds__(kSvThreads) void solve_block_kernel(const TT *__res
         }
 #pragma unroll
         for (int j = 0; j < kSvChain; ++j)
-            if (lane < bs && c0 + j < nrhs) {
-                Y[(c0 + j) * kBs + lane] = x[j];
-                if (blockIdx.x == 0) B[off(r0 + lane, c0 + j, ldb)] = x[j];
-            }
+            if (lane < bs && c0 + j < nrhs) Y[(c0 + j) * kBs + lane] = x[j];
+    }
+    // every load of the block's rows of B has been consumed above; the last
+    // workgroup to arrive stores the solved rows (the counter wraps to zero)
+    __syncthreads();
+    if (t == 0) {
+        if (gridDim.x == 1) {
+            last = 1;
+        } else {
+            __threadfence();
+            last = atomicInc(done, gridDim.x - 1) == gridDim.x - 1;
+        }
     }
     __syncthreads();
+    if (last) {
+        for (int64_t e = t; e < nrhs * kBs; e += kSvThreads) {
+            const int r = (int)(e % kBs);
+            if (r < bs) B[off(r0 + r, e / kBs, ldb)] = Y[e];
+        }
+    }
     if (row_end <= row_begin) return;
 
     // ---- 2. update of this workgroup's rows: one row per thread; the row's kBs
@@ -173,7 +190,7 @@ __global__ __launch_bounds__(kApThreads) void apply_plans_seq_kernel(double *__r
 }  // namespace
 
 int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs, int64_t r0, int64_t bs,
-                       int64_t row_begin, int64_t row_end, int mode, hipStream_t st)
+                       int64_t row_begin, int64_t row_end, int mode, unsigned *done, hipStream_t st)
 {
     if (bs <= 0 || nrhs <= 0) return HPL_OK;
     if (bs > kBs) return HPL_ERR_INTERNAL;
@@ -187,19 +204,19 @@ int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int
     switch (mode) {
     case 0:
         hipLaunchKernelGGL((solve_block_kernel<0, double>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
-                           r0, (int)bs, row_begin, row_end);
+                           r0, (int)bs, row_begin, row_end, done);
         break;
     case 1:
         hipLaunchKernelGGL((solve_block_kernel<1, double>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
-                           r0, (int)bs, row_begin, row_end);
+                           r0, (int)bs, row_begin, row_end, done);
         break;
     case 2:
         hipLaunchKernelGGL((solve_block_kernel<2, double>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
-                           r0, (int)bs, row_begin, row_end);
+                           r0, (int)bs, row_begin, row_end, done);
         break;
     case 3:
         hipLaunchKernelGGL((solve_block_kernel<3, double>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb, nrhs,
-                           r0, (int)bs, row_begin, row_end);
+                           r0, (int)bs, row_begin, row_end, done);
         break;
     default: return HPL_ERR_INTERNAL;
     }
@@ -209,7 +226,7 @@ int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int
 
 // FP32 factors (the mixed-precision LU), FP64 right-hand sides: modes 0 and 1.
 int launch_solve_block_f32(const float *T, int64_t ldt, double *B, int64_t ldb, int64_t nrhs, int64_t r0, int64_t bs,
-                           int64_t row_begin, int64_t row_end, int mode, hipStream_t st)
+                           int64_t row_begin, int64_t row_end, int mode, unsigned *done, hipStream_t st)
 {
     if (bs <= 0 || nrhs <= 0) return HPL_OK;
     if (bs > kBs) return HPL_ERR_INTERNAL;
@@ -221,10 +238,10 @@ int launch_solve_block_f32(const float *T, int64_t ldt, double *B, int64_t ldb, 
     if (lds > 64 * 1024) return HPL_ERR_INTERNAL;
     if (mode == 0)
         hipLaunchKernelGGL((solve_block_kernel<0, float>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb,
-                           nrhs, r0, (int)bs, row_begin, row_end);
+                           nrhs, r0, (int)bs, row_begin, row_end, done);
     else if (mode == 1)
         hipLaunchKernelGGL((solve_block_kernel<1, float>), dim3((unsigned)g), dim3(kSvThreads), lds, st, T, ldt, B, ldb,
-                           nrhs, r0, (int)bs, row_begin, row_end);
+                           nrhs, r0, (int)bs, row_begin, row_end, done);
     else
         return HPL_ERR_INTERNAL;
     HPLX_TRY_LAUNCH();

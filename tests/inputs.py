@@ -83,3 +83,52 @@ def upper_triangular(n, seed):
     U = np.triu(rng.random((n, n)) - 0.5)
     U[np.arange(n), np.arange(n)] += np.where(rng.random(n) < 0.5, -2.0, 2.0)
     return U
+
+
+# Exponents of the scaled mixed-precision construction below.
+MXP_L21_EXP = -30      # L21 entries are odd multiples of 2^-30
+MXP_U12_EXP = 27       # U12 entries are odd multiples of 2^27
+MXP_BIG = 2047         # the largest odd multiple (11 significant bits)
+
+
+def mxp_scaled_lu(n, w, seed):
+    """A = L U whose first panel (columns [0, w)) has multipliers far below FP16's
+    normal range and a U block row far above its largest value, so that FP16
+    copies of L21 and U12 are exact only after a power-of-two exchange of scale
+    between them.
+
+    L: unit lower.  L21 = rows >= w of columns < w: odd multiples of 2^-30 in
+    {+-1, +-3, +-5, +-7} * 2^-30, one entry 2047 * 2^-30 (at (i*, k*)); every
+    other strictly lower entry a multiple of 1/8 in [-1/2, 1/2].
+    U: upper, power-of-two diagonal (1, 2 or 4).  U12 = rows < w of columns >= w:
+    odd multiples of 2^27 in {+-1, ..., +-7} * 2^27, one entry 2047 * 2^27 (at
+    (k*, j*), the same k* as L's large entry, so the product 2047^2 * 2^-3
+    occurs); every other strictly upper entry an integer in [-7, 7].
+
+    FP32 holds every entry of A, of the panel's intermediate values and of the
+    trailing update's partial sums exactly (A12: multiples of 2^24 below 2^40;
+    A21: multiples of 2^-30 below 2^-14; A22: multiples of 1/8 below 2^21).
+    FP16 (11 significant bits, largest 65504, smallest subnormal 2^-24) holds
+    2^s L21 and 2^-s U12 exactly iff 22 <= s <= 35: 2^(s-30) >= 2^-24 and
+    2047 * 2^(s-30) <= 65504 for L21, 2047 * 2^(27-s) <= 65504 = 2047 * 2^5 and
+    2^(27-s) >= 2^-24 for U12.  Returns (A, L, U) as float64 Fortran arrays."""
+    rng = np.random.default_rng(seed)
+    odd = np.array([-7, -5, -3, -1, 1, 3, 5, 7], dtype=np.float64)
+    L = np.tril(rng.integers(-4, 5, (n, n)) / 8.0, -1) + np.eye(n)
+    U = np.triu(rng.integers(-7, 8, (n, n)).astype(np.float64), 1) + np.diag(2.0 ** rng.integers(0, 3, n))
+    m = n - w
+    if m > 0 and w > 0:
+        L[w:, :w] = rng.choice(odd, size=(m, w)) * 2.0 ** MXP_L21_EXP
+        U[:w, w:] = rng.choice(odd, size=(w, m)) * 2.0 ** MXP_U12_EXP
+        ib, kb, jb = w + int(rng.integers(0, m)), int(rng.integers(0, w)), w + int(rng.integers(0, m))
+        L[ib, kb] = MXP_BIG * 2.0 ** MXP_L21_EXP
+        U[kb, jb] = MXP_BIG * 2.0 ** MXP_U12_EXP
+    A = np.asfortranarray(L @ U)   # exact in fp64: see above
+    return A, L, U
+
+
+def fp16_exact(x):
+    """Whether every entry of the float64 array x is exactly an IEEE binary16 value."""
+    with np.errstate(over="ignore"):
+        h = x.astype(np.float16).astype(np.float64)
+    return bool(np.all(h == x))

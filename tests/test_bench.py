@@ -38,3 +38,57 @@ def test_flop_count_is_the_metric_formula():
     b = load_bench()
     for n in (1, 1024, 163840):
         assert b.hpl_flops(n) == 2.0 * n ** 3 / 3.0 + 2.0 * n ** 2
+
+
+def simulate(b, requested, startup_s, step_s, budget=420.0, timed_budget=100.0):
+    """Steps the benchmark's loop would run: (count, seconds since start at the end)."""
+    done, timed, est, clock = 0, 0.0, 0.0, startup_s
+    while b.may_start_step(done, requested, clock, timed, est, budget, timed_budget):
+        clock += step_s + 0.05      # generation + factor + solve
+        timed += step_s
+        est = step_s + 0.05
+        done += 1
+    return done, clock + b.RESERVE_S
+
+
+def test_step_budget_fits_the_driver_command():
+    """--steps 20 at about 46 s per full-size step: a bounded number of steps,
+    the whole run well inside 600 s even after a slow start."""
+    b = load_bench()
+    for startup in (20.0, 60.0, 150.0, 300.0):
+        for step in (40.0, 46.0, 60.0):
+            k, end = simulate(b, 20, startup, step)
+            assert k >= 1
+            assert end <= 420.0 + step + b.RESERVE_S
+            assert end < 560.0
+            assert k * step <= 100.0 + step    # the timed work stops near its budget
+    assert simulate(b, 20, 40.0, 46.0)[0] == 2
+    assert simulate(b, 1, 40.0, 46.0)[0] == 1
+    assert simulate(b, 0, 40.0, 46.0)[0] == 0
+    # short steps: the requested count is the limit
+    assert simulate(b, 20, 10.0, 1.0)[0] == 20
+
+
+def test_first_step_always_runs_and_later_ones_respect_the_process_budget():
+    b = load_bench()
+    assert b.may_start_step(0, 5, 10_000.0, 0.0, 0.0, 420.0, 100.0)
+    assert not b.may_start_step(1, 5, 380.0, 46.0, 46.0, 420.0, 1000.0)
+    assert b.may_start_step(1, 5, 300.0, 46.0, 46.0, 420.0, 1000.0)
+
+
+def test_projection_is_cubic_through_the_largest_point():
+    b = load_bench()
+    p = b.project_n3([(1024, 0.2), (4096, 12.8)], [8192, 163840])
+    assert p["8192"] == 102.4
+    assert abs(p["163840"] - 12.8 * 40.0 ** 3) < 0.1
+
+
+def test_cpu_baseline_fields_on_tiny_sizes():
+    b = load_bench()
+    base, x = b.cpu_baseline([64, 128], 2304, 3)
+    assert base["kind"] == "oracle" and base["unit"] == "TFLOP/s"
+    assert base["cores"] == 3 and base["threads"] == 3
+    assert [r["n"] for r in base["serial"]] == [64, 128] == [r["n"] for r in base["parallel"]]
+    assert set(base["projection"]["serial_seconds"]) == {"8192", "65536", "163840"}
+    assert "PROJECTION" in base["projection"]["note"]
+    assert x.shape == (64,)

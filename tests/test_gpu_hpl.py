@@ -203,8 +203,9 @@ def test_panel_base_variants_vs_oracle(base):
     assert np.max(np.abs(x - x_o)) <= XTOL * np.max(np.abs(x_o))
 
 
-@pytest.mark.parametrize("n,nrhs", [(300, 16), (1031, 4)])
+@pytest.mark.parametrize("n,nrhs", [(300, 16), (1031, 4), (600, 130)])
 def test_multi_rhs_and_transposed_vs_oracle(n, nrhs):
+    """nrhs = 130 runs the solve in chunks of 64 right-hand sides (64, 64, 2)."""
     h = hpl()
     A0, _, LU_o, ipiv_o, _, _ = oracle_solution(n)
     Bh = inputs.uniform_matrix(n, nrhs, n)

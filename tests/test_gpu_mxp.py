@@ -153,3 +153,30 @@ def test_mxp_zero_refinements_allowed():
     LU, _ = h.hpl_mxp_factor(A, nb=64, fmt=0)
     x, out = h.hpl_mxp_solve(A, LU, b, max_iter=0)
     assert out[0] == 0.0 and out[1] > 0.0
+
+
+@pytest.mark.parametrize("n,nb", [(256, 64), (2048, 256)])
+@pytest.mark.parametrize("la", [0, 1])
+def test_mxp_factor_scaling_exact(n, nb, la):
+    """The per-panel power-of-two scaling where it changes bits: the first
+    panel's FP16 copies of L21 (odd multiples of 2^-30) and U12 (up to 2047 *
+    2^27) are exact only for an exponent in [22, 35] (tests/inputs.py), so the
+    GPU factors equal the construction's L and U, and the oracle's, bit for
+    bit, only if the device computes the scaling exponent as the oracle does."""
+    import inputs
+    h = hpl()
+    A, L, U = inputs.mxp_scaled_lu(n, nb, seed=n + nb)
+    LUo, info_o = oracle.lu_mxp(A, nb, 0)
+    assert info_o == 0
+    old = h.hpl_get_option(h.HPL_OPT_LOOKAHEAD)
+    try:
+        h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, la)
+        LU, info = h.hpl_mxp_factor(to_gpu(A), nb=nb, fmt=0)
+    finally:
+        h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, old)
+    assert info == 0
+    G = LU.cpu().numpy()
+    assert np.array_equal(G.view(np.int32), np.asfortranarray(LUo).view(np.int32))
+    G = G.astype(np.float64)
+    assert np.array_equal(np.tril(G, -1) + np.eye(n), L)
+    assert np.array_equal(np.triu(G), U)

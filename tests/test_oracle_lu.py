@@ -203,3 +203,36 @@ def test_tie_explicit_column():
     A = np.array([[1.0, 2.0, 0.5], [-1.0, 1.0, 3.0], [1.0, 0.0, 1.0]])
     _, ipiv, _ = factor(A)
     assert ipiv[0] == 0
+
+
+@pytest.mark.parametrize("n,threads", [(1, 4), (37, 3), (300, 8), (301, 16), (520, 5)])
+def test_parallel_form_bitwise(n, threads):
+    """The threaded form (used only to time the oracle on every host core) gives
+    the bits of the serial oracle, pivots and info included; with a padded lda."""
+    A0 = inputs.fortran(oracle.gen(17, 0, n, n), ld=n + 3)
+    A1 = inputs.fortran(A0, ld=n + 3)
+    A2 = inputs.fortran(A0, ld=n + 3)
+    p1, i1 = oracle.lu(A1)
+    p2, i2, used = oracle.lu_par(A2, threads)
+    assert used == threads
+    assert i1 == i2 == 0
+    assert np.array_equal(p1, p2)
+    assert np.array_equal(A1.view(np.int64), A2.view(np.int64))
+
+
+def test_parallel_form_singular_and_dyadic():
+    # zero columns: info and the skipped steps as in the serial form
+    A = inputs.fortran(oracle.gen(3, 0, 60, 60))
+    A[:, 7] = 0.0
+    A[:, 40] = 0.0
+    B = inputs.fortran(A)
+    p1, i1 = oracle.lu(A)
+    p2, i2, _ = oracle.lu_par(B, 6)
+    assert i1 == i2 == 8
+    assert np.array_equal(p1, p2) and np.array_equal(A.view(np.int64), B.view(np.int64))
+    # exact factors of a dyadic construction
+    Ad, L, U, perm = inputs.dyadic_factors(200, 5)
+    F = inputs.fortran(Ad)
+    ipiv, info, _ = oracle.lu_par(F, 7)
+    assert info == 0
+    assert np.array_equal(np.tril(F, -1) + np.eye(200), L) and np.array_equal(np.triu(F), U)

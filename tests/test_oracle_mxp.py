@@ -101,3 +101,30 @@ def test_lu_mxp_unrounded_agrees_with_pivoting_oracle():
     LU32, info32 = oracle.lu_mxp(A, 32, oracle.FMT_NONE)
     assert info32 == 0
     assert np.max(np.abs(LU32 - LU64)) <= 1e-5 * np.max(np.abs(LU64))
+
+
+@pytest.mark.parametrize("n,nb", [(96, 32), (256, 64)])
+def test_lu_mxp_scaling_exchanges_exponents(n, nb):
+    """The per-panel power-of-two scaling, where it changes bits: the first
+    panel's multipliers lie below FP16's normal range (odd multiples of 2^-30)
+    and its U block row above FP16's largest value (odd multiples of 2^27, up
+    to 2047 * 2^27).  Only an exponent s in [22, 35] makes both FP16 copies
+    exact (the construction's docstring); the oracle must reproduce L and U bit
+    for bit in FP16, which an unscaled, sign-flipped or doubled s cannot."""
+    A, L, U = inputs.mxp_scaled_lu(n, nb, seed=n + nb)
+    L21, U12 = L[nb:, :nb], U[:nb, nb:]
+    # the construction is sensitive to the exponent: exact only inside the window
+    for s in range(-60, 61):
+        exact = inputs.fp16_exact(L21 * 2.0 ** s) and inputs.fp16_exact(U12 * 2.0 ** -s)
+        assert exact == (22 <= s <= 35), s
+    # the scaling rule's exponent (half the difference of the maxima's binary
+    # exponents, rounded away from zero) falls in the window: frexp gives
+    # e_L = -19 and e_U = 38, so s = 29, while -29, 0, 58 and 14 do not
+    LU, info = oracle.lu_mxp(A, nb, oracle.FMT_FP16)
+    assert info == 0
+    LU = LU.astype(np.float64)
+    assert np.array_equal(np.tril(LU, -1) + np.eye(n), L)
+    assert np.array_equal(np.triu(LU), U)
+    # unrounded (FP32 only) the same factors come back: the construction itself is exact in FP32
+    LU32, _ = oracle.lu_mxp(A, nb, oracle.FMT_NONE)
+    assert np.array_equal(LU32.astype(np.float64), LU)
