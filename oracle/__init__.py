@@ -50,6 +50,9 @@ def lib():
         L.oracle_gen_normal.argtypes = [u64, u64, P, i64, i64, i64]
         L.oracle_solve_grad.restype = i64
         L.oracle_solve_grad.argtypes = [P, i64, i64, P, i64, i64, P, i64, P, i64, P, i64, P, i64]
+        L.oracle_solve_grad_par.restype = i64
+        L.oracle_solve_grad_par.argtypes = [P, i64, i64, P, i64, i64, P, i64, P, i64, P, i64, P, i64,
+                                            ctypes.c_int]
         L.oracle_mxp_gen.restype = None
         L.oracle_mxp_gen.argtypes = [u64, P, i64, i64]
         L.oracle_round_fp16.restype = ctypes.c_float
@@ -189,8 +192,10 @@ def gen_normal(seed: int, stream: int, rows: int, cols: int, ld: int = None) -> 
     return buf[:rows, :]
 
 
-def solve_grad(A, B, W):
-    """(X, grad_B, grad_A, info) for X = A^{-1} B and the loss sum(W * X)."""
+def solve_grad(A, B, W, threads: int = 1):
+    """(X, grad_B, grad_A, info) for X = A^{-1} B and the loss sum(W * X).  With
+    threads > 1 the factorization runs on that many host threads (bitwise the
+    same factors, hence the same results)."""
     _check(A)
     n = A.shape[0]
     B = np.asfortranarray(B.reshape(n, -1), dtype=np.float64)
@@ -199,8 +204,12 @@ def solve_grad(A, B, W):
     X = np.zeros((n, nrhs), order="F")
     GB = np.zeros((n, nrhs), order="F")
     GA = np.zeros((n, n), order="F")
-    info = lib().oracle_solve_grad(_ptr(A), n, _ld(A), _ptr(B), _ld(B), nrhs, _ptr(W), _ld(W),
-                                   _ptr(X), max(n, 1), _ptr(GB), max(n, 1), _ptr(GA), max(n, 1))
+    args = (_ptr(A), n, _ld(A), _ptr(B), _ld(B), nrhs, _ptr(W), _ld(W),
+            _ptr(X), max(n, 1), _ptr(GB), max(n, 1), _ptr(GA), max(n, 1))
+    if threads > 1:
+        info = lib().oracle_solve_grad_par(*args, int(threads))
+    else:
+        info = lib().oracle_solve_grad(*args)
     return X, GB, GA, int(info)
 
 

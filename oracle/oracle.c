@@ -424,10 +424,13 @@ void oracle_gen_normal(uint64_t seed, uint64_t stream, double *M, int64_t rows, 
 /* explicit outer product summed over the right-hand sides in order.         */
 /* Outputs X (n x nrhs at ldx), GB (n x nrhs at ldgb), GA (n x n at ldga).   */
 /* Returns info of the factorization (0, or k+1 for a zero pivot).           */
+/* oracle_solve_grad_par is the same with the factorization on `threads`     */
+/* host threads (oracle_lu_par: bitwise the factors of oracle_lu), for the   */
+/* large systems whose reference would otherwise take minutes.               */
 /* ------------------------------------------------------------------------ */
-int64_t oracle_solve_grad(const double *A, int64_t n, int64_t lda, const double *B, int64_t ldb, int64_t nrhs,
-                          const double *W, int64_t ldw, double *X, int64_t ldx, double *GB, int64_t ldgb,
-                          double *GA, int64_t ldga)
+static int64_t solve_grad_impl(const double *A, int64_t n, int64_t lda, const double *B, int64_t ldb,
+                               int64_t nrhs, const double *W, int64_t ldw, double *X, int64_t ldx, double *GB,
+                               int64_t ldgb, double *GA, int64_t ldga, int threads)
 {
     if (n <= 0) return 0;
     double *LU = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
@@ -435,7 +438,11 @@ int64_t oracle_solve_grad(const double *A, int64_t n, int64_t lda, const double 
     int64_t info = 0;
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < n; ++i) LU[IDX(i, j, n)] = A[IDX(i, j, lda)];
-    oracle_lu(LU, n, n, ipiv, &info);
+    if (threads > 1) {
+        if (oracle_lu_par(LU, n, n, ipiv, &info, threads) < 1) oracle_lu(LU, n, n, ipiv, &info);
+    } else {
+        oracle_lu(LU, n, n, ipiv, &info);
+    }
     for (int64_t r = 0; r < nrhs; ++r)
         for (int64_t i = 0; i < n; ++i) {
             X[IDX(i, r, ldx)] = B[IDX(i, r, ldb)];
@@ -452,6 +459,20 @@ int64_t oracle_solve_grad(const double *A, int64_t n, int64_t lda, const double 
     free(LU);
     free(ipiv);
     return info;
+}
+
+int64_t oracle_solve_grad(const double *A, int64_t n, int64_t lda, const double *B, int64_t ldb, int64_t nrhs,
+                          const double *W, int64_t ldw, double *X, int64_t ldx, double *GB, int64_t ldgb,
+                          double *GA, int64_t ldga)
+{
+    return solve_grad_impl(A, n, lda, B, ldb, nrhs, W, ldw, X, ldx, GB, ldgb, GA, ldga, 1);
+}
+
+int64_t oracle_solve_grad_par(const double *A, int64_t n, int64_t lda, const double *B, int64_t ldb,
+                              int64_t nrhs, const double *W, int64_t ldw, double *X, int64_t ldx, double *GB,
+                              int64_t ldgb, double *GA, int64_t ldga, int threads)
+{
+    return solve_grad_impl(A, n, lda, B, ldb, nrhs, W, ldw, X, ldx, GB, ldgb, GA, ldga, threads);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -25,3 +25,18 @@ def keyed_fractions(name):
         rows = [[Fraction(t) for t in r.split()] for r in val.split(";")]
         out[key] = rows
     return out
+
+
+def diffsolve_reference(name):
+    """The differentiable-solve reference file: ({'X': max, ...}, {('X', r): (sum, abs sum)},
+    {'X': [(i, j, value)], ...}), floats from their hex form."""
+    maxabs, colsums, entries = {}, {}, {}
+    for line in _lines(name):
+        f = line.split()
+        if f[0] == "maxabs":
+            maxabs[f[1]] = float.fromhex(f[2])
+        elif f[0] == "colsum":
+            colsums[(f[1], int(f[2]))] = (float.fromhex(f[3]), float.fromhex(f[4]))
+        elif f[0] == "entry":
+            entries.setdefault(f[1], []).append((int(f[2]), int(f[3]), float.fromhex(f[4])))
+    return maxabs, colsums, entries

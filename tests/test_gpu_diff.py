@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from golden.load import diffsolve_reference
 from gpu_util import hpl, to_gpu, to_host, torch
 
 pytestmark = pytest.mark.gpu
@@ -162,3 +163,38 @@ def test_diff_solve_finite_differences_full_size():
             worst = max(worst, abs(fd - g) / (eps * l1 / hstep))
             assert abs(fd - g) <= 1e-6 * abs(g) + 1e4 * eps * l1 / hstep, (i, r, fd, g)
     print(f"finite differences: worst |fd - grad| = {worst:.3g} x eps*sum|W*X|/h (sum|W*X| = {l1:.4g})")
+
+
+def test_diff_solve_vs_oracle_full_size():
+    """N = 8192, NB = 256, 16 right-hand sides (the workload's size) against the
+    oracle's X, grad_B and grad_A, precomputed by tests/golden/make_diffsolve_n8192.py
+    (oracle only): sampled entries of all three within 1e-10 of the oracle's largest
+    entry, every column sum of X and grad_B within 1e-10 of its absolute sum, and
+    the largest magnitudes within 1e-10."""
+    h = hpl()
+    n, nrhs, nb = 8192, 16, 256
+    maxabs, colsums, entries = diffsolve_reference("diffsolve_n8192_oracle.txt")
+    A, B, W = diff_inputs(n, nrhs)
+    A.requires_grad_(True)
+    B.requires_grad_(True)
+    X = h.hpl_solve_diff(A, B, nb=nb)
+    (X * W).sum().backward()
+    got = {"X": to_host(X.detach()), "GB": to_host(B.grad)}
+    GA = A.grad.detach()
+    for name in ("X", "GB"):
+        M = got[name]
+        assert abs(np.max(np.abs(M)) - maxabs[name]) <= 1e-10 * maxabs[name], name
+        for r in range(nrhs):
+            s, sa = colsums[(name, r)]
+            assert abs(float(np.sum(M[:, r])) - s) <= 1e-10 * sa, (name, r)
+        worst = max(abs(M[i, j] - v) for i, j, v in entries[name]) / maxabs[name]
+        print(f"N={n} {name}: sampled relative error {worst:.2e}")
+        assert worst <= 1e-10, name
+    ga_max = float(GA.abs().max())
+    assert abs(ga_max - maxabs["GA"]) <= 1e-10 * maxabs["GA"]
+    idx = torch().tensor([[i, j] for i, j, _ in entries["GA"]], device="cuda")
+    vals = GA[idx[:, 0], idx[:, 1]].cpu().numpy()
+    ref = np.array([v for _, _, v in entries["GA"]])
+    worst = float(np.max(np.abs(vals - ref))) / maxabs["GA"]
+    print(f"N={n} GA: sampled relative error {worst:.2e}")
+    assert worst <= 1e-10

@@ -124,3 +124,18 @@ def test_grad_exact_rationals():
             assert abs(GBo[i, r] - float(GB[i][r])) <= 1e-14
         for j in range(4):
             assert abs(GAo[i, j] - float(GA[i][j])) <= 1e-14
+
+
+@pytest.mark.parametrize("n,k,threads", [(1, 1, 4), (97, 3, 3), (300, 16, 8)])
+def test_grad_threaded_bitwise(n, k, threads):
+    """The threaded form (factorization on several host threads) gives the
+    serial oracle's X, grad_B and grad_A bit for bit."""
+    A = oracle.gen(11, 0, n, n).copy(order="F")
+    A[np.arange(n), np.arange(n)] += 8.0
+    B = oracle.gen(11, 1, n, k).copy(order="F")
+    W = oracle.gen_normal(11, 2, n, k).copy(order="F")
+    ref = oracle.solve_grad(A, B, W)
+    got = oracle.solve_grad(A, B, W, threads=threads)
+    for r, g in zip(ref[:3], got[:3]):
+        assert np.array_equal(r.view(np.int64), g.view(np.int64))
+    assert ref[3] == got[3]
