@@ -96,6 +96,27 @@ int hpl_solve(const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, in
               int64_t lda, int64_t ldb, int trans, void *hip_stream);
 
 /*
+ * hpl_solve_noalloc -- hpl_solve for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments, kernels and results (bit for bit),
+ * but its scratch (the interchange plans of ipiv's 512-pivot chunks, a
+ * workgroup counter and an error word) lives in a fixed device array inside
+ * the library, HPL_SOLVE_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends.  No call allocates: no hipMalloc/hipFree, no events, no
+ * library workspace (the first call on a device only looks up the array's
+ * device address).
+ *   n > HPL_SOLVE_NOALLOC_MAX_N is rejected with -5 before any HIP call
+ *   (hpl_last_error_detail names the limit); other arguments as hpl_solve.
+ * All calls on one GPU share that GPU's array: calls that overlap in time on
+ * one GPU (other streams, other host threads) race.  Each call clears what
+ * must start at zero and returns after its work has completed.
+ */
+#define HPL_SOLVE_NOALLOC_MAX_N 262144
+#define HPL_SOLVE_NOALLOC_SCRATCH_BYTES (512 + 4 * 2112 * 512) /* 4.1 MiB */
+int hpl_solve_noalloc(const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, int64_t n,
+                      int64_t lda, int64_t ldb, int trans, void *hip_stream);
+
+/*
  * hpl_residual -- HPL acceptance test for A X = B with an explicit A.
  *   1 A0 device n x n at lda (the original matrix); 2 n; 3 lda >= max(1,n);
  *   4 X device n x nrhs at ldx; 5 ldx >= max(1,n); 6 B device n x nrhs at ldb;

@@ -213,6 +213,12 @@ int launch_solve_block(const double *T, int64_t ldt, double *B, int64_t ldb, int
 // Applies nchunks plans (kPlanStride layout) to B in order, or in reverse order.
 int launch_apply_plans_seq(double *B, int64_t ldb, int64_t nrhs, const int32_t *plans,
                            int64_t nchunks, bool reverse, hipStream_t st);
+// The whole solve of A X = B (trans 0) or A^T X = B (trans 1) with the factors
+// LU and ipiv, on stream st.  plans: ceil(n/kMaxSwaps) * kPlanStride int32;
+// pivot_err: raised (never cleared) on a pivot outside [k, n); done: a zero
+// word (the block launches leave it at zero).
+int solve_sequence(const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, int64_t n, int64_t lda,
+                   int64_t ldb, int trans, int32_t *plans, int *pivot_err, unsigned *done, hipStream_t st);
 
 // Pure FP64 MFMA issue loop (probe.hip): nwg workgroups of 256 threads, iters
 // rounds of 16 independent 16x16x4 MFMAs per wave; mfma_peak_flops is its flop count.

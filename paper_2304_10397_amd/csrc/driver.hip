@@ -597,40 +597,11 @@ static int solve_impl(Device *d, const double *LU, const int32_t *ipiv, double *
                       int64_t lda, int64_t ldb, int trans, hipStream_t st)
 {
     Timer tm(d, opt_timing.load() != 0);
-    const int64_t bs = 64;     // diagonal block (one row per lane)
-    const int64_t rhs_chunk = 64;
     const int64_t nchunks = (n + kMaxSwaps - 1) / kMaxSwaps;
     HPLX_PROPAGATE(ensure_solve_plans(d, nchunks));
     int id = tm.begin(ST_SOLVE, st);
-    auto swaps = [&](bool reverse) -> int {
-        HPLX_PROPAGATE(launch_swap_plans_all(ipiv, n, 0, n, reverse, d->splans, d->pivot_err, st));
-        return launch_apply_plans_seq(B, ldb, nrhs, d->splans, nchunks, reverse, st);
-    };
-    auto sweep = [&](int mode, double *Bc, int64_t nr) -> int {
-        const bool fwd = (mode == 0 || mode == 2);
-        const int64_t nblk = (n + bs - 1) / bs;
-        for (int64_t q = 0; q < nblk; ++q) {
-            const int64_t r0 = (fwd ? q : nblk - 1 - q) * bs;
-            const int64_t b = (n - r0) < bs ? (n - r0) : bs;
-            const int64_t rb = fwd ? r0 + b : 0, re = fwd ? n : r0;
-            HPLX_PROPAGATE(launch_solve_block(LU, lda, Bc, ldb, nr, r0, b, rb, re, mode, d->solve_done, st));
-        }
-        return HPL_OK;
-    };
     HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)d->solve_done, 1, 0ull, st));
-    if (trans == 0) HPLX_PROPAGATE(swaps(false));
-    for (int64_t c0 = 0; c0 < nrhs; c0 += rhs_chunk) {
-        const int64_t nr = (nrhs - c0) < rhs_chunk ? (nrhs - c0) : rhs_chunk;
-        double *Bc = B + off(0, c0, ldb);
-        if (trans == 0) {
-            HPLX_PROPAGATE(sweep(0, Bc, nr));
-            HPLX_PROPAGATE(sweep(1, Bc, nr));
-        } else {
-            HPLX_PROPAGATE(sweep(2, Bc, nr));
-            HPLX_PROPAGATE(sweep(3, Bc, nr));
-        }
-    }
-    if (trans == 1) HPLX_PROPAGATE(swaps(true));
+    HPLX_PROPAGATE(solve_sequence(LU, ipiv, B, nrhs, n, lda, ldb, trans, d->splans, d->pivot_err, d->solve_done, st));
     HPLX_PROPAGATE(tm.end(id, st, 2.0 * (double)n * (double)n * (double)nrhs, 8.0 * (double)n * (double)n));
     HPLX_TRY(hipMemcpyAsync(d->hbuf + 2, d->pivot_err, sizeof(int), hipMemcpyDeviceToHost, st));
     HPLX_TRY(hipStreamSynchronize(st));

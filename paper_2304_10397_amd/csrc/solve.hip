@@ -258,4 +258,44 @@ int launch_apply_plans_seq(double *B, int64_t ldb, int64_t nrhs, const int32_t *
     return HPL_OK;
 }
 
+// The whole solve on stream st: interchanges on B (A X = B: first; A^T X = B:
+// last, in reverse order), then per chunk of at most 64 right-hand sides the
+// forward and the backward sweep of 64-row diagonal blocks.
+int solve_sequence(const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, int64_t n, int64_t lda,
+                   int64_t ldb, int trans, int32_t *plans, int *pivot_err, unsigned *done, hipStream_t st)
+{
+    const int64_t bs = kBs;
+    const int64_t rhs_chunk = 64;
+    const int64_t nchunks = (n + kMaxSwaps - 1) / kMaxSwaps;
+    auto swaps = [&](bool reverse) -> int {
+        HPLX_PROPAGATE(launch_swap_plans_all(ipiv, n, 0, n, reverse, plans, pivot_err, st));
+        return launch_apply_plans_seq(B, ldb, nrhs, plans, nchunks, reverse, st);
+    };
+    auto sweep = [&](int mode, double *Bc, int64_t nr) -> int {
+        const bool fwd = (mode == 0 || mode == 2);
+        const int64_t nblk = (n + bs - 1) / bs;
+        for (int64_t q = 0; q < nblk; ++q) {
+            const int64_t r0 = (fwd ? q : nblk - 1 - q) * bs;
+            const int64_t b = (n - r0) < bs ? (n - r0) : bs;
+            const int64_t rb = fwd ? r0 + b : 0, re = fwd ? n : r0;
+            HPLX_PROPAGATE(launch_solve_block(LU, lda, Bc, ldb, nr, r0, b, rb, re, mode, done, st));
+        }
+        return HPL_OK;
+    };
+    if (trans == 0) HPLX_PROPAGATE(swaps(false));
+    for (int64_t c0 = 0; c0 < nrhs; c0 += rhs_chunk) {
+        const int64_t nr = (nrhs - c0) < rhs_chunk ? (nrhs - c0) : rhs_chunk;
+        double *Bc = B + off(0, c0, ldb);
+        if (trans == 0) {
+            HPLX_PROPAGATE(sweep(0, Bc, nr));
+            HPLX_PROPAGATE(sweep(1, Bc, nr));
+        } else {
+            HPLX_PROPAGATE(sweep(2, Bc, nr));
+            HPLX_PROPAGATE(sweep(3, Bc, nr));
+        }
+    }
+    if (trans == 1) HPLX_PROPAGATE(swaps(true));
+    return HPL_OK;
+}
+
 }  // namespace hplx

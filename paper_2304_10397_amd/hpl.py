@@ -58,6 +58,7 @@ def _load():
     sig = {
         "hpl_factor": (i32, [P, i64, i64, i64, P, P, P]),
         "hpl_solve": (i32, [P, P, P, i64, i64, i64, i64, i32, P]),
+        "hpl_solve_noalloc": (i32, [P, P, P, i64, i64, i64, i64, i32, P]),
         "hpl_residual": (i32, [P, i64, i64, P, i64, P, i64, i64, P, P]),
         "hpl_residual_gen": (i32, [u64, i64, P, i64, P, i64, i64, P, P]),
         "hpl_generate": (i32, [u64, u64, P, i64, i64, i64, P]),
@@ -88,7 +89,7 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("hpl_factor", "hpl_solve", "hpl_residual", "hpl_residual_gen", "hpl_generate",
+EXPORTED = ("hpl_factor", "hpl_solve", "hpl_solve_noalloc", "hpl_residual", "hpl_residual_gen", "hpl_generate",
             "hpl_set_option", "hpl_get_option", "hpl_get_stats", "hpl_reset_stats",
             "hpl_mfma_peak", "hpl_solve_grad_a", "hpl_generate_normal", "hpl_add_diagonal",
             "hpl_mxp_generate", "hpl_mxp_factor", "hpl_mxp_solve", "hpl_batched_sizes", "hpl_batched_solve",
@@ -180,6 +181,22 @@ def hpl_solve(LU, ipiv, B, trans=0, stream=None):
                         _stream(stream))
     _check("hpl_solve", rc)
     return B
+
+
+def hpl_solve_noalloc(LU, ipiv, B, trans=0, stream=None):
+    """hpl_solve with the library's fixed scratch array instead of allocated
+    workspace (n <= HPL_SOLVE_NOALLOC_MAX_N); same results."""
+    pLU, n, m, lda = _matrix("LU", LU)
+    pB, nb_, nrhs, ldb = _matrix("B", B)
+    if nb_ != n:
+        raise ValueError("B must have n rows")
+    rc = _lib.hpl_solve_noalloc(pLU, ctypes.c_void_p(ipiv.data_ptr()), pB, nrhs, n, lda, ldb, int(trans),
+                                _stream(stream))
+    _check("hpl_solve_noalloc", rc)
+    return B
+
+
+HPL_SOLVE_NOALLOC_MAX_N = 262144
 
 
 def hpl_residual(A0, X, B, stream=None):

@@ -180,3 +180,23 @@ def test_batched_argument_errors_and_sizes():
     for seed, cnt, lo, hi in ((2304, 4096, 32, 512), (7, 1000, 1, 100), (1, 10, 5, 5)):
         got = h.hpl_batched_sizes(seed, cnt, lo, hi)
         assert np.array_equal(got, oracle.batched_sizes(seed, cnt, lo, hi))
+
+
+def test_solve_noalloc_argument_errors():
+    """The no-allocation solve rejects sizes beyond its fixed scratch array (and
+    the other invalid arguments, as hpl_solve) on the host, before any HIP call."""
+    L = h.lib()
+    big = h.HPL_SOLVE_NOALLOC_MAX_N + 1
+    assert L.hpl_solve_noalloc(FAKE, FAKE, FAKE, 1, big, big, big, 0, None) == -5
+    assert b"HPL_SOLVE_NOALLOC_MAX_N" in L.hpl_last_error_detail()
+    assert L.hpl_solve_noalloc(None, FAKE, FAKE, 1, 10, 10, 10, 0, None) == -1
+    assert L.hpl_solve_noalloc(FAKE, None, FAKE, 1, 10, 10, 10, 0, None) == -2
+    assert L.hpl_solve_noalloc(FAKE, FAKE, None, 1, 10, 10, 10, 0, None) == -3
+    assert L.hpl_solve_noalloc(FAKE, FAKE, FAKE, -1, 10, 10, 10, 0, None) == -4
+    assert L.hpl_solve_noalloc(FAKE, FAKE, FAKE, 1, -1, 10, 10, 0, None) == -5
+    assert L.hpl_solve_noalloc(FAKE, FAKE, FAKE, 1, 10, 9, 10, 0, None) == -6
+    assert L.hpl_solve_noalloc(FAKE, FAKE, FAKE, 1, 10, 10, 9, 0, None) == -7
+    assert L.hpl_solve_noalloc(FAKE, FAKE, FAKE, 1, 10, 10, 10, 2, None) == -8
+    assert L.hpl_solve_noalloc(None, None, None, 1, 0, 1, 1, 0, None) == 0
+    hdr = open(HEADER).read()
+    assert f"#define HPL_SOLVE_NOALLOC_MAX_N {h.HPL_SOLVE_NOALLOC_MAX_N}" in hdr
