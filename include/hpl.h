@@ -268,10 +268,20 @@ enum hpl_option {
                                 look-ahead the whole trailing update of panel j, GEMM
                                 included, overlaps the host FACT of panel j+1.  0
                                 (default): the GPU panel.  Pinned staging: 8 n nb bytes. */
-    HPL_OPT_LASWP_WGS = 9    /* g > 0: the row interchanges of the trailing columns run on at
+    HPL_OPT_LASWP_WGS = 9,   /* g > 0: the row interchanges of the trailing columns run on at
                                 most g workgroups (each loops over 8-column groups), leaving
                                 the other CUs to the panel on the other stream (default 96);
                                 0: one workgroup per 8 columns.  Results do not depend on it. */
+    HPL_OPT_BATCH_CONFIG = 10, /* hpl_batched_solve's schedule.  0 (default): chosen from the
+                                tuned table (hpl_batched_config).  k = 1 + (occ - 1) *
+                                HPL_BATCH_VARIANTS + v forces occ in {1, 2} systems in
+                                flight per CU and variant v for every size (what the tuner
+                                measures).  The panel width and the solves' row
+                                block change the rounding order, so schedules agree
+                                to rounding, not bit for bit. */
+    HPL_OPT_MXP_GEMM = 11    /* hpl_mxp_factor's FP16/BF16 trailing update: 0 operands staged
+                                through registers, 1 through a ring of LDS DMA stages.
+                                Bit-identical results. */
 };
 /* Returns 0, or -1 (bad key) / -2 (bad value); the option is unchanged on error. */
 int hpl_set_option(int key, int64_t value);
@@ -346,6 +356,38 @@ int hpl_batched_sizes(uint64_t seed, int64_t count, int32_t nmin, int32_t nmax, 
  */
 int hpl_batched_solve(int64_t count, const int32_t *sizes, int64_t nrhs, double *A, int32_t *ipiv, double *B,
                       const double *W, double *GB, double *GA, int mode, int64_t *info, void *hip_stream);
+
+/*
+ * Schedules of hpl_batched_solve.  The factorization of a system comes in
+ * HPL_BATCH_VARIANTS variants -- panel width PB and columns of U12 per LDS
+ * stage UC of the trailing update: v = 0: PB 32, UC 128; 1: PB 32, UC 64;
+ * 2: PB 16, UC 128; 3: PB 16, UC 64 -- chosen per size bucket (n - 1) / 32,
+ * and the launch runs occ = 1 or 2 systems at a time on each CU (512-thread
+ * workgroups; with 2, one system's per-column barriers hide behind the
+ * other's work).  The library holds a table of measured costs, microseconds
+ * per system amortized over the whole device, for every (occ, v, bucket),
+ * written by the package's tuner (tune_batched.py) at nrhs = 4.
+ *
+ * hpl_batched_config -- the schedule the default option picks for a batch
+ * (host only, no GPU call): per occ, each bucket takes its cheapest variant;
+ * the occ whose predicted total (the sum of the systems' costs) is smaller
+ * wins.
+ *   1 count >= 0; 2 sizes host int32[count], 1 <= n_i <= 512
+ *   3 occ    host int* (written)
+ *   4 vtab   host int8[HPL_BATCH_BUCKETS] (written: the variant of each bucket)
+ *   5 predicted_ms  host double* (written; may be NULL)
+ */
+#define HPL_BATCH_VARIANTS 4
+#define HPL_BATCH_BUCKETS 16
+int hpl_batched_config(int64_t count, const int32_t *sizes, int *occ, int8_t *vtab, double *predicted_ms);
+
+/*
+ * hpl_batched_table -- the tuned table itself: cost[((occ - 1) *
+ * HPL_BATCH_VARIANTS + v) * HPL_BATCH_BUCKETS + bucket] in microseconds per
+ * system (2 * 4 * 16 doubles), and whether it came from a tuning run (1) or
+ * is the built-in default (0).
+ */
+int hpl_batched_table(double *cost, int *tuned);
 
 /*
  * Per-kernel-class statistics of the calls made since the last

@@ -45,13 +45,19 @@ namespace {
 
 constexpr int kBT = 512;               // threads per workgroup
 constexpr int kBW = kBT / 64;          // waves
-constexpr int kPB = 32;                // panel width
-constexpr int kKC = 8;                 // k per LDS stage of the trailing update
+constexpr int kPBmax = 32;             // widest panel of any variant
+constexpr int kSB = 32;                // row block of the solves and the adjoint
+constexpr int kKC = 8;                 // right-hand sides per LDS stage of the adjoint
 constexpr int kUpdRows = 4;            // 16-row blocks per wave in the trailing update (8 waves x 4 x 16 >= 480)
-constexpr int kUpdCols = 128;          // columns of U12 staged in LDS at a time
-constexpr int kMaxSlots = 2 * kPB;     // rows touched by one panel's interchanges
+constexpr int kUCmax = 128;            // widest U12 stage of any variant
 constexpr int kGc = 64;                // columns per chunk of the interchange pass
-static_assert(kBT % kMaxSlots == 0 && kGc % (kBT / kMaxSlots) == 0, "interchange pass shape");
+
+// Variants of the factorization (panel width PB, columns of U12 per LDS stage
+// UC); the tuner's table names them by index.
+constexpr int kNumVariants = 4;
+constexpr int kVarPB[kNumVariants] = {32, 32, 16, 16};
+constexpr int kVarUC[kNumVariants] = {128, 64, 128, 64};
+static_assert(kNumVariants == HPL_BATCH_VARIANTS, "variant count");
 
 struct BatchArgs {
     int64_t count;
@@ -69,24 +75,29 @@ struct BatchArgs {
     int mode;              // bit 0: factor + solve; bit 1: adjoint
     int64_t *info;         // [count]
     unsigned *counter;     // zero before the launch
+    signed char vtab[kBatchBuckets];  // variant of each size bucket (n - 1) / 32
 };
 
 struct BatchShared {
     union {
-        double Lc[kKC][kBatchMaxN];        // right-hand-side stage of the adjoint
-        double G[kGc][kMaxSlots + 1];      // interchange pass: [column][slot]
-        double Us[kPB][kUpdCols + 8];      // trailing update: U12 [k][column]
+        double Lc[kKC][kBatchMaxN];                // right-hand-side stage of the adjoint
+        double G32[kGc][2 * 32 + 1];               // interchange pass: [column][slot], PB = 32
+        double G16[kGc][2 * 16 + 1];               // ... PB = 16
+        double Us32x128[32][128 + 8];              // trailing update: U12 [k][column], per (PB, UC)
+        double Us32x64[32][64 + 8];
+        double Us16x128[16][128 + 8];
+        double Us16x64[16][64 + 8];
     };
-    double T[kPB][kPB + 1];                // diagonal block (L11, or a block of U / L for the solves)
-    double prow[2][kBW][kPB];              // per-wave candidate rows
-    double drow[2][kPB];                   // the diagonal row
+    double T[kPBmax][kPBmax + 1];          // diagonal block (L11, or a block of U / L for the solves)
+    double prow[2][kBW][kPBmax];           // per-wave candidate rows
+    double drow[2][kPBmax];                // the diagonal row
     double pv[2][kBW];                     // per-wave candidate |a|
     int pr[2][kBW];                        // per-wave candidate row (-1: none)
-    double Ys[kBatchMaxRhs][kPB];          // solved block of the solves
+    double Ys[kBatchMaxRhs][kSB];          // solved block of the solves
     int perm[kBatchMaxN];                  // row permutation: row i of P A is row perm[i] of A
-    int slot_row[kMaxSlots];               // interchange composition: destination rows ...
-    int slot_src[kMaxSlots];               // ... and the original row each receives
-    int pivs[kPB];                         // the panel's pivot rows, in column order
+    int slot_row[2 * kPBmax];              // interchange composition: destination rows ...
+    int slot_src[2 * kPBmax];              // ... and the original row each receives
+    int pivs[kPBmax];                      // the panel's pivot rows, in column order
     int nslots;
     int64_t info;
     int64_t job;
@@ -103,6 +114,23 @@ typedef __attribute__((address_space(1))) int32_t gi32;
 // phase functions below address it as LDS without a pointer argument)
 __shared__ BatchShared sh;
 
+// the interchange stage and the U12 stage of a variant
+template <int PB>
+__device__ __forceinline__ double &gstage(int c, int slot)
+{
+    if constexpr (PB == 32) return sh.G32[c][slot];
+    else return sh.G16[c][slot];
+}
+
+template <int PB, int UC>
+__device__ __forceinline__ double &ustage(int k, int j)
+{
+    if constexpr (PB == 32 && UC == 128) return sh.Us32x128[k][j];
+    else if constexpr (PB == 32) return sh.Us32x64[k][j];
+    else if constexpr (UC == 128) return sh.Us16x128[k][j];
+    else return sh.Us16x64[k][j];
+}
+
 __device__ __forceinline__ gf64 *col_ptr(gf64 *a, gf64 *b, int n, int c)
 {
     return c < n ? a + (size_t)c * (size_t)n : b + (size_t)(c - n) * (size_t)n;
@@ -114,8 +142,10 @@ __device__ __forceinline__ gf64 *col_ptr(gf64 *a, gf64 *b, int n, int c)
 // The column loop is not unrolled (the unrolled body overflows the
 // instruction cache): the register row rotates by one column per step, so the
 // current column is always v[0] and every register index is a constant.
+template <int PB, int OCC>
 __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, int k0)
 {
+    constexpr int kPB = PB;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int w = (n - k0) < kPB ? (n - k0) : kPB;
     const int r = k0 + t;
@@ -265,8 +295,11 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
     __syncthreads();
 }
 
+template <int PB, int OCC>
 __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int n, int ncol, int k0, int w)
 {
+    constexpr int kPB = PB, kMaxSlots = 2 * PB;
+    static_assert(kBT % kMaxSlots == 0 && kGc % (kBT / kMaxSlots) == 0, "interchange pass shape");
     const int t = threadIdx.x;
     // ---- 2. interchanges on every other column; U12 = L11^{-1} A12 on the right.
     //      Chunks of kGc columns through LDS: gather (lane = slot, so the
@@ -291,7 +324,7 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
 #pragma unroll
             for (int q = 0; q < kGc * kMaxSlots / kBT; ++q) {
                 const int cl = cq + q * (kBT / kMaxSlots);
-                sh.G[cl][slot] = gq[q];
+                gstage<PB>(cl, slot) = gq[q];
             }
             __syncthreads();
             if (t < ce) {
@@ -299,7 +332,7 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
                 if (c >= k0 + w) {
                     double x[kPB];
 #pragma unroll
-                    for (int i = 0; i < kPB; ++i) x[i] = sh.G[t][i];
+                    for (int i = 0; i < kPB; ++i) x[i] = gstage<PB>(t, i);
 #pragma unroll
                     for (int i = 1; i < kPB; ++i) {
                         if (i < w) {
@@ -311,7 +344,7 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
                         __builtin_amdgcn_sched_barrier(0);  // keep each row's LDS reads next to their use
                     }
 #pragma unroll
-                    for (int i = 0; i < kPB; ++i) sh.G[t][i] = x[i];
+                    for (int i = 0; i < kPB; ++i) gstage<PB>(t, i) = x[i];
                 }
             }
             __syncthreads();
@@ -322,7 +355,7 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
                     if (cl < ce) {
                         const int e = e0 + cl;
                         const int c = e < k0 ? e : e + w;
-                        col_ptr(a, b, n, c)[dst] = sh.G[cl][slot];
+                        col_ptr(a, b, n, c)[dst] = gstage<PB>(cl, slot);
                     }
                 }
             }
@@ -341,8 +374,10 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
 // comes out transposed: register r of lane l is C(16R + l%16, 16G + l/16 +
 // 4r), 16 consecutive rows per access.  Accumulators start from C; the
 // products are added in k order.
+template <int PB, int UC, int OCC>
 __device__ __attribute__((noinline)) void bat_update(gf64 *a, gf64 *b, int n, int ncol, int k0, int w)
 {
+    constexpr int kPB = PB, kUpdCols = UC;
     typedef double d4 __attribute__((ext_vector_type(4)));
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -377,64 +412,78 @@ __device__ __attribute__((noinline)) void bat_update(gf64 *a, gf64 *b, int n, in
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 const int e = t + q * kBT;
-                sh.Us[e % kPB][e / kPB] = uq[q];
+                ustage<PB, UC>(e % kPB, e / kPB) = uq[q];
             }
         }
         __syncthreads();
         const int g0 = cc0 >> 4;
         const int gn = (nG - g0) < (kUpdCols / 16) ? (nG - g0) : (kUpdCols / 16);
+        // per row block: the C values of all the stage's column blocks are
+        // loaded at once (clamped addresses, so no load waits on a branch),
+        // then each live block takes its MFMAs and is stored
+        constexpr int kGB = kUpdCols / 16;
 #pragma unroll
         for (int q = 0; q < kUpdRows; ++q) {
             const int R = wave + kBW * q;
             if (R < nR) {
                 const int row = r0 + 16 * R + li;
                 const int rc = row < n ? row : n - 1;
-                for (int g = 0; g < gn; ++g) {
-                    const int G = g0 + g;
-                    gf64 *cp[4];
-                    bool cok[4];
-                    d4 acc;
+                d4 cv[kGB];
+#pragma unroll
+                for (int g = 0; g < kGB; ++g)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int c = r0 + 16 * G + lg + 4 * r;
-                        cok[r] = c < ncol && row < n;
-                        cp[r] = col_ptr(a, b, n, c < ncol ? c : ncol - 1);
-                        acc[r] = cp[r][rc];
+                        const int c = r0 + 16 * (g0 + g) + lg + 4 * r;
+                        cv[g][r] = col_ptr(a, b, n, c < ncol ? c : ncol - 1)[rc];
                     }
+                // the store addresses are recomputed from a laundered copy of the
+                // stage's first column (so they are not kept live from the loads)
+                int c0s = r0 + 16 * g0;
+                asm volatile("" : "+v"(c0s));
 #pragma unroll
-                    for (int s4 = 0; s4 < kPB / 4; ++s4) {
-                        const double bu = sh.Us[4 * s4 + lg][16 * g + li];
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bu, af[q][s4], acc, 0, 0, 0);
+                for (int g = 0; g < kGB; ++g) {
+                    if (g < gn) {
+#pragma unroll
+                        for (int s4 = 0; s4 < kPB / 4; ++s4) {
+                            const double bu = ustage<PB, UC>(4 * s4 + lg, 16 * g + li);
+                            cv[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(bu, af[q][s4], cv[g], 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int c = c0s + 16 * g + lg + 4 * r;
+                            if (c < ncol && row < n) col_ptr(a, b, n, c)[row] = cv[g][r];
+                        }
                     }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (cok[r]) cp[r][row] = acc[r];
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);  // one row block's C in registers at a time
         }
         __syncthreads();
     }
 }
 
 // U X = Y, 32-row blocks from the bottom (Y = L^{-1} P B is in b)
+template <int OCC>
 __device__ __attribute__((noinline)) void bat_usolve(gcf64 *a, gf64 *b, int n, int nrhs)
 {
+    constexpr int kPB = OCC == 2 ? 16 : kSB;  // a narrower block keeps two systems per CU within 128 VGPRs
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nb0 = (n - 1) / kPB * kPB;
     for (int r0 = nb0; r0 >= 0; r0 -= kPB) {
         const int bw = (n - r0) < kPB ? (n - r0) : kPB;
         {
-            double tq[kPB * kPB / kBT];
+            constexpr int kTQ = (kPB * kPB + kBT - 1) / kBT;
+            double tq[kTQ];
 #pragma unroll
-            for (int q = 0; q < kPB * kPB / kBT; ++q) {
-                const int e = t + q * kBT, i = e % kPB, k = e / kPB;
+            for (int q = 0; q < kTQ; ++q) {
+                const int ee = t + q * kBT, e = ee < kPB * kPB ? ee : kPB * kPB - 1, i = e % kPB, k = e / kPB;
                 const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
                 tq[q] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
             }
 #pragma unroll
-            for (int q = 0; q < kPB * kPB / kBT; ++q) {
+            for (int q = 0; q < kTQ; ++q) {
                 const int e = t + q * kBT;
-                sh.T[e % kPB][e / kPB] = tq[q];
+                if (e < kPB * kPB) sh.T[e % kPB][e / kPB] = tq[q];
             }
         }
         __syncthreads();
@@ -475,8 +524,10 @@ __device__ __attribute__((noinline)) void bat_usolve(gcf64 *a, gf64 *b, int n, i
 // ---------------------------------------------------------------------------
 // forward: LU with partial pivoting of the augmented [A | B], then U X = Y
 // ---------------------------------------------------------------------------
+template <int PB, int UC, int OCC>
 __device__ void batch_forward(double *a, double *b, int32_t *ip, int n, int nrhs)
 {
+    constexpr int kPB = PB;
     const int t = threadIdx.x;
     const int ncol = n + nrhs;
     for (int i = t; i < n; i += kBT) sh.perm[i] = i;
@@ -484,19 +535,21 @@ __device__ void batch_forward(double *a, double *b, int32_t *ip, int n, int nrhs
     __syncthreads();
     for (int k0 = 0; k0 < n; k0 += kPB) {
         const int w = (n - k0) < kPB ? (n - k0) : kPB;
-        bat_panel((gf64 *)a, (gi32 *)ip, n, k0);
-        bat_interchange((gf64 *)a, (gf64 *)b, n, ncol, k0, w);
-        bat_update((gf64 *)a, (gf64 *)b, n, ncol, k0, w);
+        bat_panel<PB, OCC>((gf64 *)a, (gi32 *)ip, n, k0);
+        bat_interchange<PB, OCC>((gf64 *)a, (gf64 *)b, n, ncol, k0, w);
+        bat_update<PB, UC, OCC>((gf64 *)a, (gf64 *)b, n, ncol, k0, w);
     }
-    bat_usolve((gcf64 *)a, (gf64 *)b, n, nrhs);
+    bat_usolve<OCC>((gcf64 *)a, (gf64 *)b, n, nrhs);
 }
 
 // ---------------------------------------------------------------------------
 // adjoint: grad_B = A^{-T} W = P^T L^{-T} U^{-T} W, grad_A = -grad_B X^T
 // ---------------------------------------------------------------------------
+template <int OCC>
 __device__ __attribute__((noinline)) void batch_adjoint(gcf64 *a, gcf64 *x, gcf64 *wv, gf64 *gb,
                               gf64 *ga, int n, int nrhs)
 {
+    constexpr int kPB = OCC == 2 ? 16 : kSB;  // a narrower block keeps two systems per CU within 128 VGPRs
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     {
         constexpr int kQ = kBatchMaxN * kBatchMaxRhs / kBT;
@@ -513,17 +566,18 @@ __device__ __attribute__((noinline)) void batch_adjoint(gcf64 *a, gcf64 *x, gcf6
     for (int r0 = 0; r0 < n; r0 += kPB) {
         const int bw = (n - r0) < kPB ? (n - r0) : kPB;
         {
-            double tq[kPB * kPB / kBT];
+            constexpr int kTQ = (kPB * kPB + kBT - 1) / kBT;
+            double tq[kTQ];
 #pragma unroll
-            for (int q = 0; q < kPB * kPB / kBT; ++q) {
-                const int e = t + q * kBT, i = e % kPB, k = e / kPB;
+            for (int q = 0; q < kTQ; ++q) {
+                const int ee = t + q * kBT, e = ee < kPB * kPB ? ee : kPB * kPB - 1, i = e % kPB, k = e / kPB;
                 const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
                 tq[q] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
             }
 #pragma unroll
-            for (int q = 0; q < kPB * kPB / kBT; ++q) {
+            for (int q = 0; q < kTQ; ++q) {
                 const int e = t + q * kBT;
-                sh.T[e % kPB][e / kPB] = tq[q];
+                if (e < kPB * kPB) sh.T[e % kPB][e / kPB] = tq[q];
             }
         }
         __syncthreads();
@@ -561,17 +615,18 @@ __device__ __attribute__((noinline)) void batch_adjoint(gcf64 *a, gcf64 *x, gcf6
     for (int r0 = nb0; r0 >= 0; r0 -= kPB) {
         const int bw = (n - r0) < kPB ? (n - r0) : kPB;
         {
-            double tq[kPB * kPB / kBT];
+            constexpr int kTQ = (kPB * kPB + kBT - 1) / kBT;
+            double tq[kTQ];
 #pragma unroll
-            for (int q = 0; q < kPB * kPB / kBT; ++q) {
-                const int e = t + q * kBT, i = e % kPB, k = e / kPB;
+            for (int q = 0; q < kTQ; ++q) {
+                const int ee = t + q * kBT, e = ee < kPB * kPB ? ee : kPB * kPB - 1, i = e % kPB, k = e / kPB;
                 const int ic = i < bw ? i : bw - 1, kc = k < bw ? k : bw - 1;
                 tq[q] = a[(size_t)(r0 + ic) + (size_t)(r0 + kc) * (size_t)n];
             }
 #pragma unroll
-            for (int q = 0; q < kPB * kPB / kBT; ++q) {
+            for (int q = 0; q < kTQ; ++q) {
                 const int e = t + q * kBT;
-                sh.T[e % kPB][e / kPB] = tq[q];
+                if (e < kPB * kPB) sh.T[e % kPB][e / kPB] = tq[q];
             }
         }
         __syncthreads();
@@ -665,7 +720,9 @@ __device__ __attribute__((noinline)) void batch_adjoint(gcf64 *a, gcf64 *x, gcf6
     }
 }
 
-__global__ __launch_bounds__(kBT) void batched_solve_kernel(BatchArgs p)
+// OCC workgroups per CU (systems in flight per CU): 2 * OCC waves per SIMD
+template <int OCC>
+__global__ __launch_bounds__(kBT, 2 * OCC) void batched_solve_kernel(BatchArgs p)
 {
     const int t = threadIdx.x;
     for (;;) {
@@ -681,7 +738,12 @@ __global__ __launch_bounds__(kBT) void batched_solve_kernel(BatchArgs p)
         double *b = p.B + (size_t)vo * (size_t)p.nrhs;
         int32_t *ip = p.ipiv + vo;
         if (p.mode & 1) {
-            batch_forward(a, b, ip, n, p.nrhs);
+            switch (p.vtab[(n - 1) >> 5]) {  // uniform across the workgroup
+            case 0: batch_forward<kVarPB[0], kVarUC[0], OCC>(a, b, ip, n, p.nrhs); break;
+            case 1: batch_forward<kVarPB[1], kVarUC[1], OCC>(a, b, ip, n, p.nrhs); break;
+            case 2: batch_forward<kVarPB[2], kVarUC[2], OCC>(a, b, ip, n, p.nrhs); break;
+            default: batch_forward<kVarPB[3], kVarUC[3], OCC>(a, b, ip, n, p.nrhs); break;
+            }
         } else {
             // adjoint only: the row permutation from the stored interchanges
             if (t == 0) {
@@ -699,7 +761,7 @@ __global__ __launch_bounds__(kBT) void batched_solve_kernel(BatchArgs p)
             __syncthreads();
         }
         if (p.mode & 2)
-            batch_adjoint((gcf64 *)a, (gcf64 *)b, (gcf64 *)(p.W + (size_t)vo * (size_t)p.nrhs),
+            batch_adjoint<OCC>((gcf64 *)a, (gcf64 *)b, (gcf64 *)(p.W + (size_t)vo * (size_t)p.nrhs),
                           (gf64 *)(p.GB + (size_t)vo * (size_t)p.nrhs), (gf64 *)(p.GA + p.aoff[sys]), n, p.nrhs);
         if (t == 0) p.info[sys] = sh.info;
         __syncthreads();
@@ -710,14 +772,23 @@ __global__ __launch_bounds__(kBT) void batched_solve_kernel(BatchArgs p)
 
 int launch_batched_solve(int64_t count, const int32_t *sizes, const int64_t *aoff, const int64_t *voff,
                          const int32_t *order, double *A, int32_t *ipiv, double *B, const double *W, double *GB,
-                         double *GA, int nrhs, int mode, int64_t *info, unsigned *counter, int64_t nwg,
-                         hipStream_t st)
+                         double *GA, int nrhs, int mode, int64_t *info, unsigned *counter, int occ,
+                         const signed char *vtab, int cus, hipStream_t st)
 {
     if (count <= 0) return HPL_OK;
-    if (nrhs < 1 || nrhs > kBatchMaxRhs || mode < 1 || mode > 3 || nwg < 1) return HPL_ERR_INTERNAL;
-    BatchArgs p{count, sizes, aoff, voff, order, A, ipiv, B, W, GB, GA, nrhs, mode, info, counter};
-    const int64_t g = nwg < count ? nwg : count;
-    hipLaunchKernelGGL(batched_solve_kernel, dim3((unsigned)g), dim3(kBT), 0, st, p);
+    if (nrhs < 1 || nrhs > kBatchMaxRhs || mode < 1 || mode > 3 || cus < 1 || (occ != 1 && occ != 2))
+        return HPL_ERR_INTERNAL;
+    BatchArgs p{count, sizes, aoff, voff, order, A, ipiv, B, W, GB, GA, nrhs, mode, info, counter, {}};
+    for (int q = 0; q < kBatchBuckets; ++q) {
+        if (vtab[q] < 0 || vtab[q] >= kNumVariants) return HPL_ERR_INTERNAL;
+        p.vtab[q] = vtab[q];
+    }
+    const int64_t wgs = (int64_t)cus * occ;
+    const int64_t g = wgs < count ? wgs : count;
+    if (occ == 1)
+        hipLaunchKernelGGL(batched_solve_kernel<1>, dim3((unsigned)g), dim3(kBT), 0, st, p);
+    else
+        hipLaunchKernelGGL(batched_solve_kernel<2>, dim3((unsigned)g), dim3(kBT), 0, st, p);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }

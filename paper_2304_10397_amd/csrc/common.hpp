@@ -134,11 +134,14 @@ int host_panel_factor(double *P, int64_t m, int64_t nb, int64_t ld, int32_t *ipi
 // batched small systems (one persistent launch)
 constexpr int kBatchMaxN = 512;
 constexpr int kBatchMaxRhs = 16;
+constexpr int kBatchBuckets = kBatchMaxN / 32;  // size buckets (n - 1) / 32 of the tuned table
 constexpr uint64_t kBatchSizeStream = 3;  // generator stream of the batch's sizes
+// occ: workgroups (systems in flight) per CU, 1 or 2; vtab: the variant
+// (HPL_BATCH_VARIANTS of them) of each size bucket; cus: compute units.
 int launch_batched_solve(int64_t count, const int32_t *sizes, const int64_t *aoff, const int64_t *voff,
                          const int32_t *order, double *A, int32_t *ipiv, double *B, const double *W, double *GB,
-                         double *GA, int nrhs, int mode, int64_t *info, unsigned *counter, int64_t nwg,
-                         hipStream_t st);
+                         double *GA, int nrhs, int mode, int64_t *info, unsigned *counter, int occ,
+                         const signed char *vtab, int cus, hipStream_t st);
 
 // gemm.hip: C(m x n) -= A(m x k) * B(k x n).  variant: 0 auto, 1..4 tile shape;
 // OR kGemmTrailing for the trailing update (a separately named instance).
@@ -247,8 +250,10 @@ int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int
                      unsigned *mx, int *sexp, hipStream_t st);
 int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols,
                        int w, const int *sexp, void *A16, void *B16, hipStream_t st);
+// kernel: 0 = operands staged through registers, 1 = through a ring of LDS DMA
+// stages (bit-identical results).
 int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, const void *B16, float *C,
-                        int64_t ldc, hipStream_t st);
+                        int64_t ldc, int kernel, hipStream_t st);
 // r = b - A x with kResSplit column chunks; part holds 2 kResSplit n doubles of partial sums.
 constexpr int kResSplit = 16;
 int launch_mxp_residual(const double *A, int64_t lda, const double *x, const double *b, double *r, int64_t n,

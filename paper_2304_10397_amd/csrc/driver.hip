@@ -68,7 +68,9 @@ static std::atomic<int64_t> opt_progress{0};
 static std::atomic<int64_t> opt_serialize{0};
 static std::atomic<int64_t> opt_gemm_tile{0};
 static std::atomic<int64_t> opt_laswp_wgs{96};
-static std::atomic<int64_t> opt_host_panel{0};  // threads of the host panel (0: panel on the GPU)
+static std::atomic<int64_t> opt_host_panel{0};
+static std::atomic<int64_t> opt_batch_config{0};  // 0: tuned table; else a forced schedule
+static std::atomic<int64_t> opt_mxp_gemm{0};      // FP16/BF16 trailing update: 0 register-staged, 1 LDS DMA ring  // threads of the host panel (0: panel on the GPU)
 
 // ---------------------------------------------------------------------------
 // statistics (HPL_OPT_TIMING)
@@ -703,7 +705,7 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         const int id = tm.begin(ST_MXP_GEMM, st);
         HPLX_PROPAGATE(launch_hgemm_update(fmt, ni, nc, w, (const uint16_t *)A16[q] + (size_t)i0 * (size_t)w,
                                            (const uint16_t *)B16[q] + (size_t)j0 * (size_t)w,
-                                           LU + off(c1 + i0, c1 + j0, ldlu), ldlu, st));
+                                           LU + off(c1 + i0, c1 + j0, ldlu), ldlu, (int)opt_mxp_gemm.load(), st));
         return tm.end(id, st, 2.0 * (double)ni * (double)nc * (double)w,
                       8.0 * (double)ni * (double)nc + 2.0 * (double)w * (double)(ni + nc));
     };
@@ -1076,6 +1078,14 @@ int hpl_set_option(int key, int64_t value)
         if (value < 0 || value > 65536) return -2;
         opt_laswp_wgs = value;
         return 0;
+    case HPL_OPT_BATCH_CONFIG:
+        if (value < 0 || value > 2 * HPL_BATCH_VARIANTS) return -2;
+        opt_batch_config = value;
+        return 0;
+    case HPL_OPT_MXP_GEMM:
+        if (value != 0 && value != 1) return -2;
+        opt_mxp_gemm = value;
+        return 0;
     default: return -1;
     }
 }
@@ -1092,6 +1102,8 @@ int64_t hpl_get_option(int key)
     case HPL_OPT_GEMM_TILE: return opt_gemm_tile;
     case HPL_OPT_HOST_PANEL: return opt_host_panel;
     case HPL_OPT_LASWP_WGS: return opt_laswp_wgs;
+    case HPL_OPT_BATCH_CONFIG: return opt_batch_config;
+    case HPL_OPT_MXP_GEMM: return opt_mxp_gemm;
     default: return INT64_MIN;
     }
 }
@@ -1177,6 +1189,62 @@ int hpl_batched_sizes(uint64_t seed, int64_t count, int32_t nmin, int32_t nmax, 
     return HPL_OK;
 }
 
+// The tuned table: kBatchCostUs[occ - 1][variant][bucket], microseconds per
+// system amortized over the device, and kBatchTableTuned (0: built-in default).
+#include "batched_tuned.inc"
+static_assert(sizeof(kBatchCostUs) == sizeof(double) * 2 * HPL_BATCH_VARIANTS * kBatchBuckets, "table shape");
+static_assert(kBatchBuckets == HPL_BATCH_BUCKETS, "bucket count");
+
+// Per occ, each bucket's cheapest variant; the occ with the smaller predicted
+// sum over the batch wins.
+static void batch_choose(int64_t count, const int32_t *sizes, int *occ, signed char *vtab, double *pred_ms)
+{
+    std::vector<int64_t> hist(kBatchBuckets, 0);
+    for (int64_t i = 0; i < count; ++i) ++hist[(size_t)((sizes[i] - 1) >> 5)];
+    double best = 1e300;
+    for (int o = 0; o < 2; ++o) {
+        signed char vt[kBatchBuckets];
+        double tot = 0.0;
+        for (int q = 0; q < kBatchBuckets; ++q) {
+            int bv = 0;
+            for (int v = 1; v < HPL_BATCH_VARIANTS; ++v)
+                if (kBatchCostUs[o][v][q] < kBatchCostUs[o][bv][q]) bv = v;
+            vt[q] = (signed char)bv;
+            tot += (double)hist[(size_t)q] * kBatchCostUs[o][bv][q];
+        }
+        if (tot < best) {
+            best = tot;
+            *occ = o + 1;
+            memcpy(vtab, vt, sizeof vt);
+        }
+    }
+    if (pred_ms) *pred_ms = best * 1e-3;
+}
+
+int hpl_batched_config(int64_t count, const int32_t *sizes, int *occ, int8_t *vtab, double *predicted_ms)
+{
+    if (count < 0) return -1;
+    if (count > 0 && sizes == nullptr) return -2;
+    for (int64_t i = 0; i < count; ++i)
+        if (sizes[i] < 1 || sizes[i] > kBatchMaxN) return -2;
+    if (occ == nullptr) return -3;
+    if (vtab == nullptr) return -4;
+    batch_choose(count, sizes, occ, (signed char *)vtab, predicted_ms);
+    return HPL_OK;
+}
+
+int hpl_batched_table(double *cost, int *tuned)
+{
+    if (cost == nullptr) return -1;
+    if (tuned == nullptr) return -2;
+    for (int o = 0; o < 2; ++o)
+        for (int v = 0; v < HPL_BATCH_VARIANTS; ++v)
+            for (int q = 0; q < kBatchBuckets; ++q)
+                cost[((size_t)o * HPL_BATCH_VARIANTS + v) * kBatchBuckets + q] = kBatchCostUs[o][v][q];
+    *tuned = kBatchTableTuned;
+    return HPL_OK;
+}
+
 int hpl_batched_solve(int64_t count, const int32_t *sizes, int64_t nrhs, double *A, int32_t *ipiv, double *B,
                       const double *W, double *GB, double *GA, int mode, int64_t *info, void *hip_stream)
 {
@@ -1226,12 +1294,21 @@ int hpl_batched_solve(int64_t count, const int32_t *sizes, int64_t nrhs, double 
     HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)(ws + o_cnt), 1, 0ull, st));
     int cus = 0;
     HPLX_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d->id));
+    int occ = 1;
+    signed char vtab[kBatchBuckets];
+    const int64_t forced = opt_batch_config.load();
+    if (forced == 0) {
+        batch_choose(count, sizes, &occ, vtab, nullptr);
+    } else {
+        occ = 1 + (int)((forced - 1) / HPL_BATCH_VARIANTS);
+        memset(vtab, (int)((forced - 1) % HPL_BATCH_VARIANTS), sizeof vtab);
+    }
     Timer tm(d, opt_timing.load() != 0);
     const int id = tm.begin(ST_BATCHED, st);
     HPLX_PROPAGATE(launch_batched_solve(count, (const int32_t *)(ws + o_sizes), (const int64_t *)(ws + o_aoff),
                                         (const int64_t *)(ws + o_voff), (const int32_t *)(ws + o_order), A, ipiv, B,
                                         W, GB, GA, (int)nrhs, mode, (int64_t *)(ws + o_info),
-                                        (unsigned *)(ws + o_cnt), (int64_t)cus, st));
+                                        (unsigned *)(ws + o_cnt), occ, vtab, cus, st));
     double fl = 0.0;
     for (int64_t i = 0; i < count; ++i) {
         const double n = (double)sizes[i];

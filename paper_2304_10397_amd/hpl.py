@@ -30,6 +30,10 @@ HPL_OPT_SERIALIZE = 6
 HPL_OPT_GEMM_TILE = 7
 HPL_OPT_HOST_PANEL = 8
 HPL_OPT_LASWP_WGS = 9
+HPL_OPT_BATCH_CONFIG = 10
+HPL_OPT_MXP_GEMM = 11
+HPL_BATCH_VARIANTS = 4
+HPL_BATCH_BUCKETS = 16
 
 STAT_CLASSES = ("gemm", "panel", "laswp", "trsm", "solve", "plan", "mxp_gemm", "mxp_fact", "grad_a", "batched")
 
@@ -77,6 +81,8 @@ def _load():
         "hpl_host_panel": (i32, [P, i64, i64, i64, P, i32, P]),
         "hpl_panel_factor": (i32, [P, i64, i64, i64, P, P, P]),
         "hpl_batched_solve": (i32, [i64, P, i64, P, P, P, P, P, P, i32, P, P]),
+        "hpl_batched_config": (i32, [i64, P, P, P, P]),
+        "hpl_batched_table": (i32, [P, P]),
         "hpl_release": (i32, []),
         "hpl_strerror": (ctypes.c_char_p, [i32]),
         "hpl_last_error_detail": (ctypes.c_char_p, []),
@@ -93,6 +99,7 @@ EXPORTED = ("hpl_factor", "hpl_solve", "hpl_solve_noalloc", "hpl_residual", "hpl
             "hpl_set_option", "hpl_get_option", "hpl_get_stats", "hpl_reset_stats",
             "hpl_mfma_peak", "hpl_solve_grad_a", "hpl_generate_normal", "hpl_add_diagonal",
             "hpl_mxp_generate", "hpl_mxp_factor", "hpl_mxp_solve", "hpl_batched_sizes", "hpl_batched_solve",
+            "hpl_batched_config", "hpl_batched_table",
             "hpl_host_panel", "hpl_panel_factor",
             "hpl_release", "hpl_strerror", "hpl_last_error_detail")
 
@@ -361,6 +368,27 @@ def batch_layout(sizes, nrhs):
     aoff = np.concatenate([[0], np.cumsum(sizes * sizes)[:-1]]) if sizes.size else np.zeros(0, np.int64)
     voff = np.concatenate([[0], np.cumsum(sizes)[:-1]]) if sizes.size else np.zeros(0, np.int64)
     return aoff, voff, int(np.sum(sizes * sizes)), int(np.sum(sizes)) * int(nrhs)
+
+
+def hpl_batched_config(sizes):
+    """The schedule hpl_batched_solve picks for these sizes by default:
+    (occ, variant per size bucket (numpy int8[16]), predicted ms)."""
+    sizes = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    occ = ctypes.c_int(0)
+    vtab = np.zeros(HPL_BATCH_BUCKETS, dtype=np.int8)
+    pred = ctypes.c_double(0.0)
+    _check("hpl_batched_config", _lib.hpl_batched_config(int(sizes.size), sizes.ctypes.data_as(ctypes.c_void_p),
+                                                         ctypes.byref(occ), vtab.ctypes.data_as(ctypes.c_void_p),
+                                                         ctypes.byref(pred)))
+    return int(occ.value), vtab, float(pred.value)
+
+
+def hpl_batched_table():
+    """(cost[occ-1, variant, bucket] in microseconds per system, tuned flag) of the library's table."""
+    cost = np.zeros((2, HPL_BATCH_VARIANTS, HPL_BATCH_BUCKETS))
+    tuned = ctypes.c_int(0)
+    _check("hpl_batched_table", _lib.hpl_batched_table(cost.ctypes.data_as(ctypes.c_void_p), ctypes.byref(tuned)))
+    return cost, bool(tuned.value)
 
 
 def hpl_batched_solve(sizes, A, ipiv, B, nrhs, W=None, GB=None, GA=None, mode=BATCH_FORWARD, stream=None):

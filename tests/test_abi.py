@@ -200,3 +200,23 @@ def test_solve_noalloc_argument_errors():
     assert L.hpl_solve_noalloc(None, None, None, 1, 0, 1, 1, 0, None) == 0
     hdr = open(HEADER).read()
     assert f"#define HPL_SOLVE_NOALLOC_MAX_N {h.HPL_SOLVE_NOALLOC_MAX_N}" in hdr
+
+
+def test_batched_schedule_choice():
+    """hpl_batched_config (host only) against a plain re-derivation from the
+    library's own table: per systems-per-CU, each size bucket's cheapest variant;
+    the smaller predicted total wins."""
+    import numpy as np
+    cost, tuned = h.hpl_batched_table()
+    assert cost.shape == (2, h.HPL_BATCH_VARIANTS, h.HPL_BATCH_BUCKETS) and np.all(cost > 0)
+    for seed, lo, hi in ((2304, 32, 512), (1, 1, 64), (7, 400, 512)):
+        sizes = h.hpl_batched_sizes(seed, 1000, lo, hi)
+        occ, vtab, pred = h.hpl_batched_config(sizes)
+        hist = np.bincount((sizes - 1) // 32, minlength=h.HPL_BATCH_BUCKETS)
+        best = [(float(np.sum(hist * cost[o].min(axis=0))), o + 1, cost[o].argmin(axis=0)) for o in (0, 1)]
+        tot, o_ref, v_ref = min(best, key=lambda b: b[0])
+        assert occ == o_ref
+        assert np.array_equal(vtab, v_ref.astype(np.int8))
+        assert abs(pred - tot * 1e-3) <= 1e-9 * max(1.0, tot)
+    assert h.lib().hpl_set_option(h.HPL_OPT_BATCH_CONFIG, 2 * h.HPL_BATCH_VARIANTS + 1) == -2
+    assert h.lib().hpl_get_option(h.HPL_OPT_BATCH_CONFIG) == 0

@@ -180,3 +180,30 @@ def test_full_size_batch_residuals_and_sampled_oracle():
         assert rel(X[nrhs * voff[i]:nrhs * voff[i] + n * nrhs], ref["X"]) <= 1e-10, (i, n)
         assert rel(GB.cpu().numpy()[nrhs * voff[i]:nrhs * voff[i] + n * nrhs], ref["GB"]) <= 1e-10, (i, n)
         assert rel(GA.cpu().numpy()[aoff[i]:aoff[i] + n * n], ref["GA"]) <= 1e-10, (i, n)
+
+
+CONFIGS = [(occ, v) for occ in (1, 2) for v in range(4)]
+
+
+@pytest.mark.parametrize("occ,v", CONFIGS)
+def test_every_schedule_vs_oracle(occ, v):
+    """Every schedule the tuner can choose (systems per CU occ, variant v: panel
+    width and U12 stage width), forced for the whole batch: factor + solve +
+    adjoint in one launch against the oracle, on sizes that straddle the panel
+    widths (16, 32), the solves' row blocks and the update's stage widths."""
+    h = hpl()
+    sizes = np.concatenate([np.array([1, 2, 15, 16, 17, 31, 32, 33, 48, 64, 65, 100, 130, 200, 257, 512],
+                                     dtype=np.int32), h.hpl_batched_sizes(9, 20, 1, 300)])
+    nrhs = 4
+    A, B, W, GB, GA, ipiv = gpu_batch(sizes, nrhs, adjoint=True)
+    h.hpl_set_option(h.HPL_OPT_BATCH_CONFIG, 1 + (occ - 1) * h.HPL_BATCH_VARIANTS + v)
+    try:
+        info = h.hpl_batched_solve(sizes, A, ipiv, B, nrhs, W=W, GB=GB, GA=GA, mode=h.BATCH_BOTH)
+    finally:
+        h.hpl_set_option(h.HPL_OPT_BATCH_CONFIG, 0)
+    assert np.all(info == 0)
+    Ah, Bh, Wh = host_batch(sizes, nrhs, adjoint=True)
+    Wg = W.cpu().numpy()[:Wh.size]
+    ref = oracle.batched_solve(sizes, Ah, Bh, nrhs, W=Wg)
+    check_against_oracle(sizes, nrhs, (A.cpu().numpy(), ipiv.cpu().numpy(), B.cpu().numpy(), GB.cpu().numpy(),
+                                       GA.cpu().numpy()), ref)
