@@ -9,11 +9,15 @@ elementwise backward-error bound |A - LU| <= c n u |L||U| with the format's
 unit roundoff u, and by agreement with the partial-pivoting oracle (which
 makes no interchange on these inputs) in the unrounded format.
 """
+import os
+
 import numpy as np
 import pytest
 
 import inputs
 import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_round_fp16_matches_numpy():
@@ -128,3 +132,35 @@ def test_lu_mxp_scaling_exchanges_exponents(n, nb):
     # unrounded (FP32 only) the same factors come back: the construction itself is exact in FP32
     LU32, _ = oracle.lu_mxp(A, nb, oracle.FMT_NONE)
     assert np.array_equal(LU32.astype(np.float64), LU)
+
+
+@pytest.mark.parametrize("mutation", ["-mxp_scale_exponent(lmax, umax)", "0", "2 * mxp_scale_exponent(lmax, umax)",
+                                      "mxp_scale_exponent(lmax, umax) / 2"])
+def test_scaling_pin_catches_planted_mistakes(mutation, tmp_path):
+    """The scaling pin above is not blind: copies of the oracle with the
+    exponent's sign flipped, the scaling dropped, doubled or halved (built from
+    the oracle's source with that one line changed, here on the CPU) no longer
+    reproduce the exact factors of the construction."""
+    import ctypes
+    import subprocess
+    src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    line = "const int s = mxp_scale_exponent(lmax, umax);"
+    assert src.count(line) == 1
+    mutated = tmp_path / "oracle_mut.c"
+    mutated.write_text(src.replace(line, f"const int s = {mutation};"))
+    lib = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
+                           "-o", str(lib), str(mutated), "-lm"])
+    L_ = ctypes.CDLL(str(lib))
+    L_.oracle_lu_mxp.restype = ctypes.c_int64
+    L_.oracle_lu_mxp.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                 ctypes.c_void_p, ctypes.c_int64]
+    n, nb = 96, 32
+    A, L, U = inputs.mxp_scaled_lu(n, nb, seed=n + nb)
+    A = np.asfortranarray(A)
+    LU = np.zeros((n, n), dtype=np.float32, order="F")
+    L_.oracle_lu_mxp(A.ctypes.data_as(ctypes.c_void_p), n, n, nb, oracle.FMT_FP16,
+                     LU.ctypes.data_as(ctypes.c_void_p), n)
+    LU = LU.astype(np.float64)
+    exact = np.array_equal(np.tril(LU, -1) + np.eye(n), L) and np.array_equal(np.triu(LU), U)
+    assert not exact, mutation
