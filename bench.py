@@ -230,8 +230,6 @@ def bench_mxp(args, torch, h):
     refinement) against the FP64 path (partial-pivoting LU + solve) on the same
     matrix; speed-up = t_fp64 / t_mxp."""
     n = 65536 if args.n == 163840 else args.n
-    if args.mxp_gemm is not None:
-        h.hpl_set_option(h.HPL_OPT_MXP_GEMM, args.mxp_gemm)
     nb = args.nb            # FP64 path (its best panel width)
     mnb = args.mxp_nb       # mixed-precision path (its best: the FP32 trailing matrix wants a wider panel)
     A = h.colmajor(n, n)
@@ -313,8 +311,7 @@ def bench_mxp(args, torch, h):
             "fp16_phase_ms": {"trailing_update": round(g["ms"], 2), "panel_u12_convert": round(f["ms"], 2)},
         },
         "roofline": {
-            "kernel": ("hgemm_dma_kernel" if h.hpl_get_option(h.HPL_OPT_MXP_GEMM) == 1 else "hgemm_update_kernel")
-                      + " (A22 += (-L21) U12, FP16 MFMA, FP32 C)",
+            "kernel": "hgemm_update_kernel (A22 += (-L21) U12, FP16 MFMA, FP32 C)",
             "bound": "hbm",
             "achieved": round(g["bytes"] / (g["ms"] * 1e-3) / 1e9, 1) if g["ms"] else None,
             "peak": PEAK_HBM_GBS,
@@ -719,8 +716,6 @@ def main():
     ap.add_argument("--n", type=int, default=163840)
     ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--mxp-nb", type=int, default=1024, help="panel width of the mixed-precision LU (--workload mxp)")
-    ap.add_argument("--mxp-gemm", type=int, default=None, choices=[0, 1],
-                    help="mixed-precision trailing-update kernel (HPL_OPT_MXP_GEMM; default: the library's)")
     ap.add_argument("--lookahead", type=int, default=1)
     ap.add_argument("--seed", type=int, default=2304)
     ap.add_argument("--pad", type=int, default=0, help="lda = n + pad")

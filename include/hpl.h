@@ -272,16 +272,13 @@ enum hpl_option {
                                 most g workgroups (each loops over 8-column groups), leaving
                                 the other CUs to the panel on the other stream (default 96);
                                 0: one workgroup per 8 columns.  Results do not depend on it. */
-    HPL_OPT_BATCH_CONFIG = 10, /* hpl_batched_solve's schedule.  0 (default): chosen from the
+    HPL_OPT_BATCH_CONFIG = 10 /* hpl_batched_solve's schedule.  0 (default): chosen from the
                                 tuned table (hpl_batched_config).  k = 1 + (occ - 1) *
                                 HPL_BATCH_VARIANTS + v forces occ in {1, 2} systems in
                                 flight per CU and variant v for every size (what the tuner
                                 measures).  The panel width and the solves' row
                                 block change the rounding order, so schedules agree
                                 to rounding, not bit for bit. */
-    HPL_OPT_MXP_GEMM = 11    /* hpl_mxp_factor's FP16/BF16 trailing update: 0 operands staged
-                                through registers, 1 through a ring of LDS DMA stages.
-                                Bit-identical results. */
 };
 /* Returns 0, or -1 (bad key) / -2 (bad value); the option is unchanged on error. */
 int hpl_set_option(int key, int64_t value);

@@ -250,10 +250,8 @@ int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int
                      unsigned *mx, int *sexp, hipStream_t st);
 int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols,
                        int w, const int *sexp, void *A16, void *B16, hipStream_t st);
-// kernel: 0 = operands staged through registers, 1 = through a ring of LDS DMA
-// stages (bit-identical results).
 int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, const void *B16, float *C,
-                        int64_t ldc, int kernel, hipStream_t st);
+                        int64_t ldc, hipStream_t st);
 // r = b - A x with kResSplit column chunks; part holds 2 kResSplit n doubles of partial sums.
 constexpr int kResSplit = 16;
 int launch_mxp_residual(const double *A, int64_t lda, const double *x, const double *b, double *r, int64_t n,

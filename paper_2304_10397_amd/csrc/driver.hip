@@ -69,8 +69,7 @@ static std::atomic<int64_t> opt_serialize{0};
 static std::atomic<int64_t> opt_gemm_tile{0};
 static std::atomic<int64_t> opt_laswp_wgs{96};
 static std::atomic<int64_t> opt_host_panel{0};
-static std::atomic<int64_t> opt_batch_config{0};  // 0: tuned table; else a forced schedule
-static std::atomic<int64_t> opt_mxp_gemm{0};      // FP16/BF16 trailing update: 0 register-staged, 1 LDS DMA ring  // threads of the host panel (0: panel on the GPU)
+static std::atomic<int64_t> opt_batch_config{0};  // 0: tuned table; else a forced schedule  // threads of the host panel (0: panel on the GPU)
 
 // ---------------------------------------------------------------------------
 // statistics (HPL_OPT_TIMING)
@@ -705,7 +704,7 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         const int id = tm.begin(ST_MXP_GEMM, st);
         HPLX_PROPAGATE(launch_hgemm_update(fmt, ni, nc, w, (const uint16_t *)A16[q] + (size_t)i0 * (size_t)w,
                                            (const uint16_t *)B16[q] + (size_t)j0 * (size_t)w,
-                                           LU + off(c1 + i0, c1 + j0, ldlu), ldlu, (int)opt_mxp_gemm.load(), st));
+                                           LU + off(c1 + i0, c1 + j0, ldlu), ldlu, st));
         return tm.end(id, st, 2.0 * (double)ni * (double)nc * (double)w,
                       8.0 * (double)ni * (double)nc + 2.0 * (double)w * (double)(ni + nc));
     };
@@ -1082,10 +1081,6 @@ int hpl_set_option(int key, int64_t value)
         if (value < 0 || value > 2 * HPL_BATCH_VARIANTS) return -2;
         opt_batch_config = value;
         return 0;
-    case HPL_OPT_MXP_GEMM:
-        if (value != 0 && value != 1) return -2;
-        opt_mxp_gemm = value;
-        return 0;
     default: return -1;
     }
 }
@@ -1103,7 +1098,6 @@ int64_t hpl_get_option(int key)
     case HPL_OPT_HOST_PANEL: return opt_host_panel;
     case HPL_OPT_LASWP_WGS: return opt_laswp_wgs;
     case HPL_OPT_BATCH_CONFIG: return opt_batch_config;
-    case HPL_OPT_MXP_GEMM: return opt_mxp_gemm;
     default: return INT64_MIN;
     }
 }

@@ -470,142 +470,6 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// The same update with the operands moved global -> LDS by DMA through a ring
-// of kDS stages of 32 k (global_load_lds_dwordx4: 64 lanes x 16 bytes straight
-// into 1 KB of LDS, no staging registers), so that three stages are in flight
-// while one is computed and every fragment of a stage fits in registers.
-//  * Tile 128 x 128, 4 waves of 64 x 64 (4 x 4 blocks of 16 x 16), the MFMA
-//    and its operand order as in hgemm_update_kernel: each accumulator sees
-//    the same products in the same k order, so the results are bit-identical.
-//  * LDS rows (tile rows of A, tile columns of B) are 64 bytes = four 16-byte
-//    chunks of 8 k; chunk c of row r sits in slot c ^ ((r >> 2) & 3), so the
-//    16 rows x 16 bytes of one fragment read cover 256 distinct bytes.
-//  * Every wave moves 2 KB of A and 2 KB of B per stage (4 instructions); a
-//    wave waits for its own copies of stage s (vmcnt), then a barrier makes
-//    every wave's copies visible, then stage s + 3 is issued into the slot
-//    that stage s - 1 used (read by every wave before that barrier).
-//  * Past the last row or column the copies read the last one (their results
-//    are never stored).  Requires K % 32 == 0.
-// ---------------------------------------------------------------------------
-constexpr int kDBK = 32;   // k per stage
-constexpr int kDS = 4;     // ring slots (stages in flight + the one computed)
-constexpr int kDStage = kHBM * kDBK * 2;  // bytes of one operand's stage (8 KB)
-
-#define HPLX_LDS_PTR(p) ((__attribute__((address_space(3))) void *)(p))
-
-template <int FMT>
-__global__ __launch_bounds__(256, 2) void hgemm_dma_kernel(int64_t m, int64_t n, int64_t K,
-                                                           const typename Half<FMT>::T *__restrict__ A16,
-                                                           const typename Half<FMT>::T *__restrict__ B16,
-                                                           float *__restrict__ C, int64_t ldc, int64_t tiles_m)
-{
-    typedef typename Half<FMT>::T H;
-    typedef H h8 __attribute__((ext_vector_type(8)));
-    typedef float f4 __attribute__((ext_vector_type(4)));
-    asm volatile("" ::: "a0");
-    __shared__ __attribute__((aligned(1024))) char smem[2][kDS][kDStage];  // [A|B][slot][128 rows x 64 B]
-    const int64_t tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-    const int64_t m0 = tm * kHBM, n0 = tn * kHBN;
-    const int t = threadIdx.x, lane = t & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(t >> 6) & 3;
-    const int wm = wave & 1, wn = wave >> 1;
-    const int li = lane & 15, lg = lane >> 4;
-
-    // accumulators from C, as in hgemm_update_kernel
-    f4 acc[4][4];
-    const int64_t rbase = m0 + 64 * wm + li, cbase = n0 + 64 * wn + 4 * lg;
-#pragma unroll
-    for (int R = 0; R < 4; ++R)
-#pragma unroll
-        for (int G = 0; G < 4; ++G)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
-                acc[R][G][r] = (i < m && j < n) ? C[off(i, j, ldc)] : 0.0f;
-            }
-
-    // DMA sources: instruction q (0, 1) of this wave covers tile rows
-    // 16 (2 wave + q) .. +16; lane i moves chunk (i & 3) ^ ((row >> 2) & 3)
-    // of row 16 (2 wave + q) + i / 4 (clamped to the last row / column)
-    uint32_t a_off[2], b_off[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int row = 16 * (2 * wave + q) + (lane >> 2);
-        const int c = (lane & 3) ^ ((row >> 2) & 3);
-        const int64_t ra = (m0 + row < m) ? row : (m - 1 - m0);
-        const int64_t rb = (n0 + row < n) ? row : (n - 1 - n0);
-        a_off[q] = (uint32_t)(ra * K * 2 + 16 * c);
-        b_off[q] = (uint32_t)(rb * K * 2 + 16 * c);
-    }
-    const char *a_tile = (const char *)(A16 + (size_t)m0 * (size_t)K);
-    const char *b_tile = (const char *)(B16 + (size_t)n0 * (size_t)K);
-    const uint32_t lds0 = (uint32_t)(uintptr_t)HPLX_LDS_PTR(&smem[0][0][0]);
-    auto dma = [&](int s) __attribute__((always_inline)) {
-        const int slot = s % kDS;
-        const char *sa = a_tile + (size_t)s * kDBK * 2;
-        const char *sb = b_tile + (size_t)s * kDBK * 2;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const uint32_t da = lds0 + (uint32_t)(slot * kDStage + (2 * wave + q) * 1024);
-            const uint32_t db = lds0 + (uint32_t)(kDS * kDStage + slot * kDStage + (2 * wave + q) * 1024);
-            asm volatile("global_load_lds_dwordx4 %0, %1" ::"v"(a_off[q]), "s"(sa), "{m0}"(da) : "memory");
-            asm volatile("global_load_lds_dwordx4 %0, %1" ::"v"(b_off[q]), "s"(sb), "{m0}"(db) : "memory");
-        }
-    };
-    const int nst = (int)(K / kDBK);
-#pragma unroll
-    for (int s = 0; s < kDS - 1; ++s)
-        if (s < nst) dma(s);
-
-    // fragment addresses: row 64 w + 16 X + li, chunk lg in its slot
-    const int swz = (lg ^ ((li >> 2) & 3)) * 16;
-    const char *fa = &smem[0][0][0] + (64 * wm + li) * 64 + swz;
-    const char *fb = &smem[1][0][0] + (64 * wn + li) * 64 + swz;
-
-    for (int s = 0; s < nst; ++s) {
-        // this wave's copies of stage s have landed (later stages may still fly)
-        const int later = (nst - 1 - s) < (kDS - 2) ? (nst - 1 - s) : (kDS - 2);
-        if (later >= 2)
-            asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
-        else if (later == 1)
-            asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
-        else
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_sched_barrier(0);
-        if (s + kDS - 1 < nst) dma(s + kDS - 1);
-        const int slot = s % kDS;
-        h8 af[4], bf[4];
-#pragma unroll
-        for (int X = 0; X < 4; ++X) {
-            bf[X] = *(const h8 *)(fb + slot * kDStage + X * 16 * 64);
-            af[X] = *(const h8 *)(fa + slot * kDStage + X * 16 * 64);
-        }
-        __builtin_amdgcn_sched_barrier(0);  // all eight reads in flight before the first MFMA waits
-#pragma unroll
-        for (int R = 0; R < 4; ++R)
-#pragma unroll
-            for (int G = 0; G < 4; ++G) {
-                if constexpr (FMT == 0)
-                    acc[R][G] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bf[G], af[R], acc[R][G], 0, 0, 0);
-                else
-                    acc[R][G] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[G], af[R], acc[R][G], 0, 0, 0);
-            }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int R = 0; R < 4; ++R)
-#pragma unroll
-        for (int G = 0; G < 4; ++G)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
-                if (i < m && j < n) C[off(i, j, ldc)] = acc[R][G][r];
-            }
-}
-
-// ---------------------------------------------------------------------------
 // refinement: r = b - A x (FP64, explicit A) in two passes, deterministic:
 //   1. workgroup (row block, column chunk q) writes the partial sums
 //      P[q][i] = sum_{j in chunk q} a_ij x_j (FMA chain, j in order) and, on
@@ -788,24 +652,13 @@ int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const fl
 }
 
 int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, const void *B16, float *C,
-                        int64_t ldc, int kernel, hipStream_t st)
+                        int64_t ldc, hipStream_t st)
 {
     if (m <= 0 || n <= 0 || K <= 0) return HPL_OK;
     if (K % kHBK) return HPL_ERR_INTERNAL;
     const int64_t tiles_m = blocks_of(m, kHBM), tiles_n = blocks_of(n, kHBN);
     const int64_t g = tiles_m * tiles_n;
     if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
-    // the DMA offsets are 32-bit: rows x K x 2 bytes of one tile's operands
-    if (kernel == 1 && (int64_t)kHBM * K * 2 < 0x7fffffffll) {
-        if (fmt == 0)
-            hipLaunchKernelGGL(hgemm_dma_kernel<0>, dim3((unsigned)g), dim3(256), 0, st, m, n, K,
-                               (const _Float16 *)A16, (const _Float16 *)B16, C, ldc, tiles_m);
-        else
-            hipLaunchKernelGGL(hgemm_dma_kernel<1>, dim3((unsigned)g), dim3(256), 0, st, m, n, K,
-                               (const __bf16 *)A16, (const __bf16 *)B16, C, ldc, tiles_m);
-        HPLX_TRY_LAUNCH();
-        return HPL_OK;
-    }
     if (fmt == 0)
         hipLaunchKernelGGL(hgemm_update_kernel<0>, dim3((unsigned)g), dim3(256), 0, st, m, n, K,
                            (const _Float16 *)A16, (const _Float16 *)B16, C, ldc, tiles_m);

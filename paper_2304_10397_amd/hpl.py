@@ -31,7 +31,6 @@ HPL_OPT_GEMM_TILE = 7
 HPL_OPT_HOST_PANEL = 8
 HPL_OPT_LASWP_WGS = 9
 HPL_OPT_BATCH_CONFIG = 10
-HPL_OPT_MXP_GEMM = 11
 HPL_BATCH_VARIANTS = 4
 HPL_BATCH_BUCKETS = 16
 

@@ -181,22 +181,3 @@ def test_mxp_factor_scaling_exact(n, nb, la):
     assert np.array_equal(np.tril(G, -1) + np.eye(n), L)
     assert np.array_equal(np.triu(G), U)
 
-
-@pytest.mark.parametrize("n,nb", [(64, 64), (130, 64), (1000, 128), (3000, 512), (4160, 1024), (5000, 2048)])
-@pytest.mark.parametrize("fmt", [0, 1])
-def test_mxp_update_kernels_bitwise(n, nb, fmt):
-    """The trailing update with its operands moved through the LDS DMA ring
-    gives the bits of the register-staged kernel (same products, same k order
-    per accumulator), on ragged tiles and panel widths up to 2048."""
-    h = hpl()
-    A, _ = gpu_mxp_system(n, 13)
-    old = h.hpl_get_option(h.HPL_OPT_MXP_GEMM)
-    try:
-        h.hpl_set_option(h.HPL_OPT_MXP_GEMM, 0)
-        LU0, info0 = h.hpl_mxp_factor(A, nb=nb, fmt=fmt)
-        h.hpl_set_option(h.HPL_OPT_MXP_GEMM, 1)
-        LU1, info1 = h.hpl_mxp_factor(A, nb=nb, fmt=fmt)
-    finally:
-        h.hpl_set_option(h.HPL_OPT_MXP_GEMM, old)
-    assert info0 == info1 == 0
-    assert np.array_equal(LU0.cpu().numpy().view(np.int32), LU1.cpu().numpy().view(np.int32))
