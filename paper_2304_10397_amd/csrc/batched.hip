@@ -150,14 +150,17 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
     const int w = (n - k0) < kPB ? (n - k0) : kPB;
     const int r = k0 + t;
     const bool own = r < n;
+    // the panel rows, all loads issued at once: a row past the system (not
+    // own) or a column past the panel (q >= w) reads a clamped element that
+    // is never used -- masking it would put each load behind a branch that
+    // waits for it
     double v[kPB];
     {
         const int rr = own ? r : n - 1;
 #pragma unroll
         for (int q = 0; q < kPB; ++q) {
             const int cq = (k0 + q) < n ? (k0 + q) : (n - 1);
-            const double x = a[(size_t)rr + (size_t)cq * (size_t)n];
-            v[q] = (own && q < w) ? x : 0.0;
+            v[q] = a[(size_t)rr + (size_t)cq * (size_t)n];
         }
     }
     __syncthreads();
