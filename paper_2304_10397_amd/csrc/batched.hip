@@ -137,6 +137,27 @@ __device__ __forceinline__ gf64 *col_ptr(gf64 *a, gf64 *b, int n, int c)
 }
 
 
+// Maximum of x over the 64 lanes of the wave, returned to every lane: rotations
+// within each row of 16 lanes through DPP (no LDS traffic), then the four row
+// maxima read out and combined.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double wave_max(double x)
+{
+    x = fmax(x, dpp_mov<0x128>(x));  // row_ror:8
+    x = fmax(x, dpp_mov<0x124>(x));  // row_ror:4
+    x = fmax(x, dpp_mov<0x122>(x));  // row_ror:2
+    x = fmax(x, dpp_mov<0x121>(x));  // row_ror:1
+    return fmax(fmax(read_lane(x, 0), read_lane(x, 16)), fmax(read_lane(x, 32), read_lane(x, 48)));
+}
+
 // FACT of the panel [k0, k0+w) (rows k0..n-1 in registers), its interchanges
 // recorded in ip, the permutation and the slot lists; L11 left in sh.T.
 // The column loop is not unrolled (the unrolled body overflows the
@@ -169,8 +190,7 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
         // wave argmax of |v[0]| over rows >= k0+j; ties: the lowest row (lane)
         const bool cand = own && t >= j;
         const double cv = cand ? fabs(v[0]) : -1.0;
-        double vm = cv;
-        for (int o = 32; o > 0; o >>= 1) vm = fmax(vm, __shfl_xor(vm, o, 64));
+        const double vm = wave_max(cv);
         const unsigned long long hit = __ballot(cand && cv == vm);
         const int wl = hit ? (int)__builtin_ctzll(hit) : -1;
         if (lane == 0) {
@@ -188,40 +208,60 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
         __syncthreads();
         double gv = -1.0;
         int gp = 0x7fffffff, gw = 0;
+        {
+            double qv[kBW];
+            int qr[kBW];
 #pragma unroll
-        for (int q = 0; q < kBW; ++q) {
-            const double qv = sh.pv[par][q];
-            const int qr = sh.pr[par][q];
-            if (qr >= 0 && (qv > gv || (qv == gv && qr < gp))) {
-                gv = qv;
-                gp = qr;
-                gw = q;
+            for (int q = 0; q < kBW; ++q) {
+                qv[q] = sh.pv[par][q];
+                qr[q] = sh.pr[par][q];
             }
+#pragma unroll
+            for (int q = 0; q < kBW; ++q)
+                if (qr[q] >= 0 && (qv[q] > gv || (qv[q] == gv && qr[q] < gp))) {
+                    gv = qv[q];
+                    gp = qr[q];
+                    gw = q;
+                }
         }
         // no valid candidate (a NaN column): keep the diagonal row, so
         // every row index stays inside the system
         if (gp == 0x7fffffff) gp = k0 + j;
-        const double *u = (gp == k0 + j) ? sh.drow[par] : sh.prow[par][gw];
+        // the pivot row, in registers (broadcast reads, all issued at once)
+        double u[kPB];
+        {
+            const double *up = (gp == k0 + j) ? sh.drow[par] : sh.prow[par][gw];
+#pragma unroll
+            for (int q = 0; q < kPB; ++q) u[q] = up[q];
+        }
         if (gp != k0 + j) {
             if (r == k0 + j) {
 #pragma unroll
                 for (int q = 0; q < kPB; ++q) v[q] = u[q];
-            } else if (r == gp) {
+            } else if (((gp - k0) >> 6) == wave) {  // the pivot row's wave (uniform branch)
+                double d[kPB];
 #pragma unroll
-                for (int q = 0; q < kPB; ++q) v[q] = sh.drow[par][q];
+                for (int q = 0; q < kPB; ++q) d[q] = sh.drow[par][q];
+                if (r == gp) {
+#pragma unroll
+                    for (int q = 0; q < kPB; ++q) v[q] = d[q];
+                }
             }
         }
         if (t == 0) sh.pivs[j] = gp;  // composed after the loop (off the per-column path)
         const double piv = u[0];
         if (piv == 0.0) {
             if (t == 0 && sh.info == 0) sh.info = k0 + j + 1;  // column left unscaled
-        } else if (own && r > k0 + j) {
-            const double l = v[0] / piv;
-            v[0] = l;
-            // the panel's remaining columns sit at 1 .. w-1-j
+        } else {
+            const bool below = own && r > k0 + j;
+            const double l = below ? v[0] / piv : 0.0;
+            if (below) v[0] = l;
+            // the panel's remaining columns sit at 1 .. w-1-j (selects, no branches)
 #pragma unroll
-            for (int q = 1; q < kPB; ++q)
-                if (q < w - j) v[q] = __fma_rn(-l, u[q], v[q]);
+            for (int q = 1; q < kPB; ++q) {
+                const double x = __fma_rn(-l, u[q], v[q]);
+                v[q] = (below && q < w - j) ? x : v[q];
+            }
         }
         // rotate: the next column moves to v[0], this one to the end
         const double c0 = v[0];
