@@ -21,14 +21,16 @@
 //      row is published too, and every thread then knows the pivot row and
 //      performs the interchange and the rank-1 update of its own row.  The
 //      column loop is rolled (the register row rotates by one column per step).
-//   2. The 32 interchanges are composed (by thread 0, during FACT) into one
+//   2. The 32 interchanges are composed (by one wave, after the column loop) into one
 //      permutation of the <= 64 rows they touch; every other column (left:
 //      LAPACK-form L; right: U12 and the trailing columns; the right-hand
 //      sides, carried as extra columns so that B becomes L^{-1} P B as in
 //      HPL's augmented system) goes through LDS in chunks of 64 columns:
 //      gathered with lane = slot (the panel rows of a column are consecutive,
-//      so the reads coalesce), the right columns' top 32 rows solved with the
-//      unit-lower L11, and scattered to the destination rows.
+//      so the reads coalesce), the right columns' top 32 rows multiplied by
+//      L11^{-1} (the triangular inverse, formed once per panel by
+//      substitution) on the matrix cores, and scattered to the destination
+//      rows.
 //   3. Trailing update C -= L21 U12 over rows [k0+32, n) and columns
 //      [k0+32, n+nrhs) on the FP64 matrix cores (16 x 16 blocks, masked at
 //      the ragged edges), -L21 fragments in registers, U12 through LDS.
@@ -89,6 +91,7 @@ struct BatchShared {
         double Us16x64[16][64 + 8];
     };
     double T[kPBmax][kPBmax + 1];          // diagonal block (L11, or a block of U / L for the solves)
+    double Ti[kPBmax][kPBmax + 1];         // L11^{-1}, identity past the panel width
     double prow[2][kBW][kPBmax];           // per-wave candidate rows
     double drow[2][kPBmax];                // the diagonal row
     double pv[2][kBW];                     // per-wave candidate |a|
@@ -239,12 +242,9 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
 #pragma unroll
                 for (int q = 0; q < kPB; ++q) v[q] = u[q];
             } else if (((gp - k0) >> 6) == wave) {  // the pivot row's wave (uniform branch)
-                double d[kPB];
-#pragma unroll
-                for (int q = 0; q < kPB; ++q) d[q] = sh.drow[par][q];
                 if (r == gp) {
 #pragma unroll
-                    for (int q = 0; q < kPB; ++q) v[q] = d[q];
+                    for (int q = 0; q < kPB; ++q) v[q] = sh.drow[par][q];
                 }
             }
         }
@@ -343,11 +343,27 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
 {
     constexpr int kPB = PB, kMaxSlots = 2 * PB;
     static_assert(kBT % kMaxSlots == 0 && kGc % (kBT / kMaxSlots) == 0, "interchange pass shape");
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // ---- 1. L11^{-1} (the triangular inverse; unit lower, identity past the
+    //      panel width) into sh.Ti: lane j of wave 0 solves L11 y = e_j row by
+    //      row, y_i = -sum_{k<i} l_ik y_k, with y_k = 0 above the diagonal
+    if (wave == 0 && lane < kPB) {
+        double y[kPB];
+#pragma unroll
+        for (int i = 0; i < kPB; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) acc = __fma_rn(-sh.T[i][k], y[k], acc);
+            y[i] = (i == lane) ? 1.0 : ((i > lane && i < w) ? acc : 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < kPB; ++i) sh.Ti[i][lane] = y[i];
+    }
     // ---- 2. interchanges on every other column; U12 = L11^{-1} A12 on the right.
     //      Chunks of kGc columns through LDS: gather (lane = slot, so the
-    //      panel rows of a column are read coalesced), the unit-lower solve
-    //      of the right columns' top rows (one thread per column), scatter.
+    //      panel rows of a column are read coalesced), the right columns' top
+    //      rows multiplied by L11^{-1} on the matrix cores (one 16 x 16 block
+    //      per wave), scatter.
     {
         const int nslots = sh.nslots;
         const int nother = ncol - w;
@@ -370,24 +386,27 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
                 gstage<PB>(cl, slot) = gq[q];
             }
             __syncthreads();
-            if (t < ce) {
-                const int c = (e0 + t) < k0 ? (e0 + t) : (e0 + t + w);
-                if (c >= k0 + w) {
-                    double x[kPB];
+            if (e0 + ce > k0) {  // the chunk has right columns (uniform)
+                // block (rb, cb) of Y = L11^{-1} G_top: rows 16 rb.., columns 16 cb..;
+                // lane l supplies Ti(16 rb + l%16, 4 s + l/16) and G(4 s + l/16, 16 cb + l%16)
+                typedef double d4 __attribute__((ext_vector_type(4)));
+                constexpr int kRB = kPB / 16, kCB = kGc / 16;
+                const int rb = wave % kRB, cb = wave / kRB;
+                const int li = lane & 15, lg = lane >> 4;
+                d4 y = {0.0, 0.0, 0.0, 0.0};
+                if (cb < kCB) {
 #pragma unroll
-                    for (int i = 0; i < kPB; ++i) x[i] = gstage<PB>(t, i);
+                    for (int s4 = 0; s4 < kPB / 4; ++s4)
+                        y = __builtin_amdgcn_mfma_f64_16x16x4f64(sh.Ti[16 * rb + li][4 * s4 + lg],
+                                                                 gstage<PB>(16 * cb + li, 4 * s4 + lg), y, 0, 0, 0);
+                }
+                __syncthreads();  // every fragment of G read before any is replaced
+                if (cb < kCB) {
+                    const int cl = 16 * cb + li;
+                    if (cl < ce && e0 + cl >= k0) {
 #pragma unroll
-                    for (int i = 1; i < kPB; ++i) {
-                        if (i < w) {
-                            double acc = x[i];
-#pragma unroll
-                            for (int k = 0; k < i; ++k) acc = __fma_rn(-sh.T[i][k], x[k], acc);
-                            x[i] = acc;
-                        }
-                        __builtin_amdgcn_sched_barrier(0);  // keep each row's LDS reads next to their use
+                        for (int r = 0; r < 4; ++r) gstage<PB>(cl, 16 * rb + lg + 4 * r) = y[r];
                     }
-#pragma unroll
-                    for (int i = 0; i < kPB; ++i) gstage<PB>(t, i) = x[i];
                 }
             }
             __syncthreads();

@@ -6,11 +6,19 @@
 // traffic, far above the MI355X ridge (78.6 TFLOP/s / 8 TB/s ~ 9.8), so the
 // kernel is bound by the FP64 matrix cores.
 //
-// gfx950 design
-//  * FP64 MFMA: v_mfma_f64_4x4x4_4b_f64.  On gfx950 the four-block 4x4x4 form
-//    sustains ~72 TFLOP/s in a pure issue loop, against ~47 for the
-//    16x16x4 form (both measured on the hardware), so the kernel is built on
-//    it.  The instruction holds 4 independent blocks b: lane 16k+4b+i supplies
+// Two kernels (both FP64 MFMA, accumulators in AGPRs, XCD-aware tile order):
+//  * gemm_stream_kernel -- the hot one, used wherever its preconditions hold
+//    (the whole trailing update at the benchmark's sizes): v_mfma_f64_16x16x4,
+//    operands moved global -> LDS by DMA; described where it is defined.
+//  * gemm_sub_kernel -- the fallback for any shape and alignment:
+//    v_mfma_f64_4x4x4_4b, register-staged double-buffered LDS.
+// With accumulators in AGPRs both MFMA forms sustain ~72 TFLOP/s in a pure
+// issue loop on gfx950 (with accumulators in ordinary VGPRs the 16x16x4 form
+// drops to ~48, because its C operand then shares the register read ports
+// with A and B).
+//
+// gemm_sub_kernel in detail
+//  * The instruction holds 4 independent blocks b: lane 16k+4b+i supplies
 //    A_b(i,k), lane 16k+4b+j supplies B_b(k,j), and lane 16i+4b+j holds
 //    D_b(i,j) (layout checked on the hardware).  All four blocks get the same
 //    4-row slice of A (the A value depends only on lane%4 and lane/16) and
@@ -20,12 +28,11 @@
 //  * Block tile BM x BN, K staged BK = 16 at a time through double-buffered
 //    LDS (one barrier per stage); each wave owns a (BM/WM) x (BN/WN) sub-tile
 //    of accumulators that stay in registers for the whole K loop.
-//  * Accumulators live in AGPRs (so the A/B operands do not compete with them
-//    for VGPR read ports) and start from zero; the epilogue applies
-//    C <- C - acc a column group at a time.  Every element is therefore
-//    C - sum_k a_ik b_kj with the same k order and the same instruction
-//    whatever the tiling -- the look-ahead split of the update reproduces the
-//    unsplit update bit for bit.
+//  * Accumulators start from zero; the epilogue applies C <- C - acc a
+//    column group at a time.  Every element is therefore C - sum_k a_ik b_kj
+//    with the same k order and the same instruction whatever the tiling --
+//    the look-ahead split of the update reproduces the unsplit update bit for
+//    bit.
 //  * Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 //    L2).  The block index is remapped so that each XCD receives a contiguous
 //    run of tiles, and tiles are ordered in groups of kGroupM tile-rows so the
