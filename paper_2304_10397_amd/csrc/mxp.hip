@@ -397,18 +397,33 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 15, lg = lane >> 4;
 
-    // accumulators from C: acc[R][G][r] = C(m0 + 64wm + 16R + li, n0 + 64wn + 16G + 4lg + r)
+    // accumulators from C: acc[R][G][r] = C(m0 + 64wm + 16R + li, n0 + 64wn + 16G + 4lg + r).
+    // A tile inside the matrix (all but the last row and column of tiles)
+    // reads each column's four rows 16 R apart from one address with
+    // immediate offsets and no tests; an edge tile tests every element.
     f4 acc[4][4];
     const int64_t rbase = m0 + 64 * wm + li, cbase = n0 + 64 * wn + 4 * lg;
-#pragma unroll
-    for (int R = 0; R < 4; ++R)
+    const bool inner = m0 + kHBM <= m && n0 + kHBN <= n;  // uniform
+    if (inner) {
 #pragma unroll
         for (int G = 0; G < 4; ++G)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
-                acc[R][G][r] = (i < m && j < n) ? C[off(i, j, ldc)] : 0.0f;
+                const float *col = C + off(rbase, cbase + 16 * G + r, ldc);
+#pragma unroll
+                for (int R = 0; R < 4; ++R) acc[R][G][r] = col[16 * R];
             }
+    } else {
+#pragma unroll
+        for (int R = 0; R < 4; ++R)
+#pragma unroll
+            for (int G = 0; G < 4; ++G)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
+                    acc[R][G][r] = (i < m && j < n) ? C[off(i, j, ldc)] : 0.0f;
+                }
+    }
 
     // global -> register staging: A tile 128 x 64 halves = 1024 x 16 B, 4 per thread
     u4 ra[4], rb[4];
@@ -458,15 +473,26 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
         if (s + 1 < nst) store(buf ^ 1);
         __syncthreads();
     }
-#pragma unroll
-    for (int R = 0; R < 4; ++R)
+    if (inner) {
 #pragma unroll
         for (int G = 0; G < 4; ++G)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
-                if (i < m && j < n) C[off(i, j, ldc)] = acc[R][G][r];
+                float *col = C + off(rbase, cbase + 16 * G + r, ldc);
+#pragma unroll
+                for (int R = 0; R < 4; ++R) col[16 * R] = acc[R][G][r];
             }
+    } else {
+#pragma unroll
+        for (int R = 0; R < 4; ++R)
+#pragma unroll
+            for (int G = 0; G < 4; ++G)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
+                    if (i < m && j < n) C[off(i, j, ldc)] = acc[R][G][r];
+                }
+    }
 }
 
 // ---------------------------------------------------------------------------
