@@ -92,3 +92,22 @@ def test_cpu_baseline_fields_on_tiny_sizes():
     assert set(base["projection"]["serial_seconds"]) == {"8192", "65536", "163840"}
     assert "PROJECTION" in base["projection"]["note"]
     assert x.shape == (64,)
+
+
+def test_tuner_table_round_trip(tmp_path):
+    """The batched tuner's table writer: the file it writes holds every cost
+    of the (systems per CU, variant, bucket) array it was given, in the shape
+    the library compiles (host only, no GPU)."""
+    import re
+    import numpy as np
+    from paper_2304_10397_amd import tune_batched
+    cost = np.arange(2 * 4 * 16, dtype=np.float64).reshape(2, 4, 16) / 7.0 + 0.5
+    out = tmp_path / "table.inc"
+    tune_batched.write_table(str(out), cost, "gfx950 (256 CUs)", 4, [4096] * 16)
+    text = out.read_text()
+    assert "static const int kBatchTableTuned = 1;" in text
+    assert "kBatchCostUs[2][4][16]" in text
+    body = text[text.index("= {"):]
+    vals = np.array([float(v) for v in re.findall(r"-?\d+\.\d+", body)])
+    assert vals.size == cost.size
+    assert np.allclose(vals, cost.ravel(), atol=5e-5)
