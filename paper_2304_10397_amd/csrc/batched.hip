@@ -140,27 +140,6 @@ __device__ __forceinline__ gf64 *col_ptr(gf64 *a, gf64 *b, int n, int c)
 }
 
 
-// Maximum of x over the 64 lanes of the wave, returned to every lane: rotations
-// within each row of 16 lanes through DPP (no LDS traffic), then the four row
-// maxima read out and combined.
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double x)
-{
-    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-__device__ __forceinline__ double wave_max(double x)
-{
-    x = fmax(x, dpp_mov<0x128>(x));  // row_ror:8
-    x = fmax(x, dpp_mov<0x124>(x));  // row_ror:4
-    x = fmax(x, dpp_mov<0x122>(x));  // row_ror:2
-    x = fmax(x, dpp_mov<0x121>(x));  // row_ror:1
-    return fmax(fmax(read_lane(x, 0), read_lane(x, 16)), fmax(read_lane(x, 32), read_lane(x, 48)));
-}
-
 // FACT of the panel [k0, k0+w) (rows k0..n-1 in registers), its interchanges
 // recorded in ip, the permutation and the slot lists; L11 left in sh.T.
 // The column loop is not unrolled (the unrolled body overflows the

@@ -21,8 +21,6 @@ __host__ __device__ __forceinline__ size_t off(int64_t i, int64_t j, int64_t ld)
     return (size_t)i + (size_t)j * (size_t)ld;
 }
 
-// Value of v held by lane l of the wave (l uniform across the wave): two
-// v_readlane_b32, a few cycles, instead of an LDS round trip.
 // p[0] when ok, else z, with the load issued unconditionally (from p, or from
 // the always-valid address safe): a guarded load written as "ok ? p[0] : z"
 // is compiled to a branch around the load followed by a wait for it, so a
@@ -55,12 +53,46 @@ __device__ __forceinline__ void tile_of_block(int64_t bid, int64_t nwg, int64_t 
     tn = r / gm;
 }
 
+// Value of v held by lane l of the wave (l uniform across the wave): two
+// v_readlane_b32, a few cycles, instead of an LDS round trip.
 __device__ __forceinline__ double read_lane(double v, int l)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Wave-wide reductions returned to every lane: rotations within each row of 16
+// lanes through DPP (no LDS traffic), then the four row results read out and
+// combined.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double wave_max(double x)
+{
+    x = fmax(x, dpp_mov<0x128>(x));  // row_ror:8
+    x = fmax(x, dpp_mov<0x124>(x));  // row_ror:4
+    x = fmax(x, dpp_mov<0x122>(x));  // row_ror:2
+    x = fmax(x, dpp_mov<0x121>(x));  // row_ror:1
+    return fmax(fmax(read_lane(x, 0), read_lane(x, 16)), fmax(read_lane(x, 32), read_lane(x, 48)));
+}
+
+__device__ __forceinline__ unsigned wave_min_u32(unsigned x)
+{
+    x = min(x, (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xf, 0xf, false));
+    x = min(x, (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x124, 0xf, 0xf, false));
+    x = min(x, (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x122, 0xf, 0xf, false));
+    x = min(x, (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x121, 0xf, 0xf, false));
+    const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)x, 0), b = (unsigned)__builtin_amdgcn_readlane((int)x, 16);
+    const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)x, 32), d = (unsigned)__builtin_amdgcn_readlane((int)x, 48);
+    return min(min(a, b), min(c, d));
 }
 
 // ---------------------------------------------------------------------------
@@ -149,6 +181,12 @@ constexpr int kGemmTrailing = 0x100;
 int launch_gemm_sub(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda,
                     const double *B, int64_t ldb, double *C, int64_t ldc, int variant,
                     hipStream_t st);
+
+// skinny.hip: C(m x n) -= A(m x k) * B(k x n) for k = 16, 32 or 64 and n <= k
+// (the updates inside the recursive panel).
+bool gemm_skinny_ok(int64_t n, int64_t k);
+int launch_gemm_skinny(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B, int64_t ldb,
+                       double *C, int64_t ldc, hipStream_t st);
 
 // trsm.hip: B(nbk x ncols) <- L^{-1} B, L unit lower nbk x nbk (nbk <= 512).
 int launch_trsm_llnu(const double *L, int64_t ldl, double *B, int64_t ldb, int64_t nbk,

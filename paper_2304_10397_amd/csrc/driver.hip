@@ -364,9 +364,14 @@ static int panel_rec(Ctx &x, int64_t c, int64_t w, hipStream_t st)
     HPLX_PROPAGATE(launch_swap_plan(x.ipiv + c, (int)w1, c, x.n, false, d->pint, st));
     HPLX_PROPAGATE(launch_laswp(x.A, x.lda, c + w1, w2, d->pint, 0, st));
     HPLX_PROPAGATE(launch_trsm_llnu(x.A + off(c, c, x.lda), x.lda, x.A + off(c, c + w1, x.lda), x.lda, w1, w2, st));
-    HPLX_PROPAGATE(launch_gemm_sub(x.n - c - w1, w2, w1, x.A + off(c + w1, c, x.lda), x.lda,
-                                   x.A + off(c, c + w1, x.lda), x.lda, x.A + off(c + w1, c + w1, x.lda), x.lda, 0,
-                                   st));
+    if (gemm_skinny_ok(w2, w1))
+        HPLX_PROPAGATE(launch_gemm_skinny(x.n - c - w1, w2, w1, x.A + off(c + w1, c, x.lda), x.lda,
+                                          x.A + off(c, c + w1, x.lda), x.lda, x.A + off(c + w1, c + w1, x.lda), x.lda,
+                                          st));
+    else
+        HPLX_PROPAGATE(launch_gemm_sub(x.n - c - w1, w2, w1, x.A + off(c + w1, c, x.lda), x.lda,
+                                       x.A + off(c, c + w1, x.lda), x.lda, x.A + off(c + w1, c + w1, x.lda), x.lda,
+                                       0, st));
     HPLX_PROPAGATE(panel_rec(x, c + w1, w2, st));
     HPLX_PROPAGATE(launch_swap_plan(x.ipiv + c + w1, (int)w2, c + w1, x.n, false, d->pint, st));
     return launch_laswp(x.A, x.lda, c, w1, d->pint, 0, st);

@@ -234,20 +234,25 @@ __device__ __forceinline__ void put_tagged(unsigned long long *p, uint32_t tag, 
     __hip_atomic_store(p, ((unsigned long long)tag << 32) | payload, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Spins until *p carries tag (or the abort flag rises / the wall-clock limit passes).
+// Spins until *p carries tag (or the abort flag rises / the wall-clock limit
+// passes).  The abort flag and the clock are looked at only every 32nd poll:
+// each look is another trip to memory, and a poll loop that made it every time
+// would see the awaited word up to one such trip late.
 __device__ __forceinline__ bool get_tagged(const unsigned long long *p, uint32_t tag, uint32_t &payload,
                                            int *abort_flag, unsigned long long t0)
 {
-    for (;;) {
+    for (unsigned it = 1;; ++it) {
         const unsigned long long v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((uint32_t)(v >> 32) == tag) {
             payload = (uint32_t)v;
             return true;
         }
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-        if (wall_clock64() - t0 > kSpinLimit) {
-            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
+        if ((it & 31u) == 0) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+            if (wall_clock64() - t0 > kSpinLimit) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
         }
         __builtin_amdgcn_s_sleep(1);
     }
@@ -258,18 +263,29 @@ __device__ __forceinline__ double dbl_of(uint32_t lo, uint32_t hi)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__device__ __forceinline__ void block_argmax512(double &v, int64_t &i, double *rv, int64_t *ri)
+// Largest v over the workgroup, the lowest row i among its holders on ties
+// (every v >= -1, rows below 2^31 or INT64_MAX for none).  The wave's maximum
+// and the lowest row holding it go through DPP and lane reads; the eight wave
+// results meet in rv/ri behind one barrier.  rv/ri are read after that barrier
+// and written again only on the next call: a caller must pass a barrier of its
+// own between two calls with the same arrays.
+__device__ __forceinline__ void block_argmax512(double &v, int64_t &i, double *rv, unsigned *ri)
 {
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    wave_argmax(v, i);
-    if (lane == 0) { rv[wid] = v; ri[wid] = i; }
+    const double m = wave_max(v);
+    const unsigned r = wave_min_u32(v == m ? (unsigned)i : 0xffffffffu);
+    if (lane == 0) { rv[wid] = m; ri[wid] = r; }
     __syncthreads();
-    v = rv[0];
-    i = ri[0];
+    double bv = rv[0];
+    unsigned br = ri[0];
 #pragma unroll
-    for (int q = 1; q < kRegWaves; ++q)
-        if (better(rv[q], ri[q], v, i)) { v = rv[q]; i = ri[q]; }
-    __syncthreads();
+    for (int q = 1; q < kRegWaves; ++q) {
+        const double x = rv[q];
+        const unsigned y = ri[q];
+        if (x > bv || (x == bv && y < br)) { bv = x; br = y; }
+    }
+    v = bv;
+    i = (br == 0xffffffffu) ? INT64_MAX : (int64_t)br;
 }
 
 __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restrict__ A, int64_t lda, int64_t c,
@@ -280,8 +296,8 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
     __shared__ double topv[kRegW];   // diagonal row (workgroup 0)
     __shared__ double u[kRegW];      // pivot row, active columns
     __shared__ double tr[kRegW];     // old diagonal row, active columns
-    __shared__ double rv[kRegWaves];
-    __shared__ int64_t ri[kRegWaves];
+    __shared__ double rv[2][kRegWaves];
+    __shared__ unsigned ri[2][kRegWaves];
     __shared__ int s_abort;
     __shared__ uint32_t xw[3 * kLeafMaxWGs + 4 * kRegW];  // payloads of one exchange: keys, then two rows
 
@@ -310,23 +326,24 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
     }
     if (t == 0) s_abort = 0;
 
+    // Register slots at and beyond the active count hold values that are never
+    // used; the copies and the rank-1 update run over all kRegW slots without
+    // per-slot tests (a test per slot costs a branch per slot and step).
     for (int k = 0; k < w; ++k) {
         const int na = w - k;  // active columns
         const uint32_t tag = tag0 + (uint32_t)k + 1u;
         const int par = k & 1;
         // ---- 1. this workgroup's candidate and the rows to publish
-        block_argmax512(bv, bi, rv, ri);
+        block_argmax512(bv, bi, rv[0], ri[0]);
 #pragma unroll
         for (int q = 0; q < kRegRPT; ++q) {
             if (row[q] == bi && row[q] < rend) {
 #pragma unroll
-                for (int j = 0; j < kRegW; ++j)
-                    if (j < na) cand[j] = v[q][j];
+                for (int j = 0; j < kRegW; ++j) cand[j] = v[q][j];
             }
             if (g == 0 && row[q] == k) {
 #pragma unroll
-                for (int j = 0; j < kRegW; ++j)
-                    if (j < na) topv[j] = v[q][j];
+                for (int j = 0; j < kRegW; ++j) topv[j] = v[q][j];
             }
         }
         __syncthreads();
@@ -373,7 +390,7 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
                 gv = dbl_of(xw[3 * t + 1], xw[3 * t + 2]);
                 gi = (int64_t)xw[3 * t];
             }
-            block_argmax512(gv, gi, rv, ri);
+            block_argmax512(gv, gi, rv[1], ri[1]);
             pv = gv;
             p = gi;
             // (b) the winner's row and the diagonal row (2 words per value)
@@ -406,7 +423,10 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
         __syncthreads();
         // ---- 5. U row k, interchange of the active parts, scale, rank-1 update
         if (g == 0 && t < na) S[off(k, k + t, lda)] = u[t];
-        const double piv = u[0];
+        double uu[kRegW];
+#pragma unroll
+        for (int j = 0; j < kRegW; ++j) uu[j] = u[j];
+        const double piv = uu[0];
         bv = -1.0;
         bi = INT64_MAX;
 #pragma unroll
@@ -415,14 +435,17 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
             if (i >= rend || i <= k) continue;
             if (i == p) {
 #pragma unroll
-                for (int j = 0; j < kRegW; ++j)
-                    if (j < na) v[q][j] = tr[j];
+                for (int j = 0; j < kRegW; ++j) v[q][j] = tr[j];
             }
             const double l = singular ? v[q][0] : v[q][0] / piv;
             S[off(i, k, lda)] = l;
+            if (singular) {
 #pragma unroll
-            for (int j = 1; j < kRegW; ++j)
-                if (j < na) v[q][j - 1] = singular ? v[q][j] : __fma_rn(-l, u[j], v[q][j]);
+                for (int j = 1; j < kRegW; ++j) v[q][j - 1] = v[q][j];
+            } else {
+#pragma unroll
+                for (int j = 1; j < kRegW; ++j) v[q][j - 1] = __fma_rn(-l, uu[j], v[q][j]);
+            }
             if (na > 1) {
                 const double a = fabs(v[q][0]);
                 if (better(a, i, bv, bi)) { bv = a; bi = i; }
