@@ -3,6 +3,11 @@
 
 One step = generate the random system (untimed), then factor + solve (timed):
     HPL TFLOP/s = (2 N^3 / 3 + 2 N^2) / t(factor + solve)
+By default the step is HPL's own formulation (Sec. II): b is carried through
+the LU as column N of [A | b], each panel's row interchanges reach only the
+columns right of it, and x follows from U x = L^-1 P^-1 b by back
+substitution (hpl_solve_augmented).  --form lapack times hpl_factor (LAPACK
+form: the interchanges applied across all columns) + hpl_solve instead.
 The default workload is N = 163840, NB = 512, look-ahead depth 1 (A fills
 about 215 GB of HBM), seeded synthetic input.  Prints ONE JSON line on stdout;
 progress goes to stderr.
@@ -580,13 +585,14 @@ def bench_hpl(args, torch, h, dev):
     # Warm-up (not timed): factor + solve at N = 4096 loads the code objects and
     # the workspace; a full-size warm-up would add nothing else.
     for _ in range(max(1, args.warmup)):
-        A_s = h.colmajor(4096, 4096)
+        A_s = h.colmajor(4096, 4097)
         h.hpl_generate(1, 0, A_s)
-        b_s = h.colmajor(4096, 1)
-        h.hpl_generate(1, 1, b_s)
-        piv_s, _ = h.hpl_factor(A_s, nb)
-        h.hpl_solve(A_s, piv_s, b_s)
-        del A_s, b_s, piv_s
+        if args.form == "augmented":
+            h.hpl_solve_augmented(A_s, 4096, nb)
+        else:
+            piv_s, _ = h.hpl_factor(A_s[:, :4096], nb)
+            h.hpl_solve(A_s[:, :4096], piv_s, A_s[:, 4096:])
+        del A_s
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
@@ -610,11 +616,17 @@ def bench_hpl(args, torch, h, dev):
         cfg1["gpu_speedup_vs_oracle_serial"] = round(s1["seconds"] / cfg1["gpu_median_s"], 1)
         base["config_n1024_nb64"] = cfg1
 
-    A = h.colmajor(n, n, ld=n + args.pad)
+    augmented = args.form == "augmented"
+    if augmented:
+        # [A | b] in one allocation: b is column n, carried through the factorization
+        AB = h.colmajor(n, n + 1, ld=n + args.pad)
+        A, x = AB[:, :n], AB[:, n:]
+    else:
+        A = h.colmajor(n, n, ld=n + args.pad)
+        x = h.colmajor(n, 1)
     b = h.colmajor(n, 1)
-    x = h.colmajor(n, 1)
     ipiv = torch.empty(n, dtype=torch.int32, device=dev)
-    log(f"allocated A: {A.stride(1) * n * 8 / 1e9:.1f} GB")
+    log(f"allocated A: {A.stride(1) * n * 8 / 1e9:.1f} GB ({args.form} form)")
 
     times = []
     info = 0
@@ -631,8 +643,11 @@ def bench_hpl(args, torch, h, dev):
         h.hpl_reset_stats()
         h.hpl_set_option(h.HPL_OPT_TIMING, 1)
         t0 = time.perf_counter()
-        _, info = h.hpl_factor(A, nb, ipiv=ipiv)
-        h.hpl_solve(A, ipiv, x)
+        if augmented:
+            _, info = h.hpl_solve_augmented(AB, n, nb, ipiv=ipiv)
+        else:
+            _, info = h.hpl_factor(A, nb, ipiv=ipiv)
+            h.hpl_solve(A, ipiv, x)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         h.hpl_set_option(h.HPL_OPT_TIMING, 0)
@@ -659,7 +674,7 @@ def bench_hpl(args, torch, h, dev):
         "steps": len(times),
         "steps_requested": args.steps,
         "warmup": args.warmup,
-        "warmup_note": "warm-up steps are factor + solve at N = 4096 (code objects, workspace)",
+        "warmup_note": "warm-up steps are the same factor + solve at N = 4096 (code objects, workspace)",
         "ms_per_step": round(1e3 * total / len(times), 3),
         "step_seconds": [round(t, 3) for t in times],
         "higher_is_better": True,
@@ -674,6 +689,9 @@ def bench_hpl(args, torch, h, dev):
             "workload": f"HPL FP64 LU+solve, N={n}, NB={nb}, look-ahead {args.lookahead}, "
                         f"A,b ~ U[-0.5,0.5) seed {args.seed}",
             "n": n, "nb": nb, "lda": n + args.pad, "lookahead": args.lookahead,
+            "form": ("augmented [A | b]: LU with b carried as column N, row swaps right of each panel only, "
+                     "then back substitution (hpl_solve_augmented)" if augmented else
+                     "LAPACK: hpl_factor (swaps across all columns) + hpl_solve"),
             "interchange_workgroups": h.hpl_get_option(h.HPL_OPT_LASWP_WGS), "seed": args.seed,
             "scaled_residual": float(res[0]), "residual_pass": bool(res[0] < 16.0), "info": info,
             "budget_s": args.budget, "timed_budget_s": args.timed_budget,
@@ -717,6 +735,9 @@ def main():
     ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--mxp-nb", type=int, default=1024, help="panel width of the mixed-precision LU (--workload mxp)")
     ap.add_argument("--lookahead", type=int, default=1)
+    ap.add_argument("--form", choices=["augmented", "lapack"], default="augmented",
+                    help="hpl: augmented = the HPL formulation (b carried through the LU as column N, "
+                         "row swaps only right of each panel, then U x = b'); lapack = hpl_factor + hpl_solve")
     ap.add_argument("--seed", type=int, default=2304)
     ap.add_argument("--pad", type=int, default=0, help="lda = n + pad")
     ap.add_argument("--cpu-sample", type=int, default=4096,

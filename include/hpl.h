@@ -96,6 +96,34 @@ int hpl_solve(const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, in
               int64_t lda, int64_t ldb, int trans, void *hip_stream);
 
 /*
+ * hpl_solve_augmented -- the HPL benchmark's own formulation (Sec. II): A x = b
+ * is treated as the augmented system [A | B], which the blocked LU with
+ * partial pivoting turns into U X = L^{-1} P^{-1} B; X then follows by back
+ * substitution.  The row interchanges of each panel (the RS phase, Sec. II)
+ * reach only the columns to the right of the panel -- the remaining matrix and
+ * the right-hand sides -- never the finished L columns to its left.
+ *   1 A     device, n x (n + nrhs) at leading dimension lda: columns [0, n)
+ *           the matrix, columns [n, n + nrhs) the right-hand sides B.  On
+ *           return U is on and above the diagonal; below it, the multipliers of
+ *           each nb-column panel in the row order of that panel's own
+ *           factorization (the interchanges of later panels not applied to
+ *           them, unlike hpl_factor's LAPACK form); columns [n, n + nrhs) hold
+ *           the solution X (when info = 0).
+ *   2 n     order, 0 <= n <= 2^31 - 1.
+ *   3 lda   >= max(1, n).
+ *   4 nb    panel width, 1 <= nb <= 1024.
+ *   5 nrhs  right-hand sides, >= 0.
+ *   6 ipiv  device int32[n]: as hpl_factor's (the same pivots).
+ *   7 info  host int64*: as hpl_factor's; when info > 0 the back substitution
+ *           is skipped and columns [n, n + nrhs) hold L^{-1} P^{-1} B.
+ *   8 hip_stream
+ * The pivots and U are those of hpl_factor on the same matrix; look-ahead on or
+ * off gives bit-identical results.  Returns after X is complete.
+ */
+int hpl_solve_augmented(double *A, int64_t n, int64_t lda, int64_t nb, int64_t nrhs, int32_t *ipiv,
+                        int64_t *info, void *hip_stream);
+
+/*
  * hpl_solve_noalloc -- hpl_solve for callers that cannot allocate device
  * memory (code under stream capture, tight serving loops, harnesses that
  * forbid hipMalloc): the same arguments, kernels and results (bit for bit),

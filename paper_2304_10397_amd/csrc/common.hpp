@@ -260,6 +260,8 @@ int launch_apply_plans_seq(double *B, int64_t ldb, int64_t nrhs, const int32_t *
 // word (the block launches leave it at zero).
 int solve_sequence(const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, int64_t n, int64_t lda,
                    int64_t ldb, int trans, int32_t *plans, int *pivot_err, unsigned *done, hipStream_t st);
+int solve_upper_sequence(const double *U, double *B, int64_t nrhs, int64_t n, int64_t lda, int64_t ldb, unsigned *done,
+                         hipStream_t st);
 
 // Pure FP64 MFMA issue loop (probe.hip): nwg workgroups of 256 threads, iters
 // rounds of 16 independent 16x16x4 MFMAs per wave; mfma_peak_flops is its flop count.

@@ -481,9 +481,18 @@ static double now_s()
     return ts.tv_sec + 1e-9 * ts.tv_nsec;
 }
 
+// LU of the n x n matrix in A's first n columns.  nextra > 0: the columns
+// [n, n + nextra) are right-hand sides carried along as part of an augmented
+// system (every panel's interchanges, TRSM and GEMM reach them like any other
+// trailing column, so they end as L^{-1} P^{-1} B).  left_swaps: each panel's
+// interchanges are also applied to the columns left of it (L in LAPACK form);
+// without, each panel's multipliers stay in the row order of their own
+// factorization, as in HPL, where the row swaps reach only the columns to the
+// right of the panel (Sec. II).
 static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb, int32_t *ipiv, int64_t *info,
-                       hipStream_t su)
+                       hipStream_t su, int64_t nextra = 0, bool left_swaps = true)
 {
+    const int64_t ncol = n + nextra;
     Timer tm(d, opt_timing.load() != 0);
     Ctx x{d, A, n, lda, ipiv, (int)opt_panel_base.load(), (int)opt_panel_wgs.load(), (int)opt_gemm_tile.load(), &tm};
     x.host_threads = (int)opt_host_panel.load();
@@ -521,8 +530,8 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
                 // the next iteration waits for the panel's event
                 HPLX_PROPAGATE(update_cols(x, c0, jb, c1, jb2, plans, su, true));
                 HPLX_TRY(hipEventRecord(d->ev_la[j % kRing], su));
-                HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, n - c1 - jb2, plans, su, true));
-                HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
+                HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, ncol - c1 - jb2, plans, su, true));
+                if (left_swaps) HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
                 left_done = true;
                 HPLX_TRY(hipStreamWaitEvent(sp, d->ev_la[j % kRing], 0));
                 HPLX_PROPAGATE(panel_host(x, c1, jb2, next_plans, sp));
@@ -535,25 +544,28 @@ static int factor_impl(Device *d, double *A, int64_t n, int64_t lda, int64_t nb,
                 HPLX_TRY(hipEventRecord(d->ev_panel[(j + 1) % kRing], sp));
                 if (la_mode == 2) {
                     // full overlap: the trailing GEMM shares the GPU with the panel
-                    HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, n - c1 - jb2, plans, su, true));
+                    HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, ncol - c1 - jb2, plans, su, true));
                 } else {
                     // the panel overlaps the memory-bound RS and TRSM of the
                     // remaining columns and the interchanges on the left; the
                     // trailing GEMM starts once the panel is done, so the two
                     // never compete for the CUs
-                    HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, n - c1 - jb2, plans, su, false));
-                    HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
+                    HPLX_PROPAGATE(update_cols(x, c0, jb, c1 + jb2, ncol - c1 - jb2, plans, su, false));
+                    if (left_swaps) HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
                     left_done = true;
                     HPLX_TRY(hipStreamWaitEvent(su, d->ev_panel[(j + 1) % kRing], 0));
-                    HPLX_PROPAGATE(update_gemm(x, c0, jb, c1 + jb2, n - c1 - jb2, su));
+                    HPLX_PROPAGATE(update_gemm(x, c0, jb, c1 + jb2, ncol - c1 - jb2, su));
                 }
             } else {
-                HPLX_PROPAGATE(update_cols(x, c0, jb, c1, n - c1, plans, su, true));
+                HPLX_PROPAGATE(update_cols(x, c0, jb, c1, ncol - c1, plans, su, true));
                 HPLX_PROPAGATE(panel_any(x, c1, jb2, next_plans, su));
             }
+        } else if (nextra > 0) {
+            // last panel: its interchanges and L11^{-1} reach the carried columns
+            HPLX_PROPAGATE(update_cols(x, c0, jb, n, nextra, plans, su, true));
         }
         // interchanges of panel j on the columns to its left (L in LAPACK form)
-        if (!left_done) HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
+        if (!left_done && left_swaps) HPLX_PROPAGATE(apply_plans(A, lda, 0, c0, jb, plans, su, &tm));
         HPLX_TRY(hipEventRecord(d->ev_iter[j % kRing], su));
         // keep at most two iterations queued ahead of the device
         if (j >= 2) HPLX_TRY(hipEventSynchronize(d->ev_iter[(j - 2) % kRing]));
@@ -891,6 +903,33 @@ int hpl_solve(const double *LU, const int32_t *ipiv, double *B, int64_t nrhs, in
     Device *d = nullptr;
     HPLX_PROPAGATE(get_device(&d));
     return solve_impl(d, LU, ipiv, B, nrhs, n, lda, ldb, trans, (hipStream_t)hip_stream);
+}
+
+int hpl_solve_augmented(double *A, int64_t n, int64_t lda, int64_t nb, int64_t nrhs, int32_t *ipiv, int64_t *info,
+                        void *hip_stream)
+{
+    if (n > 0 && A == nullptr) return -1;
+    if (n < 0 || n > INT32_MAX) return -2;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (nb < 1 || nb > (int64_t)kMaxChunks * kMaxSwaps) return -4;
+    if (nrhs < 0) return -5;
+    if (n > 0 && ipiv == nullptr) return -6;
+    if (info == nullptr) return -7;
+    *info = 0;
+    if (n == 0) return HPL_OK;
+    Device *d = nullptr;
+    HPLX_PROPAGATE(get_device(&d));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HPLX_PROPAGATE(factor_impl(d, A, n, lda, nb, ipiv, info, st, nrhs, false));
+    if (*info != 0 || nrhs == 0) return HPL_OK;
+    // back substitution U X = L^{-1} P^{-1} B on the carried columns
+    Timer tm(d, opt_timing.load() != 0);
+    int id = tm.begin(ST_SOLVE, st);
+    HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)d->solve_done, 1, 0ull, st));
+    HPLX_PROPAGATE(solve_upper_sequence(A, A + off(0, n, lda), nrhs, n, lda, lda, d->solve_done, st));
+    HPLX_PROPAGATE(tm.end(id, st, (double)n * (double)n * (double)nrhs, 8.0 * 0.5 * (double)n * (double)n));
+    HPLX_TRY(hipStreamSynchronize(st));
+    return tm.collect();
 }
 
 int hpl_residual(const double *A0, int64_t n, int64_t lda, const double *X, int64_t ldx, const double *B, int64_t ldb,

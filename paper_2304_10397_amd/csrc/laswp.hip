@@ -21,6 +21,9 @@ namespace hplx {
 namespace {
 
 constexpr int kPlanThreads = kMaxSwaps;  // one thread per interchange
+constexpr int kHash = 4 * kMaxSwaps;     // open-addressing table of the rows outside the block (load <= 1/4)
+constexpr int kHashBits = 11;
+static_assert(kHash == 1 << kHashBits, "table size");
 constexpr int kLwCols = 8;               // columns per laswp workgroup
 constexpr int kLwThreads = 256;
 
@@ -47,9 +50,15 @@ __global__ __launch_bounds__(kPlanThreads) void swap_plan_kernel(const int32_t *
     __shared__ int used[2 * kMaxSwaps];
     __shared__ int pos[2 * kMaxSwaps];    // compacted position of slot s
     __shared__ int scan[kPlanThreads];
+    __shared__ int hkey[kHash];           // outside row (relative to r0), or -1
+    __shared__ int hfirst[kHash];         // its first interchange index
     __shared__ int bad;
     const int t = threadIdx.x;
     if (t == 0) bad = 0;
+    for (int e = t; e < kHash; e += kPlanThreads) {
+        hkey[e] = -1;
+        hfirst[e] = kMaxSwaps;
+    }
     __syncthreads();
     if (t < cnt) {
         const int64_t p = ipiv[t];
@@ -66,16 +75,28 @@ __global__ __launch_bounds__(kPlanThreads) void swap_plan_kernel(const int32_t *
         }
         return;
     }
+    // a row outside the contiguous block takes slot cnt + (its first interchange
+    // index): the rows are entered into an LDS hash table (linear probing; at
+    // most cnt keys in 4 cnt entries, so every probe sequence ends), which
+    // keeps the smallest interchange index of each row
+    int hs = -1;
+    if (t < cnt && piv[t] >= cnt) {
+        const int p = piv[t];
+        int hh = (int)(((unsigned)p * 2654435761u) >> (32 - kHashBits));
+        for (int probe = 0; probe < kHash; ++probe) {
+            const int old = atomicCAS(&hkey[hh], -1, p);
+            if (old == -1 || old == p) {
+                hs = hh;
+                break;
+            }
+            hh = (hh + 1) & (kHash - 1);
+        }
+        if (hs >= 0) atomicMin(&hfirst[hs], t);
+    }
+    __syncthreads();
     if (t < cnt) {
         const int p = piv[t];
-        int b = p;
-        if (p >= cnt) {  // outside the contiguous block: slot cnt + first k' with the same row
-            int f = t;
-            for (int k2 = 0; k2 < t; ++k2)
-                if (piv[k2] == p) { f = k2; break; }
-            b = cnt + f;
-        }
-        bslot[t] = b;
+        bslot[t] = (p >= cnt) ? cnt + (hs >= 0 ? hfirst[hs] : t) : p;
     }
     __syncthreads();
     for (int s = t; s < 2 * cnt; s += kPlanThreads)

@@ -296,8 +296,8 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
     __shared__ double topv[kRegW];   // diagonal row (workgroup 0)
     __shared__ double u[kRegW];      // pivot row, active columns
     __shared__ double tr[kRegW];     // old diagonal row, active columns
-    __shared__ double rv[2][kRegWaves];
-    __shared__ unsigned ri[2][kRegWaves];
+    __shared__ double rv[kRegWaves];
+    __shared__ unsigned ri[kRegWaves];
     __shared__ int s_abort;
     __shared__ uint32_t xw[3 * kLeafMaxWGs + 4 * kRegW];  // payloads of one exchange: keys, then two rows
 
@@ -333,44 +333,76 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
         const int na = w - k;  // active columns
         const uint32_t tag = tag0 + (uint32_t)k + 1u;
         const int par = k & 1;
-        // ---- 1. this workgroup's candidate and the rows to publish
-        block_argmax512(bv, bi, rv[0], ri[0]);
-#pragma unroll
-        for (int q = 0; q < kRegRPT; ++q) {
-            if (row[q] == bi && row[q] < rend) {
-#pragma unroll
-                for (int j = 0; j < kRegW; ++j) cand[j] = v[q][j];
-            }
-            if (g == 0 && row[q] == k) {
-#pragma unroll
-                for (int j = 0; j < kRegW; ++j) topv[j] = v[q][j];
-            }
-        }
-        __syncthreads();
+        // ---- 1. this workgroup's candidate (one barrier)
+        block_argmax512(bv, bi, rv, ri);
         double pv;
         int64_t p;
+        bool singular;
         if (G == 1) {
+#pragma unroll
+            for (int q = 0; q < kRegRPT; ++q) {
+                if (row[q] == bi && row[q] < rend) {
+#pragma unroll
+                    for (int j = 0; j < kRegW; ++j) cand[j] = v[q][j];
+                }
+                if (row[q] == k) {
+#pragma unroll
+                    for (int j = 0; j < kRegW; ++j) topv[j] = v[q][j];
+                }
+            }
+            __syncthreads();
             pv = bv;
             p = bi;
+            singular = !(pv > 0.0);
             if (t < na) {
-                u[t] = cand[t];
                 tr[t] = topv[t];
+                u[t] = singular ? topv[t] : cand[t];  // singular: no interchange, u is the diagonal row
             }
         } else {
-            // ---- 2. publish (tagged words, no fences)
+            // ---- 2. publish (tagged words, no fences): the key, then the
+            //      candidate row and (workgroup 0) the diagonal row, each sent
+            //      by the wave that holds it: the holding lane puts the row in
+            //      LDS and its wave reads it back one value per lane (the LDS
+            //      operations of one wave complete in order).  A workgroup
+            //      without a candidate still sends tagged words, so that no
+            //      reader ever waits on a slot that is not written.
             unsigned long long *my = slots + ((size_t)par * kLeafMaxWGs + g) * kLeafSlotWords;
             if (t == 0) put_tagged(my, tag, (uint32_t)bi);
             if (t == 1) put_tagged(my + 1, tag, (uint32_t)(__double_as_longlong(bv)));
             if (t == 2) put_tagged(my + 2, tag, (uint32_t)((unsigned long long)__double_as_longlong(bv) >> 32));
-            if (t >= 64 && t < 64 + 2 * na) {
-                const int e = t - 64, j = e >> 1;
-                const unsigned long long bits = (unsigned long long)__double_as_longlong(cand[j]);
-                put_tagged(my + 3 + e, tag, (e & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits);
+            const int lane = t & 63;
+            const bool mine = bi != INT64_MAX && (row[0] == bi || row[1] == bi);
+            if (__ballot(mine) != 0) {
+                if (mine) {
+                    const bool q0 = row[0] == bi;
+#pragma unroll
+                    for (int j = 0; j < kRegW; ++j) cand[j] = q0 ? v[0][j] : v[1][j];
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                if (lane < 2 * na) {
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(cand[lane >> 1]);
+                    put_tagged(my + 3 + lane, tag, (lane & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits);
+                }
+            } else if (bi == INT64_MAX && t < 2 * na) {
+                put_tagged(my + 3 + t, tag, 0u);
             }
-            if (g == 0 && t >= 128 && t < 128 + 2 * na) {
-                const int e = t - 128, j = e >> 1;
-                const unsigned long long bits = (unsigned long long)__double_as_longlong(topv[j]);
-                put_tagged(topw + (size_t)par * 2 * kRegW + e, tag, (e & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits);
+            if (g == 0) {
+                const bool diag = row[0] == k || row[1] == k;
+                if (__ballot(diag) != 0) {
+                    if (diag) {
+                        const bool q0 = row[0] == k;
+#pragma unroll
+                        for (int j = 0; j < kRegW; ++j) topv[j] = q0 ? v[0][j] : v[1][j];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    if (lane < 2 * na) {
+                        const unsigned long long bits = (unsigned long long)__double_as_longlong(topv[lane >> 1]);
+                        put_tagged(topw + (size_t)par * 2 * kRegW + lane, tag,
+                                   (lane & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits);
+                    }
+                }
             }
             // ---- 3. two short round trips.  (a) every candidate's key (row,
             //      |a|): one tagged word per thread, so the polls of a step run
@@ -384,43 +416,50 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
             }
             __syncthreads();
             if (s_abort) return;
-            double gv = -1.0;
-            int64_t gi = INT64_MAX;
-            if (t < G) {
-                gv = dbl_of(xw[3 * t + 1], xw[3 * t + 2]);
-                gi = (int64_t)xw[3 * t];
+            // every wave reduces the G keys itself (largest |a|, lowest row on
+            // ties), so that no further barrier is needed
+            {
+                double gv = -1.0;
+                unsigned gr = 0xffffffffu;
+                for (int e = lane; e < G; e += 64) {
+                    const double x = dbl_of(xw[3 * e + 1], xw[3 * e + 2]);
+                    const unsigned y = xw[3 * e];
+                    if (x > gv || (x == gv && y < gr)) { gv = x; gr = y; }
+                }
+                pv = wave_max(gv);
+                const unsigned r = wave_min_u32(gv == pv ? gr : 0xffffffffu);
+                p = (r == 0xffffffffu) ? INT64_MAX : (int64_t)r;
             }
-            block_argmax512(gv, gi, rv[1], ri[1]);
-            pv = gv;
-            p = gi;
-            // (b) the winner's row and the diagonal row (2 words per value)
+            singular = !(pv > 0.0);
+            // (b) the winner's row and the diagonal row: each thread t < 2 na
+            //     takes one value (its two tagged halves)
             const int64_t owner0 = (p == INT64_MAX) ? 0 : p / R;
             const int owner = (int)(owner0 < G ? owner0 : G - 1);
-            uint32_t *rw = xw + 3 * kLeafMaxWGs;
-            if (t < 4 * na) {
-                uint32_t pay = 0;
+            if (t < 2 * na) {
+                const bool top = t >= na;
+                const int j = top ? t - na : t;
                 const unsigned long long *src =
-                    (t < 2 * na) ? slots + ((size_t)par * kLeafMaxWGs + owner) * kLeafSlotWords + 3 + t
-                                 : topw + (size_t)par * 2 * kRegW + (t - 2 * na);
-                if (!get_tagged(src, tag, pay, sync.abort_flag, t0)) s_abort = 1;
-                rw[t] = pay;
-            }
-            __syncthreads();
-            if (s_abort) return;
-            if (t < na) {
-                u[t] = dbl_of(rw[2 * t], rw[2 * t + 1]);
-                tr[t] = dbl_of(rw[2 * na + 2 * t], rw[2 * na + 2 * t + 1]);
+                    top ? topw + (size_t)par * 2 * kRegW + 2 * j
+                        : slots + ((size_t)par * kLeafMaxWGs + owner) * kLeafSlotWords + 3 + 2 * j;
+                uint32_t lo = 0, hi = 0;
+                if (!get_tagged(src, tag, lo, sync.abort_flag, t0) || !get_tagged(src + 1, tag, hi, sync.abort_flag, t0))
+                    s_abort = 1;
+                const double x = dbl_of(lo, hi);
+                if (top) {
+                    tr[j] = x;
+                    if (singular) u[j] = x;  // no interchange: u is the diagonal row
+                } else if (!singular) {
+                    u[j] = x;
+                }
             }
         }
         __syncthreads();
-        const bool singular = !(pv > 0.0);
-        if (singular) p = k;  // no interchange; u already is the diagonal row when p == k
-        if (singular && t < na) u[t] = tr[t];
+        if (s_abort) return;
+        if (singular) p = k;
         if (g == 0 && t == 0) {
             ipiv[c + k] = (int32_t)(c + p);
             if (singular) atomicMin(sync.info, (unsigned long long)(c + k + 1));
         }
-        __syncthreads();
         // ---- 5. U row k, interchange of the active parts, scale, rank-1 update
         if (g == 0 && t < na) S[off(k, k + t, lda)] = u[t];
         double uu[kRegW];

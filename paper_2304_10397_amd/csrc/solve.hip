@@ -298,4 +298,25 @@ int solve_sequence(const double *LU, const int32_t *ipiv, double *B, int64_t nrh
     return HPL_OK;
 }
 
+// U X = B alone (the back substitution of an augmented system, whose
+// right-hand sides already hold L^{-1} P^{-1} B): per chunk of at most 64
+// right-hand sides, the backward sweep of 64-row diagonal blocks.
+int solve_upper_sequence(const double *U, double *B, int64_t nrhs, int64_t n, int64_t lda, int64_t ldb, unsigned *done,
+                         hipStream_t st)
+{
+    const int64_t bs = kBs;
+    const int64_t rhs_chunk = 64;
+    const int64_t nblk = (n + bs - 1) / bs;
+    for (int64_t c0 = 0; c0 < nrhs; c0 += rhs_chunk) {
+        const int64_t nr = (nrhs - c0) < rhs_chunk ? (nrhs - c0) : rhs_chunk;
+        double *Bc = B + off(0, c0, ldb);
+        for (int64_t q = nblk - 1; q >= 0; --q) {
+            const int64_t r0 = q * bs;
+            const int64_t b = (n - r0) < bs ? (n - r0) : bs;
+            HPLX_PROPAGATE(launch_solve_block(U, lda, Bc, ldb, nr, r0, b, 0, r0, 1, done, st));
+        }
+    }
+    return HPL_OK;
+}
+
 }  // namespace hplx

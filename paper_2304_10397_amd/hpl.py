@@ -62,6 +62,7 @@ def _load():
         "hpl_factor": (i32, [P, i64, i64, i64, P, P, P]),
         "hpl_solve": (i32, [P, P, P, i64, i64, i64, i64, i32, P]),
         "hpl_solve_noalloc": (i32, [P, P, P, i64, i64, i64, i64, i32, P]),
+        "hpl_solve_augmented": (i32, [P, i64, i64, i64, i64, P, P, P]),
         "hpl_residual": (i32, [P, i64, i64, P, i64, P, i64, i64, P, P]),
         "hpl_residual_gen": (i32, [u64, i64, P, i64, P, i64, i64, P, P]),
         "hpl_generate": (i32, [u64, u64, P, i64, i64, i64, P]),
@@ -187,6 +188,24 @@ def hpl_solve(LU, ipiv, B, trans=0, stream=None):
                         _stream(stream))
     _check("hpl_solve", rc)
     return B
+
+
+def hpl_solve_augmented(AB, n, nb, ipiv=None, stream=None):
+    """Solve of the augmented system AB = [A | B] (n x (n + nrhs), column-major
+    CUDA tensor) in place: returns (ipiv, info); AB[:, n:] then holds X."""
+    torch = _torch()
+    pA, rows, cols, lda = _matrix("AB", AB)
+    if rows != n or cols < n:
+        raise ValueError(f"AB must be {n} x (n + nrhs), got {rows} x {cols}")
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=AB.device)
+    if ipiv.dtype != torch.int32 or not ipiv.is_cuda or ipiv.numel() < n:
+        raise TypeError("ipiv must be an int32 CUDA tensor with n entries")
+    info = ctypes.c_int64(0)
+    _check("hpl_solve_augmented", _lib.hpl_solve_augmented(pA, n, lda, int(nb), cols - n,
+                                                            ctypes.c_void_p(ipiv.data_ptr()), ctypes.byref(info),
+                                                            _stream(stream)))
+    return ipiv[:n], int(info.value)
 
 
 def hpl_solve_noalloc(LU, ipiv, B, trans=0, stream=None):

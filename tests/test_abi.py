@@ -51,6 +51,21 @@ def test_factor_argument_errors():
     assert L.hpl_factor(None, 0, 1, 64, None, ctypes.byref(info), None) == 0 and info.value == 0
 
 
+def test_solve_augmented_argument_errors():
+    L = h.lib()
+    info = ctypes.c_int64(7)
+    assert L.hpl_solve_augmented(None, 10, 10, 64, 1, FAKE, ctypes.byref(info), None) == -1
+    assert L.hpl_solve_augmented(FAKE, -1, 10, 64, 1, FAKE, ctypes.byref(info), None) == -2
+    assert L.hpl_solve_augmented(FAKE, 10, 9, 64, 1, FAKE, ctypes.byref(info), None) == -3
+    assert L.hpl_solve_augmented(FAKE, 10, 10, 0, 1, FAKE, ctypes.byref(info), None) == -4
+    assert L.hpl_solve_augmented(FAKE, 10, 10, 1025, 1, FAKE, ctypes.byref(info), None) == -4
+    assert L.hpl_solve_augmented(FAKE, 10, 10, 64, -1, FAKE, ctypes.byref(info), None) == -5
+    assert L.hpl_solve_augmented(FAKE, 10, 10, 64, 1, None, ctypes.byref(info), None) == -6
+    assert L.hpl_solve_augmented(FAKE, 10, 10, 64, 1, FAKE, None, None) == -7
+    assert info.value == 7  # untouched on argument errors
+    assert L.hpl_solve_augmented(None, 0, 1, 64, 1, None, ctypes.byref(info), None) == 0 and info.value == 0
+
+
 def test_solve_argument_errors():
     L = h.lib()
     assert L.hpl_solve(None, FAKE, FAKE, 1, 10, 10, 10, 0, None) == -1
