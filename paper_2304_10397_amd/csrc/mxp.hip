@@ -377,6 +377,7 @@ __global__ __launch_bounds__(256) void cvt_u_kernel(const float *__restrict__ U,
 // Requires K % 64 == 0.
 // ---------------------------------------------------------------------------
 constexpr int kHBM = 128, kHBN = 128, kHBK = 64, kHPad = 8;
+constexpr int64_t kHGroupM = 8;  // tile-rows per group of the XCD-aware order
 
 template <int FMT>
 __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t n, int64_t K,
@@ -391,7 +392,11 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
     asm volatile("" ::: "a0");
     __shared__ __attribute__((aligned(16))) H As[2][kHBM][kHBK + kHPad];
     __shared__ __attribute__((aligned(16))) H Bs[2][kHBN][kHBK + kHPad];
-    const int64_t tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    // XCD-aware tile order: the workgroups resident on one XCD at a time cover
+    // a compact block of tiles, which share A row-panels and B column-panels
+    // in that XCD's L2
+    int64_t tm, tn;
+    tile_of_block(blockIdx.x, (int64_t)gridDim.x, tiles_m, (n + kHBN - 1) / kHBN, kHGroupM, tm, tn);
     const int64_t m0 = tm * kHBM, n0 = tn * kHBN;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
@@ -492,6 +497,178 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
                     const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
                     if (i < m && j < n) C[off(i, j, ldc)] = acc[R][G][r];
                 }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The same update on 256 x 128 tiles for the large trailing matrices.  With K
+// = NB = 1024 a 128 x 128 tile streams 512 KB of operands through its k-loop,
+// and its double-buffered staging leaves each load one 64-k step of matrix-core
+// work (~0.2 us) to arrive in: the loop waits on the operands far more than it
+// computes.  Here:
+//  * tile 256 x 128, 4 waves of 128 x 64 (8 x 4 blocks of 16 x 16, 128 FP32
+//    accumulators in AGPRs): a third more matrix-core work per operand byte
+//    than the 128 x 128 tile;
+//  * K staged 32 at a time (one MFMA k-step) in a ring of 3 LDS buffers of
+//    24 KB, filled by global_load_lds_dwordx4 (64 lanes x 16 bytes straight
+//    into LDS, no staging registers) two stages ahead; two workgroups per CU,
+//    so four stages per CU are in flight while two are computed;
+//  * A (and B) sit in LDS as 16-byte units, row r's 4 units (8 k each) in the
+//    order s ^ ((r >> 1) & 3): the fragment reads (16 rows x 8 k per lane
+//    group) then touch all banks once per 8 lanes.  The DMA takes its swizzle
+//    from the lane -> global address map;
+//  * the accumulators start at zero and C is added once at the end (read into
+//    the accumulators up front, C would leave the compiler's waits for those
+//    loads inside the k-loop, where -- blind to the DMA of the inline assembly
+//    -- they would also drain the stages in flight).  The 128 x 128 kernel
+//    starts from C: the two round differently.
+// Requires K % 32 == 0 and K <= 2^20 (32-bit DMA offsets).
+// ---------------------------------------------------------------------------
+constexpr int kH2M = 256, kH2N = 128, kH2K = 32, kH2S = 3;
+constexpr int kH2AInst = kH2M / 16 / 4;  // A DMA instructions per wave per stage (16 rows each)
+constexpr int kH2BInst = kH2N / 16 / 4;  // B DMA instructions per wave per stage
+
+#define HPLX_LDS3(p) ((__attribute__((address_space(3))) void *)(p))
+
+template <int FMT>
+__global__ __launch_bounds__(256, 2) void hgemm256_update_kernel(int64_t m, int64_t n, int64_t K,
+                                                                 const typename Half<FMT>::T *__restrict__ A16,
+                                                                 const typename Half<FMT>::T *__restrict__ B16,
+                                                                 float *__restrict__ C, int64_t ldc, int64_t tiles_m,
+                                                                 int64_t tiles_n)
+{
+    typedef typename Half<FMT>::T H;
+    typedef H h8 __attribute__((ext_vector_type(8)));
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    asm volatile("" ::: "a0");
+    __shared__ __attribute__((aligned(1024))) H As[kH2S][kH2M * kH2K];
+    __shared__ __attribute__((aligned(1024))) H Bs[kH2S][kH2N * kH2K];
+    int64_t tm, tn;
+    tile_of_block(blockIdx.x, (int64_t)gridDim.x, tiles_m, tiles_n, 4, tm, tn);
+    const int64_t m0 = tm * kH2M, n0 = tn * kH2N;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & 3;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 15, lg = lane >> 4;
+
+    // DMA map: instruction q of an operand stage fills LDS units 64q .. 64q+63;
+    // lane i writes unit u = 64q + i = 4r + (s ^ ((r >> 1) & 3)), so it loads
+    // row r = 16q + i/4, k segment s = (i & 3) ^ ((r >> 1) & 3).  Rows
+    // (columns) past the matrix are clamped to the last one.
+    uint32_t a_off[kH2AInst], b_off[kH2BInst];
+#pragma unroll
+    for (int q = 0; q < kH2AInst; ++q) {
+        const int r = 16 * (kH2AInst * wave + q) + (lane >> 2);
+        const int sg = (lane & 3) ^ ((r >> 1) & 3);
+        const int64_t rc = (m0 + r < m) ? r : (m - 1 - m0);
+        a_off[q] = (uint32_t)(rc * K + 8 * sg) * 2u;
+    }
+#pragma unroll
+    for (int q = 0; q < kH2BInst; ++q) {
+        const int r = 16 * (kH2BInst * wave + q) + (lane >> 2);
+        const int sg = (lane & 3) ^ ((r >> 1) & 3);
+        const int64_t rc = (n0 + r < n) ? r : (n - 1 - n0);
+        b_off[q] = (uint32_t)(rc * K + 8 * sg) * 2u;
+    }
+    const char *a_tile = (const char *)(A16 + (size_t)m0 * (size_t)K);
+    const char *b_tile = (const char *)(B16 + (size_t)n0 * (size_t)K);
+    const uint32_t lds_a = (uint32_t)(uintptr_t)HPLX_LDS3(&As[0][0]);
+    const uint32_t lds_b = (uint32_t)(uintptr_t)HPLX_LDS3(&Bs[0][0]);
+    auto dma_stage = [&](int st, int buf) __attribute__((always_inline)) {
+        const char *asrc = a_tile + (size_t)st * kH2K * 2;
+        const char *bsrc = b_tile + (size_t)st * kH2K * 2;
+#pragma unroll
+        for (int q = 0; q < kH2AInst; ++q) {
+            const uint32_t dst = lds_a + 2u * (uint32_t)(buf * kH2M * kH2K) + 1024u * (uint32_t)(kH2AInst * wave + q);
+            asm volatile("global_load_lds_dwordx4 %0, %1" ::"v"(a_off[q]), "s"(asrc), "{m0}"(dst) : "memory");
+        }
+#pragma unroll
+        for (int q = 0; q < kH2BInst; ++q) {
+            const uint32_t dst = lds_b + 2u * (uint32_t)(buf * kH2N * kH2K) + 1024u * (uint32_t)(kH2BInst * wave + q);
+            asm volatile("global_load_lds_dwordx4 %0, %1" ::"v"(b_off[q]), "s"(bsrc), "{m0}"(dst) : "memory");
+        }
+    };
+
+    // acc[R][G][r]: the update of C(m0 + 128wm + 16R + li, n0 + 64wn + 16G + 4lg + r)
+    f4 acc[8][4];
+#pragma unroll
+    for (int R = 0; R < 8; ++R)
+#pragma unroll
+        for (int G = 0; G < 4; ++G) acc[R][G] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t rbase = m0 + 128 * wm + li, cbase = n0 + 64 * wn + 4 * lg;
+    const bool inner = m0 + kH2M <= m && n0 + kH2N <= n;  // uniform
+
+    const int nst = (int)(K / kH2K);
+    constexpr int kPer = kH2AInst + kH2BInst;  // DMA instructions per wave per stage
+    // prologue: stages 0 and 1 in flight; stage 0 landed before the loop
+    dma_stage(0, 0);
+    if (nst > 1) {
+        dma_stage(1, 1);
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(kPer) : "memory");
+    } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    __syncthreads();
+
+    // fragment read offsets (in halves) within a stage buffer
+    int a_unit[8], b_unit[4];
+#pragma unroll
+    for (int R = 0; R < 8; ++R) {
+        const int r = 128 * wm + 16 * R + li;
+        a_unit[R] = 8 * (4 * r + (lg ^ ((r >> 1) & 3)));
+    }
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const int c = 64 * wn + 16 * G + li;
+        b_unit[G] = 8 * (4 * c + (lg ^ ((c >> 1) & 3)));
+    }
+    int buf = 0;
+    for (int st = 0; st < nst; ++st) {
+        if (st + 2 < nst) dma_stage(st + 2, buf == 0 ? 2 : buf - 1);
+        h8 af[8], bf[4];
+#pragma unroll
+        for (int R = 0; R < 8; ++R) af[R] = *(const h8 *)&As[buf][a_unit[R]];
+#pragma unroll
+        for (int G = 0; G < 4; ++G) bf[G] = *(const h8 *)&Bs[buf][b_unit[G]];
+#pragma unroll
+        for (int R = 0; R < 8; ++R)
+#pragma unroll
+            for (int G = 0; G < 4; ++G) {
+                if constexpr (FMT == 0)
+                    acc[R][G] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bf[G], af[R], acc[R][G], 0, 0, 0);
+                else
+                    acc[R][G] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[G], af[R], acc[R][G], 0, 0, 0);
+            }
+        // stage st+1 must have landed; the DMA of stage st+2 may still be in flight
+        if (st + 2 < nst)
+            asm volatile("s_waitcnt vmcnt(%0)" ::"n"(kPer) : "memory");
+        else
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        buf = (buf == kH2S - 1) ? 0 : buf + 1;
+    }
+
+    // C += acc: an inner tile reads and writes each column's 8 rows from one
+    // address; an edge tile tests every element
+    if (inner) {
+#pragma unroll
+        for (int G = 0; G < 4; ++G)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float *col = C + off(rbase, cbase + 16 * G + r, ldc);
+#pragma unroll
+                for (int R = 0; R < 8; ++R) col[16 * R] += acc[R][G][r];
+            }
+    } else {
+#pragma unroll
+        for (int G = 0; G < 4; ++G)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j = cbase + 16 * G + r;
+#pragma unroll
+                for (int R = 0; R < 8; ++R)
+                    if (j < n && rbase + 16 * R < m) C[off(rbase + 16 * R, j, ldc)] += acc[R][G][r];
+            }
     }
 }
 
@@ -682,6 +859,21 @@ int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A1
 {
     if (m <= 0 || n <= 0 || K <= 0) return HPL_OK;
     if (K % kHBK) return HPL_ERR_INTERNAL;
+    // large updates on 256 x 128 tiles (at least two tiles per CU), the rest
+    // on 128 x 128
+    const int64_t t2m = blocks_of(m, kH2M), t2n = blocks_of(n, kH2N);
+    if (t2m * t2n >= 512 && K % kH2K == 0 && K <= (1 << 20)) {
+        const int64_t g2 = t2m * t2n;
+        if (g2 > 0x7fffffffll) return HPL_ERR_INTERNAL;
+        if (fmt == 0)
+            hipLaunchKernelGGL(hgemm256_update_kernel<0>, dim3((unsigned)g2), dim3(256), 0, st, m, n, K,
+                               (const _Float16 *)A16, (const _Float16 *)B16, C, ldc, t2m, t2n);
+        else
+            hipLaunchKernelGGL(hgemm256_update_kernel<1>, dim3((unsigned)g2), dim3(256), 0, st, m, n, K,
+                               (const __bf16 *)A16, (const __bf16 *)B16, C, ldc, t2m, t2n);
+        HPLX_TRY_LAUNCH();
+        return HPL_OK;
+    }
     const int64_t tiles_m = blocks_of(m, kHBM), tiles_n = blocks_of(n, kHBN);
     const int64_t g = tiles_m * tiles_n;
     if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
