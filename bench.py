@@ -43,8 +43,8 @@ PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X, FP64 vector (256 CUs x 128 flop/clk x 2
 # HBM bytes per trailing-GEMM launch measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 2048 MiB copy: x2.000 and x1.000) at the default
 # workload, valid only for the GEMM source with this SHA-256 prefix.
-MEASURED_TRAFFIC = {"gemm_sha256_16": "87004d1e525164c4", "n": 163840, "nb": 512,
-                    "fetch_gb": 134.13, "write_gb": 35.79}
+MEASURED_TRAFFIC = {"gemm_sha256_16": "87004d1e525164c4", "n": 163840, "nb": 512, "form": "augmented",
+                    "fetch_gb": 138.35, "write_gb": 35.74}
 
 
 def log(msg):
@@ -132,14 +132,14 @@ def cpu_baseline(sizes, seed, threads):
     return out, x_small
 
 
-def measured_traffic(n, nb):
+def measured_traffic(n, nb, form):
     """Counter-measured bytes per trailing-GEMM launch, or None if the kernel or workload differs."""
     import hashlib
     src = os.path.join(ROOT, "paper_2304_10397_amd", "csrc", "gemm.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
     t = MEASURED_TRAFFIC
-    if sha != t["gemm_sha256_16"] or n != t["n"] or nb != t["nb"]:
+    if sha != t["gemm_sha256_16"] or n != t["n"] or nb != t["nb"] or form != t["form"]:
         return None
     return round((t["fetch_gb"] + t["write_gb"]) * 1e9)
 
@@ -316,7 +316,7 @@ def bench_mxp(args, torch, h):
             "fp16_phase_ms": {"trailing_update": round(g["ms"], 2), "panel_u12_convert": round(f["ms"], 2)},
         },
         "roofline": {
-            "kernel": "hgemm_update_kernel (A22 += (-L21) U12, FP16 MFMA, FP32 C)",
+            "kernel": "hgemm256_update_kernel (256x128 tiles) and hgemm_update_kernel (128x128, small updates): A22 += (-L21) U12, FP16 MFMA, FP32 C",
             "bound": "hbm",
             "achieved": round(g["bytes"] / (g["ms"] * 1e-3) / 1e9, 1) if g["ms"] else None,
             "peak": PEAK_HBM_GBS,
@@ -707,7 +707,7 @@ def bench_hpl(args, torch, h, dev):
             "launches": g["launches"],
             "avg_launch_ms": round(g["ms"] / g["launches"], 4) if g["launches"] else None,
             "avg_launch_gflop": round(g["flops"] / g["launches"] / 1e9, 3) if g["launches"] else None,
-            "traffic": measured_traffic(n, nb),
+            "traffic": measured_traffic(n, nb, args.form),
             "traffic_unit": "bytes per launch (L2-miss fetch + write, rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated; includes MALL hits)",
             "algorithmic_bytes_per_launch": round(g["bytes"] / g["launches"]) if g["launches"] else None,

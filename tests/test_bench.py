@@ -29,9 +29,11 @@ def test_traffic_reported_only_for_the_measured_kernel_and_workload():
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
     t = b.MEASURED_TRAFFIC
     expect = round((t["fetch_gb"] + t["write_gb"]) * 1e9) if sha == t["gemm_sha256_16"] else None
-    assert b.measured_traffic(t["n"], t["nb"]) == expect
-    assert b.measured_traffic(t["n"], 256) is None
-    assert b.measured_traffic(1024, t["nb"]) is None
+    assert b.measured_traffic(t["n"], t["nb"], t["form"]) == expect
+    assert b.measured_traffic(t["n"], 256, t["form"]) is None
+    assert b.measured_traffic(1024, t["nb"], t["form"]) is None
+    other = "lapack" if t["form"] == "augmented" else "augmented"
+    assert b.measured_traffic(t["n"], t["nb"], other) is None
 
 
 def test_flop_count_is_the_metric_formula():
