@@ -581,6 +581,8 @@ def bench_hpl(args, torch, h, dev):
     n, nb = args.n, args.nb
     log(f"device {torch.cuda.get_device_name(dev)}; N={n} NB={nb} look-ahead={args.lookahead}")
     h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, args.lookahead)
+    if args.laswp_wgs is not None:
+        h.hpl_set_option(h.HPL_OPT_LASWP_WGS, args.laswp_wgs)
 
     # Warm-up (not timed): factor + solve at N = 4096 loads the code objects and
     # the workspace; a full-size warm-up would add nothing else.
@@ -735,6 +737,8 @@ def main():
     ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--mxp-nb", type=int, default=1024, help="panel width of the mixed-precision LU (--workload mxp)")
     ap.add_argument("--lookahead", type=int, default=1)
+    ap.add_argument("--laswp-wgs", type=int, default=None,
+                    help="hpl: workgroups of the trailing interchanges (HPL_OPT_LASWP_WGS; default: the library's)")
     ap.add_argument("--form", choices=["augmented", "lapack"], default="augmented",
                     help="hpl: augmented = the HPL formulation (b carried through the LU as column N, "
                          "row swaps only right of each panel, then U x = b'); lapack = hpl_factor + hpl_solve")
