@@ -191,6 +191,11 @@ int launch_gemm_skinny(int64_t m, int64_t n, int64_t k, const double *A, int64_t
 // trsm.hip: B(nbk x ncols) <- L^{-1} B, L unit lower nbk x nbk (nbk <= 512).
 int launch_trsm_llnu(const double *L, int64_t ldl, double *B, int64_t ldb, int64_t nbk,
                      int64_t ncols, hipStream_t st);
+// The same small solve (one wave per column) for the FP32 panel of the
+// mixed-precision factorization: nbk <= 512, ncols <= 4096.
+bool trsm32_small_ok(int64_t nbk, int64_t ncols);
+int launch_trsm32_small(const float *L, int64_t ldl, float *B, int64_t ldb, int64_t nbk, int64_t ncols,
+                        hipStream_t st);
 
 // laswp.hip
 // Interchanges k = 0..cnt-1: row r0+k <-> ipiv[k] (global rows, ipiv[k] >= r0+k),

@@ -646,6 +646,9 @@ static int mxp_trsm(const float *L, int64_t ldl, int64_t nbk, float *B, int64_t 
 {
     if (nbk <= 0 || ncols <= 0) return HPL_OK;
     if (nbk <= 32) return launch_trsm32_leaf(L, ldl, B, ldb, (int)nbk, ncols, st);
+    // the panel's own solves (few columns): one launch instead of a recursion
+    // of leaves and GEMMs
+    if (trsm32_small_ok(nbk, ncols)) return launch_trsm32_small(L, ldl, B, ldb, nbk, ncols, st);
     const int64_t h = ((nbk / 2 + 31) / 32) * 32;
     HPLX_PROPAGATE(mxp_trsm(L, ldl, h, B, ldb, ncols, st));
     HPLX_PROPAGATE(launch_sgemm32(nbk - h, ncols, h, L + h, ldl, B, ldb, B + h, ldb, st));

@@ -150,44 +150,53 @@ __global__ __launch_bounds__(kTrWaves * 64, 2) void trsm_llnu_kernel(const doubl
     }
 }
 
-// Small TRSM (the panel's inner solves: nbk <= 256, few columns).  One wave per
-// column of B: lane l holds rows l, l+64, l+128, l+192 of that column, and step
-// k broadcasts the finished x_k with v_readlane (k is uniform), so the
+// Small TRSM (the panel's inner solves: nbk <= 64 RPL, few columns).  One wave
+// per column of B: lane l holds rows l, l+64, l+128, ... of that column, and
+// step k broadcasts the finished x_k with v_readlane (k is uniform), so the
 // dependency chain per step is a readlane and an FMA.  The 4 waves of a
 // workgroup share L, staged through LDS 16 columns at a time (double-buffered:
 // the next chunk is fetched into registers while the current one is used).
-constexpr int kSmRPL = 4;    // rows per lane (nbk <= 256)
-constexpr int kSmChunk = 16; // columns of L per LDS stage
-__global__ __launch_bounds__(256) void trsm_small_kernel(const double *__restrict__ L, int64_t ldl,
-                                                         double *__restrict__ B, int64_t ldb, int nbk,
-                                                         int64_t ncols)
+// T = double (FP64 factorization, RPL = 4) or float (the mixed-precision
+// factorization's FP32 panel, RPL = 8).
+__device__ __forceinline__ double lane_value(double v, int l) { return read_lane(v, l); }
+__device__ __forceinline__ float lane_value(float v, int l)
 {
-    __shared__ double Lc[2][kSmChunk][64 * kSmRPL + 1];  // Lc[buf][kk][r] = L(r, chunk*16 + kk)
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+constexpr int kSmRPL = 4;    // rows per lane of the FP64 form (nbk <= 256)
+constexpr int kSmRPL32 = 8;  // rows per lane of the FP32 form (nbk <= 512)
+constexpr int kSmChunk = 16; // columns of L per LDS stage
+template <typename T, int kSmRPL>
+__global__ __launch_bounds__(256) void trsm_small_kernel(const T *__restrict__ L, int64_t ldl, T *__restrict__ B,
+                                                         int64_t ldb, int nbk, int64_t ncols)
+{
+    __shared__ T Lc[2][kSmChunk][64 * kSmRPL + 1];  // Lc[buf][kk][r] = L(r, chunk*16 + kk)
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t col = (int64_t)blockIdx.x * 4 + wave;
     const bool live = col < ncols;
-    double x[kSmRPL];
+    T x[kSmRPL];
 #pragma unroll
     for (int s = 0; s < kSmRPL; ++s) {
         const int r = lane + 64 * s;
-        x[s] = (live && r < nbk) ? B[off(r, col, ldb)] : 0.0;
+        x[s] = (live && r < nbk) ? B[off(r, col, ldb)] : (T)0;
     }
     const int nchunk = (nbk + kSmChunk - 1) / kSmChunk;
-    // each thread fetches 16 of the 16 x 256 chunk entries: column kk = t / 16, rows (t % 16) + 16e
-    double pre[kSmChunk];
+    // each thread fetches 4 RPL of the 16 x 64 RPL chunk entries: column kk = t / 16, rows (t % 16) + 16e
+    constexpr int kPre = 4 * kSmRPL;
+    T pre[kPre];
     auto fetch = [&](int ch) {
         const int kk = t >> 4, r0 = t & 15;
         const int gc = ch * kSmChunk + kk;
 #pragma unroll
-        for (int e = 0; e < kSmChunk; ++e) {
+        for (int e = 0; e < kPre; ++e) {
             const int r = r0 + 16 * e;
-            pre[e] = (gc < nbk && r < nbk) ? L[off(r, gc, ldl)] : 0.0;
+            pre[e] = (gc < nbk && r < nbk) ? L[off(r, gc, ldl)] : (T)0;
         }
     };
     auto stash = [&](int buf) {
         const int kk = t >> 4, r0 = t & 15;
 #pragma unroll
-        for (int e = 0; e < kSmChunk; ++e) Lc[buf][kk][r0 + 16 * e] = pre[e];
+        for (int e = 0; e < kPre; ++e) Lc[buf][kk][r0 + 16 * e] = pre[e];
     };
     fetch(0);
     stash(0);
@@ -199,11 +208,11 @@ __global__ __launch_bounds__(256) void trsm_small_kernel(const double *__restric
         for (int kk = 0; kk < kend; ++kk) {
             const int k = ch * kSmChunk + kk;
             const int sk = k >> 6, lk = k & 63;
-            double xs = x[0];
+            T xs = x[0];
 #pragma unroll
             for (int s = 1; s < kSmRPL; ++s)
                 if (sk == s) xs = x[s];
-            const double xk = read_lane(xs, lk);
+            const T xk = lane_value(xs, lk);
 #pragma unroll
             for (int s = 0; s < kSmRPL; ++s) {
                 const int r = lane + 64 * s;
@@ -230,7 +239,8 @@ int launch_trsm_llnu(const double *L, int64_t ldl, double *B, int64_t ldb, int64
     if (nbk <= 0 || ncols <= 0) return HPL_OK;
     if (nbk <= 64 * kSmRPL && ncols <= 4096) {
         const int64_t g = (ncols + 3) / 4;
-        hipLaunchKernelGGL(trsm_small_kernel, dim3((unsigned)g), dim3(256), 0, st, L, ldl, B, ldb, (int)nbk, ncols);
+        hipLaunchKernelGGL((trsm_small_kernel<double, kSmRPL>), dim3((unsigned)g), dim3(256), 0, st, L, ldl, B, ldb,
+                           (int)nbk, ncols);
         HPLX_TRY_LAUNCH();
         return HPL_OK;
     }
@@ -239,6 +249,23 @@ int launch_trsm_llnu(const double *L, int64_t ldl, double *B, int64_t ldb, int64
     if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
     hipLaunchKernelGGL(trsm_llnu_kernel, dim3((unsigned)g), dim3(kTrWaves * 64), 0, st, L, ldl, B, ldb, (int)nbk,
                        ncols);
+    HPLX_TRY_LAUNCH();
+    return HPL_OK;
+}
+
+bool trsm32_small_ok(int64_t nbk, int64_t ncols)
+{
+    return nbk > 0 && nbk <= 64 * kSmRPL32 && ncols <= 4096;
+}
+
+int launch_trsm32_small(const float *L, int64_t ldl, float *B, int64_t ldb, int64_t nbk, int64_t ncols,
+                        hipStream_t st)
+{
+    if (nbk <= 0 || ncols <= 0) return HPL_OK;
+    if (!trsm32_small_ok(nbk, ncols)) return HPL_ERR_INTERNAL;
+    const int64_t g = (ncols + 3) / 4;
+    hipLaunchKernelGGL((trsm_small_kernel<float, kSmRPL32>), dim3((unsigned)g), dim3(256), 0, st, L, ldl, B, ldb,
+                       (int)nbk, ncols);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
