@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = "HPL TFLOP/s (2N³/3+2N²) & % FP64 MFMA peak; MxP+IR speed-up at FP64 residual"
 PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X datasheet, dense FP64 matrix
 PEAK_HBM_GBS = 8000.0
+PEAK_FP16_MFMA_TFLOPS = 2500.0   # MI355X datasheet, dense FP16/BF16 matrix (no sparsity)
 PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X, FP64 vector (256 CUs x 128 flop/clk x 2.4 GHz); FP64 MFMA is rated the same
 
 # HBM bytes per trailing-GEMM launch measured with rocprofv3 FETCH_SIZE and
@@ -293,6 +294,20 @@ def bench_mxp(args, torch, h):
                      "effective_tflops": round(flops / (sum(ts) / len(ts)) / 1e12, 2)}
     g = gemm_stats["mxp_gemm"]
     f = gemm_stats["mxp_fact"]
+    # the updates' bound: their arithmetic intensity (algorithmic flops per
+    # algorithmic byte, over all launches) against the ridge point peak FP16
+    # flop/s / peak HBM byte/s = 312.5; the joint updates of two panels (k =
+    # 2 NB = 2048: 512 flop/B) are above it, single-panel ones (256) below
+    ai = g["flops"] / g["bytes"] if g["bytes"] else 0.0
+    ridge = PEAK_FP16_MFMA_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    gbs = g["bytes"] / (g["ms"] * 1e-3) / 1e9 if g["ms"] else None
+    tfs = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] else None
+    if ai >= ridge:
+        rl = {"bound": "mfma", "achieved": round(tfs, 2) if tfs else None, "peak": PEAK_FP16_MFMA_TFLOPS,
+              "unit": "TFLOP/s", "frac": round(tfs / PEAK_FP16_MFMA_TFLOPS, 4) if tfs else None}
+    else:
+        rl = {"bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": PEAK_HBM_GBS,
+              "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4) if gbs else None}
     out = {
         "metric": "HPL-MxP: speed-up of FP16 LU + FP64 refinement over the FP64 path, to FP64 residual < 16",
         "value": res["fp16"]["speedup_vs_fp64"],
@@ -317,14 +332,13 @@ def bench_mxp(args, torch, h):
         },
         "roofline": {
             "kernel": "hgemm256_update_kernel (256x128 tiles) and hgemm_update_kernel (128x128, small updates): A22 += (-L21) U12, FP16 MFMA, FP32 C",
-            "bound": "hbm",
-            "achieved": round(g["bytes"] / (g["ms"] * 1e-3) / 1e9, 1) if g["ms"] else None,
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": round(g["bytes"] / (g["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if g["ms"] else None,
+            **rl,
+            "arithmetic_intensity": round(ai, 1),
+            "hbm_gbs": round(gbs, 1) if gbs else None,
+            "hbm_frac": round(gbs / PEAK_HBM_GBS, 4) if gbs else None,
+            "tflops": round(tfs, 2) if tfs else None,
             "launches": g["launches"],
             "avg_launch_ms": round(g["ms"] / g["launches"], 4) if g["launches"] else None,
-            "tflops": round(g["flops"] / (g["ms"] * 1e-3) / 1e12, 2) if g["ms"] else None,
             "traffic": None,
         },
     }

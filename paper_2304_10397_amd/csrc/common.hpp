@@ -293,10 +293,14 @@ int launch_sgemm32(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
                    float *C, int64_t ldc, hipStream_t st);
 int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols, int w,
                      unsigned *mx, int *sexp, hipStream_t st);
+// -L21 and U12 scaled and rounded into the blocked low-precision layout (1 KB
+// blocks of 16 rows x 32 k, ordered by k slab then 16-row group; sa, sb = slab
+// strides in elements, multiples of 512; A16 and B16 point at the block of
+// the first row and k).
 int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols,
-                       int w, const int *sexp, void *A16, void *B16, hipStream_t st);
-int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, const void *B16, float *C,
-                        int64_t ldc, hipStream_t st);
+                       int w, const int *sexp, void *A16, int64_t sa, void *B16, int64_t sb, hipStream_t st);
+int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, int64_t sa, const void *B16,
+                        int64_t sb, float *C, int64_t ldc, hipStream_t st);
 // r = b - A x with kResSplit column chunks; part holds 2 kResSplit n doubles of partial sums.
 constexpr int kResSplit = 16;
 int launch_mxp_residual(const double *A, int64_t lda, const double *x, const double *b, double *r, int64_t n,

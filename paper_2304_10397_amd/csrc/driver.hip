@@ -117,6 +117,7 @@ struct Device {
     hipStream_t sp = nullptr;  // panel stream (non-blocking)
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
     hipEvent_t ev_panel[kRing] = {}, ev_la[kRing] = {}, ev_iter[kRing] = {};
+    hipEvent_t ev_mxp[5] = {};          // mixed precision look-ahead: main -> panel stream (4), back (1)
     void *ws = nullptr;
     LeafSync sync{};
     unsigned long long bar_epoch = 0;
@@ -210,6 +211,7 @@ static int init_device(Device &d, int id)
         HPLX_TRY(hipEventCreateWithFlags(&d.ev_la[i], hipEventDisableTiming));
         HPLX_TRY(hipEventCreateWithFlags(&d.ev_iter[i], hipEventDisableTiming));
     }
+    for (hipEvent_t &e : d.ev_mxp) HPLX_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // one workspace block: sync words, leaf slots, interchange plans
     const size_t plan_bytes = align_up(2 * kMaxSwaps * sizeof(int32_t), 256) * 2 + 256;
     size_t o = 0;
@@ -670,30 +672,42 @@ static int mxp_panel(float *A, int64_t lda, int64_t n, int64_t c, int64_t w, uns
     return mxp_panel(A, lda, n, c + w1, w2, info, done, st);
 }
 
-// One step of the mixed-precision factorization is FACT of the panel (FP32),
-// U12 = L11^{-1} A12 (FP32), the scaling and conversion of -L21 and U12 to
-// FP16/BF16, and A22 += (-L21) U12 on the matrix cores.  With look-ahead
-// (Sec. III) the update of step j first does the next panel's columns, then the
-// next panel's rows, then the rest.  The panel stream factors the next panel
-// as soon as its columns are updated, and computes its U12 and low-precision
-// copies (into the second of two buffers) as soon as its rows are, both beside
-// the bulk of the update; step j+1 starts when both streams are done.  Every
-// element takes the same operations in the same order either way, so the
-// factors are bitwise equal.
+// The mixed-precision factorization takes the panels in pairs P, Q (columns
+// [c, c+nb) and [c+nb, c+2nb)).  Per panel: FACT (FP32), U12 = L11^{-1} A12
+// (FP32), the scaling and conversion of -L21 and U12 to FP16/BF16.  Between
+// the two panels of a pair, P's update reaches only Q's columns and Q's rows;
+// the rest of the trailing matrix takes the update of both panels at once,
+// A22 += [-L21(P) -L21(Q)] [U12(P); U12(Q)] with k = 2 nb: the FP32 trailing
+// matrix is read and written once per two panels instead of once per panel
+// (the same products; only the FP32 sum of the two updates is rounded once
+// more before it meets A22).  The operand copies of P and Q sit side by side
+// in k in one buffer, indexed from the first row (column) below (right of) P.
+//
+// With look-ahead (Sec. III) the pair's joint update does, in order, the next
+// pair's P columns, its P rows, its Q columns, its Q rows, then the rest; the
+// panel stream factors the next P as soon as its columns are done, and so on
+// (FACT, U12 and copies of P into the second buffer, P's update of Q's
+// columns, FACT of Q, P's update of Q's rows, U12 and copies of Q), each step
+// as soon as its region is done, all beside the bulk of the joint update; the
+// next pair starts when both streams are done.  Every element takes the same
+// operations in the same order either way (the two update kernels round
+// alike), so the factors are bitwise equal.
 static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU,
                            int64_t ldlu, int64_t *info, hipStream_t st)
 {
     const bool la = opt_lookahead.load() != 0 && opt_serialize.load() == 0 && n > nb;
-    const size_t half_bytes = (sizeof(uint16_t) * (size_t)n * (size_t)nb + 255) / 256 * 256;
+    // a buffer holds 2 nb slabs of k for rows (columns) 0 .. n-1 below P
+    const int64_t ss = (n + 15) / 16 * 512;  // slab stride, elements
+    const size_t half_bytes = (sizeof(uint16_t) * (size_t)ss * (size_t)(2 * nb / 32) + 255) / 256 * 256;
     const int nbuf = la ? 2 : 1;
     const size_t sc_off = 2 * (size_t)nbuf * half_bytes;
     HPLX_PROPAGATE(ensure_mxp_ws(d, sc_off + 256));
     char *ws = (char *)d->mxp_ws;
-    void *A16[2], *B16[2];
+    uint16_t *A16[2], *B16[2];
     for (int q = 0; q < 2; ++q) {
         const int qq = q < nbuf ? q : 0;
-        A16[q] = ws + 2 * (size_t)qq * half_bytes;
-        B16[q] = ws + (2 * (size_t)qq + 1) * half_bytes;
+        A16[q] = (uint16_t *)(ws + 2 * (size_t)qq * half_bytes);
+        B16[q] = (uint16_t *)(ws + (2 * (size_t)qq + 1) * half_bytes);
     }
     unsigned *mx = (unsigned *)(ws + sc_off);
     int *sexp = (int *)(ws + sc_off + 16);
@@ -707,58 +721,83 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c, w, dinfo, leaf_done, s));
         return tm.end(id, s, (double)(n - c) * (double)w * (double)w, 4.0 * (double)(n - c) * (double)w * 2.0);
     };
-    // U12 of the panel at c and the low-precision copies of -L21 and U12 into buffer q, on stream s
-    auto prep = [&](int64_t c, int64_t w, int q, hipStream_t s) -> int {
-        const int64_t c1 = c + w, m = n - c1;
+    // U12 of the panel at c (width nb) and the low-precision copies of -L21 and
+    // U12 into buffer q, rows (columns) from index off and k from kh nb, on s
+    auto prep = [&](int64_t c, int q, int64_t idx, int kh, hipStream_t s) -> int {
+        const int64_t c1 = c + nb, m = n - c1;
+        const size_t o = (size_t)kh * (size_t)(nb / 32) * (size_t)ss + (size_t)(idx / 16) * 512;
         const int id = tm.begin(ST_MXP_FACT, s);
-        HPLX_PROPAGATE(mxp_trsm(LU + off(c, c, ldlu), ldlu, w, LU + off(c, c1, ldlu), ldlu, m, s));
-        HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)w, mx,
+        HPLX_PROPAGATE(mxp_trsm(LU + off(c, c, ldlu), ldlu, nb, LU + off(c, c1, ldlu), ldlu, m, s));
+        HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)nb, mx,
                                         sexp, s));
-        HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)w,
-                                          sexp, A16[q], B16[q], s));
-        return tm.end(id, s, (double)w * (double)w * (double)m, 4.0 * (double)w * (double)m * 2.0);
+        HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)nb,
+                                          sexp, A16[q] + o, ss, B16[q] + o, ss, s));
+        return tm.end(id, s, (double)nb * (double)nb * (double)m, 4.0 * (double)nb * (double)m * 2.0);
     };
-    // A22 rows [c1 + i0, c1 + i0 + ni) x columns [c1 + j0, c1 + j0 + nc) += (-L21) U12 of the
-    // panel ending at c1 (width w), from buffer q, on the main stream
-    auto update = [&](int64_t c1, int64_t w, int q, int64_t i0, int64_t ni, int64_t j0, int64_t nc) -> int {
-        const int id = tm.begin(ST_MXP_GEMM, st);
-        HPLX_PROPAGATE(launch_hgemm_update(fmt, ni, nc, w, (const uint16_t *)A16[q] + (size_t)i0 * (size_t)w,
-                                           (const uint16_t *)B16[q] + (size_t)j0 * (size_t)w,
-                                           LU + off(c1 + i0, c1 + j0, ldlu), ldlu, st));
-        return tm.end(id, st, 2.0 * (double)ni * (double)nc * (double)w,
-                      8.0 * (double)ni * (double)nc + 2.0 * (double)w * (double)(ni + nc));
+    // A22 rows [b0 + i0, b0 + i0 + ni) x columns [b0 + j0, b0 + j0 + nc) += the
+    // product of k = K of buffer q (b0 = the first row below the pair's P), on s
+    auto update = [&](int64_t b0, int q, int64_t i0, int64_t ni, int64_t j0, int64_t nc, int64_t K,
+                      hipStream_t s) -> int {
+        if (ni <= 0 || nc <= 0) return HPL_OK;
+        const int id = tm.begin(ST_MXP_GEMM, s);
+        HPLX_PROPAGATE(launch_hgemm_update(fmt, ni, nc, K, A16[q] + (size_t)(i0 / 16) * 512, ss,
+                                           B16[q] + (size_t)(j0 / 16) * 512, ss, LU + off(b0 + i0, b0 + j0, ldlu),
+                                           ldlu, s));
+        return tm.end(id, s, 2.0 * (double)ni * (double)nc * (double)K,
+                      8.0 * (double)ni * (double)nc + 2.0 * (double)K * (double)(ni + nc));
+    };
+    // the panel work of the pair at c into buffer q, on stream s; with
+    // look-ahead each step first waits for its region of the previous joint
+    // update (events recorded on the main stream by the caller)
+    auto pair_panels = [&](int64_t c, int q, hipStream_t s, hipEvent_t *ev) -> int {
+        const int64_t b0 = c + nb, m1 = n - b0;
+        const int64_t wq = m1 < nb ? m1 : nb;
+        if (ev) HPLX_TRY(hipStreamWaitEvent(s, ev[1], 0));
+        HPLX_PROPAGATE(prep(c, q, 0, 0, s));
+        if (ev) HPLX_TRY(hipStreamWaitEvent(s, ev[2], 0));
+        HPLX_PROPAGATE(update(b0, q, 0, m1, 0, wq, nb, s));  // P's update of Q's columns
+        HPLX_PROPAGATE(fact(b0, wq, s));
+        if (m1 == wq) return HPL_OK;                         // Q is the last panel
+        if (ev) HPLX_TRY(hipStreamWaitEvent(s, ev[3], 0));
+        HPLX_PROPAGATE(update(b0, q, 0, wq, wq, m1 - wq, nb, s));  // P's update of Q's rows
+        return prep(b0, q, nb, 1, s);
     };
     HPLX_PROPAGATE(launch_fill_u64(dinfo, 1, ULLONG_MAX, st));
     HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)leaf_done, 1, 0ull, st));
     HPLX_PROPAGATE(launch_cvt_f64_f32(A, lda, LU, ldlu, n, n, st));
     HPLX_PROPAGATE(fact(0, nb < n ? nb : n, st));
     int cur = 0;
-    if (nb < n) HPLX_PROPAGATE(prep(0, nb, cur, st));
-    for (int64_t c0 = 0; c0 < n; c0 += nb) {
-        const int64_t w = (n - c0) < nb ? (n - c0) : nb;
-        const int64_t c1 = c0 + w;
-        if (c1 >= n) break;
-        const int64_t m = n - c1;
-        const int64_t w2 = m < nb ? m : nb;  // width of the next panel
-        const int r = (int)((c0 / nb) % kRing);
-        if (la) {
-            HPLX_PROPAGATE(update(c1, w, cur, 0, m, 0, w2));
-            HPLX_TRY(hipEventRecord(d->ev_la[r], st));
-            HPLX_TRY(hipStreamWaitEvent(sp, d->ev_la[r], 0));
-            HPLX_PROPAGATE(fact(c1, w2, sp));
-            if (m > w2) {
-                HPLX_PROPAGATE(update(c1, w, cur, 0, w2, w2, m - w2));
-                HPLX_TRY(hipEventRecord(d->ev_iter[r], st));
-                HPLX_TRY(hipStreamWaitEvent(sp, d->ev_iter[r], 0));
-                HPLX_PROPAGATE(prep(c1, w2, cur ^ 1, sp));
-                HPLX_PROPAGATE(update(c1, w, cur, w2, m - w2, w2, m - w2));
-            }
-            HPLX_TRY(hipEventRecord(d->ev_panel[r], sp));
-            HPLX_TRY(hipStreamWaitEvent(st, d->ev_panel[r], 0));
+    if (nb < n) HPLX_PROPAGATE(pair_panels(0, cur, st, nullptr));
+    for (int64_t c = 0; c + 2 * nb < n; c += 2 * nb) {
+        // the pair at c is factored and its copies are in buffer cur; the joint
+        // update covers rows and columns [c2, n), c2 = c + 2 nb, the next P
+        const int64_t b0 = c + nb, c2 = c + 2 * nb, m2 = n - c2;
+        const int64_t wp = m2 < nb ? m2 : nb;
+        const int64_t K = 2 * nb;
+        if (!la) {
+            HPLX_PROPAGATE(update(b0, cur, nb, m2, nb, m2, K, st));
+            HPLX_PROPAGATE(fact(c2, wp, st));
+            if (m2 > wp) HPLX_PROPAGATE(pair_panels(c2, cur ^ 1, st, nullptr));
         } else {
-            HPLX_PROPAGATE(update(c1, w, cur, 0, m, 0, m));
-            HPLX_PROPAGATE(fact(c1, w2, st));
-            if (m > w2) HPLX_PROPAGATE(prep(c1, w2, cur ^ 1, st));
+            hipEvent_t *ev = d->ev_mxp;
+            const int64_t wq = (m2 - wp) < nb ? (m2 - wp) : nb;  // next Q (0: none)
+            HPLX_PROPAGATE(update(b0, cur, nb, m2, nb, wp, K, st));  // next P's columns
+            HPLX_TRY(hipEventRecord(ev[0], st));
+            HPLX_TRY(hipStreamWaitEvent(sp, ev[0], 0));
+            HPLX_PROPAGATE(fact(c2, wp, sp));
+            if (wq > 0) {
+                HPLX_PROPAGATE(update(b0, cur, nb, wp, nb + wp, m2 - wp, K, st));  // next P's rows
+                HPLX_TRY(hipEventRecord(ev[1], st));
+                HPLX_PROPAGATE(update(b0, cur, nb + wp, m2 - wp, nb + wp, wq, K, st));  // next Q's columns
+                HPLX_TRY(hipEventRecord(ev[2], st));
+                HPLX_PROPAGATE(update(b0, cur, nb + wp, wq, nb + wp + wq, m2 - wp - wq, K, st));  // next Q's rows
+                HPLX_TRY(hipEventRecord(ev[3], st));
+                HPLX_PROPAGATE(pair_panels(c2, cur ^ 1, sp, ev));
+                // the rest
+                HPLX_PROPAGATE(update(b0, cur, nb + wp + wq, m2 - wp - wq, nb + wp + wq, m2 - wp - wq, K, st));
+            }
+            HPLX_TRY(hipEventRecord(ev[4], sp));
+            HPLX_TRY(hipStreamWaitEvent(st, ev[4], 0));
         }
         cur ^= 1;
     }
@@ -1416,6 +1455,7 @@ int hpl_release(void)
             (void)hipEventDestroy(d.ev_la[r]);
             (void)hipEventDestroy(d.ev_iter[r]);
         }
+        for (hipEvent_t e : d.ev_mxp) (void)hipEventDestroy(e);
         (void)hipEventDestroy(d.ev_start);
         (void)hipEventDestroy(d.ev_end);
         (void)hipStreamDestroy(d.sp);

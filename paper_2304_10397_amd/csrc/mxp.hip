@@ -333,11 +333,26 @@ template <int FMT> struct Half;
 template <> struct Half<0> { typedef _Float16 T; };
 template <> struct Half<1> { typedef __bf16 T; };
 
-// L21 (m x w at ld) -> A16 row-major m x w (k contiguous): -(2^s l) rounded.
+// Layout of the low-precision operands.  Both are stored as rows of k (a row
+// of A16 is a row of -L21, a row of B16 a column of U12) in 1 KB blocks of 16
+// rows x 32 k, row r of a block at 64 r bytes; the blocks are ordered by k
+// slab, then by 16-row group:
+//     element (i, k) at  (k / 32) * ss + (i / 16) * 512 + (i % 16) * 32 + k % 32
+// with ss the slab stride in elements (a multiple of 512).  One 32-k stage of
+// a tile is then a run of whole 1 KB blocks, each moved by one 64-lane
+// 16-byte load, and the operands of two panels sit side by side in k (panel 2
+// in the slabs after panel 1's), so that one update can take both.
+__device__ __forceinline__ size_t blk_index(int64_t i, int64_t k, int64_t ss)
+{
+    return (size_t)(k >> 5) * (size_t)ss + (size_t)(i >> 4) * 512 + (size_t)((i & 15) * 32 + (k & 31));
+}
+
+// L21 (m x w at ld) -> A16 (blocked, slab stride ss): -(2^s l) rounded.
 // A 64 x 64 tile goes through LDS: read down the columns, written along rows.
 template <int FMT>
 __global__ __launch_bounds__(256) void cvt_l_kernel(const float *__restrict__ L, int64_t ld, int64_t m, int w,
-                                                    const int *__restrict__ sexp, typename Half<FMT>::T *__restrict__ O)
+                                                    const int *__restrict__ sexp, typename Half<FMT>::T *__restrict__ O,
+                                                    int64_t ss)
 {
     __shared__ float tile[64][65];
     const int64_t i0 = (int64_t)blockIdx.x * 64;
@@ -351,30 +366,37 @@ __global__ __launch_bounds__(256) void cvt_l_kernel(const float *__restrict__ L,
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int q = e % 64, r = e / 64;
         if (i0 + r < m && k0 + q < w)
-            O[(size_t)(i0 + r) * (size_t)w + k0 + q] = (typename Half<FMT>::T)(-ldexpf(tile[r][q], s));
+            O[blk_index(i0 + r, k0 + q, ss)] = (typename Half<FMT>::T)(-ldexpf(tile[r][q], s));
     }
 }
 
-// U12 (w x n at ld) -> B16 column-major w x n (ld w): 2^-s u rounded
+// U12 (w x n at ld) -> B16 (blocked, slab stride ss; row j of B16 is column j
+// of U12): 2^-s u rounded.  Each 512 consecutive threads fill one block: reads
+// of 32 consecutive k of a column, the block written whole.
 template <int FMT>
 __global__ __launch_bounds__(256) void cvt_u_kernel(const float *__restrict__ U, int64_t ld, int w, int64_t n,
-                                                    const int *__restrict__ sexp, typename Half<FMT>::T *__restrict__ O)
+                                                    const int *__restrict__ sexp, typename Half<FMT>::T *__restrict__ O,
+                                                    int64_t ss)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)w * n) return;
-    const int64_t j = e / w, k = e - j * w;
-    O[e] = (typename Half<FMT>::T)ldexpf(U[off(k, j, ld)], -*sexp);
+    const int64_t nbj = (n + 15) / 16;  // 16-column groups
+    const int64_t blk = e >> 9, kb = blk / nbj, jb = blk - kb * nbj;
+    const int within = (int)(e & 511);
+    const int64_t j = jb * 16 + (within >> 5), k = kb * 32 + (within & 31);
+    if (kb * 32 >= w || j >= n || k >= w) return;
+    O[(size_t)kb * (size_t)ss + (size_t)jb * 512 + within] = (typename Half<FMT>::T)ldexpf(U[off(k, j, ld)], -*sexp);
 }
 
 // ---------------------------------------------------------------------------
-// Trailing update on the matrix cores: C (FP32, column-major) += A16 B16,
-// A16 m x K row-major (k contiguous), B16 K x n column-major (k contiguous).
+// Trailing update on the matrix cores: C (FP32, column-major) += A16 B16^T,
+// A16 (m rows) and B16 (n rows) blocked with slab strides sa and sb.
 // Tile 128 x 128, 4 waves of 64 x 64 (4 x 4 blocks of 16 x 16); K staged 64 at
-// a time through double-buffered LDS (rows padded by 8 halves).  The
-// accumulators start from C.  B's fragment is the MFMA's first operand, so a
-// block comes out transposed: register r of lane l holds
-// C(16R + l%16, 16G + 4(l/16) + r) -- 16 consecutive rows of 4 columns.
-// Requires K % 64 == 0.
+// a time through double-buffered LDS (rows padded by 8 halves).  B's fragment
+// is the MFMA's first operand, so a block comes out transposed: register r of
+// lane l holds C(16R + l%16, 16G + 4(l/16) + r) -- 16 consecutive rows of 4
+// columns.  The accumulators start at zero and C is added once at the end, as
+// in the 256 x 128 kernel: the two take the same MFMAs in the same k order, so
+// an element gets the same bits from either.  Requires K % 64 == 0.
 // ---------------------------------------------------------------------------
 constexpr int kHBM = 128, kHBN = 128, kHBK = 64, kHPad = 8;
 constexpr int64_t kHGroupM = 8;  // tile-rows per group of the XCD-aware order
@@ -382,8 +404,10 @@ constexpr int64_t kHGroupM = 8;  // tile-rows per group of the XCD-aware order
 template <int FMT>
 __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t n, int64_t K,
                                                               const typename Half<FMT>::T *__restrict__ A16,
+                                                              int64_t sa,
                                                               const typename Half<FMT>::T *__restrict__ B16,
-                                                              float *__restrict__ C, int64_t ldc, int64_t tiles_m)
+                                                              int64_t sb, float *__restrict__ C, int64_t ldc,
+                                                              int64_t tiles_m)
 {
     typedef typename Half<FMT>::T H;
     typedef H h8 __attribute__((ext_vector_type(8)));
@@ -402,33 +426,14 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 15, lg = lane >> 4;
 
-    // accumulators from C: acc[R][G][r] = C(m0 + 64wm + 16R + li, n0 + 64wn + 16G + 4lg + r).
-    // A tile inside the matrix (all but the last row and column of tiles)
-    // reads each column's four rows 16 R apart from one address with
-    // immediate offsets and no tests; an edge tile tests every element.
+    // acc[R][G][r]: the update of C(m0 + 64wm + 16R + li, n0 + 64wn + 16G + 4lg + r)
     f4 acc[4][4];
+#pragma unroll
+    for (int R = 0; R < 4; ++R)
+#pragma unroll
+        for (int G = 0; G < 4; ++G) acc[R][G] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
     const int64_t rbase = m0 + 64 * wm + li, cbase = n0 + 64 * wn + 4 * lg;
     const bool inner = m0 + kHBM <= m && n0 + kHBN <= n;  // uniform
-    if (inner) {
-#pragma unroll
-        for (int G = 0; G < 4; ++G)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float *col = C + off(rbase, cbase + 16 * G + r, ldc);
-#pragma unroll
-                for (int R = 0; R < 4; ++R) acc[R][G][r] = col[16 * R];
-            }
-    } else {
-#pragma unroll
-        for (int R = 0; R < 4; ++R)
-#pragma unroll
-            for (int G = 0; G < 4; ++G)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
-                    acc[R][G][r] = (i < m && j < n) ? C[off(i, j, ldc)] : 0.0f;
-                }
-    }
 
     // global -> register staging: A tile 128 x 64 halves = 1024 x 16 B, 4 per thread
     u4 ra[4], rb[4];
@@ -438,8 +443,8 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
             const int e = t + 256 * q;           // 16-byte unit
             const int row = e >> 3, kk = (e & 7) * 8;
             const int64_t gi = m0 + row, gj = n0 + row;
-            ra[q] = (gi < m) ? *(const u4 *)(A16 + (size_t)gi * (size_t)K + k0 + kk) : (u4){0, 0, 0, 0};
-            rb[q] = (gj < n) ? *(const u4 *)(B16 + (size_t)gj * (size_t)K + k0 + kk) : (u4){0, 0, 0, 0};
+            ra[q] = (gi < m) ? *(const u4 *)(A16 + blk_index(gi, k0 + kk, sa)) : (u4){0, 0, 0, 0};
+            rb[q] = (gj < n) ? *(const u4 *)(B16 + blk_index(gj, k0 + kk, sb)) : (u4){0, 0, 0, 0};
         }
     };
     auto store = [&](int buf) {
@@ -478,6 +483,9 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
         if (s + 1 < nst) store(buf ^ 1);
         __syncthreads();
     }
+    // C += acc: an inner tile (all but the last row and column of tiles)
+    // reads and writes each column's four rows from one address with
+    // immediate offsets; an edge tile tests every element
     if (inner) {
 #pragma unroll
         for (int G = 0; G < 4; ++G)
@@ -485,7 +493,7 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
             for (int r = 0; r < 4; ++r) {
                 float *col = C + off(rbase, cbase + 16 * G + r, ldc);
 #pragma unroll
-                for (int R = 0; R < 4; ++R) col[16 * R] = acc[R][G][r];
+                for (int R = 0; R < 4; ++R) col[16 * R] += acc[R][G][r];
             }
     } else {
 #pragma unroll
@@ -495,7 +503,7 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t i = rbase + 16 * R, j = cbase + 16 * G + r;
-                    if (i < m && j < n) C[off(i, j, ldc)] = acc[R][G][r];
+                    if (i < m && j < n) C[off(i, j, ldc)] += acc[R][G][r];
                 }
     }
 }
@@ -513,16 +521,17 @@ __global__ __launch_bounds__(256, 2) void hgemm_update_kernel(int64_t m, int64_t
 //    24 KB, filled by global_load_lds_dwordx4 (64 lanes x 16 bytes straight
 //    into LDS, no staging registers) two stages ahead; two workgroups per CU,
 //    so four stages per CU are in flight while two are computed;
+//  * each DMA instruction moves one 1 KB block of the blocked operand layout
+//    (16 rows x 32 k, contiguous in memory);
 //  * A (and B) sit in LDS as 16-byte units, row r's 4 units (8 k each) in the
 //    order s ^ ((r >> 1) & 3): the fragment reads (16 rows x 8 k per lane
 //    group) then touch all banks once per 8 lanes.  The DMA takes its swizzle
-//    from the lane -> global address map;
+//    from the lane -> global address map (a permutation within the block);
 //  * the accumulators start at zero and C is added once at the end (read into
 //    the accumulators up front, C would leave the compiler's waits for those
 //    loads inside the k-loop, where -- blind to the DMA of the inline assembly
-//    -- they would also drain the stages in flight).  The 128 x 128 kernel
-//    starts from C: the two round differently.
-// Requires K % 32 == 0 and K <= 2^20 (32-bit DMA offsets).
+//    -- they would also drain the stages in flight).
+// Requires K % 32 == 0.
 // ---------------------------------------------------------------------------
 constexpr int kH2M = 256, kH2N = 128, kH2K = 32, kH2S = 3;
 constexpr int kH2AInst = kH2M / 16 / 4;  // A DMA instructions per wave per stage (16 rows each)
@@ -533,9 +542,10 @@ constexpr int kH2BInst = kH2N / 16 / 4;  // B DMA instructions per wave per stag
 template <int FMT>
 __global__ __launch_bounds__(256, 2) void hgemm256_update_kernel(int64_t m, int64_t n, int64_t K,
                                                                  const typename Half<FMT>::T *__restrict__ A16,
+                                                                 int64_t sa,
                                                                  const typename Half<FMT>::T *__restrict__ B16,
-                                                                 float *__restrict__ C, int64_t ldc, int64_t tiles_m,
-                                                                 int64_t tiles_n)
+                                                                 int64_t sb, float *__restrict__ C, int64_t ldc,
+                                                                 int64_t tiles_m, int64_t tiles_n)
 {
     typedef typename Half<FMT>::T H;
     typedef H h8 __attribute__((ext_vector_type(8)));
@@ -553,30 +563,31 @@ __global__ __launch_bounds__(256, 2) void hgemm256_update_kernel(int64_t m, int6
 
     // DMA map: instruction q of an operand stage fills LDS units 64q .. 64q+63;
     // lane i writes unit u = 64q + i = 4r + (s ^ ((r >> 1) & 3)), so it loads
-    // row r = 16q + i/4, k segment s = (i & 3) ^ ((r >> 1) & 3).  Rows
-    // (columns) past the matrix are clamped to the last one.
+    // row r = 16q + i/4, k segment s = (i & 3) ^ ((r >> 1) & 3): 16 bytes of
+    // the block of rows 16q .. 16q+15 of the stage's slab.  Rows (columns)
+    // past the matrix are clamped to the last one.
     uint32_t a_off[kH2AInst], b_off[kH2BInst];
 #pragma unroll
     for (int q = 0; q < kH2AInst; ++q) {
         const int r = 16 * (kH2AInst * wave + q) + (lane >> 2);
         const int sg = (lane & 3) ^ ((r >> 1) & 3);
         const int64_t rc = (m0 + r < m) ? r : (m - 1 - m0);
-        a_off[q] = (uint32_t)(rc * K + 8 * sg) * 2u;
+        a_off[q] = (uint32_t)((rc >> 4) * 512 + (rc & 15) * 32 + 8 * sg) * 2u;
     }
 #pragma unroll
     for (int q = 0; q < kH2BInst; ++q) {
         const int r = 16 * (kH2BInst * wave + q) + (lane >> 2);
         const int sg = (lane & 3) ^ ((r >> 1) & 3);
         const int64_t rc = (n0 + r < n) ? r : (n - 1 - n0);
-        b_off[q] = (uint32_t)(rc * K + 8 * sg) * 2u;
+        b_off[q] = (uint32_t)((rc >> 4) * 512 + (rc & 15) * 32 + 8 * sg) * 2u;
     }
-    const char *a_tile = (const char *)(A16 + (size_t)m0 * (size_t)K);
-    const char *b_tile = (const char *)(B16 + (size_t)n0 * (size_t)K);
+    const char *a_tile = (const char *)(A16 + (size_t)(m0 >> 4) * 512);
+    const char *b_tile = (const char *)(B16 + (size_t)(n0 >> 4) * 512);
     const uint32_t lds_a = (uint32_t)(uintptr_t)HPLX_LDS3(&As[0][0]);
     const uint32_t lds_b = (uint32_t)(uintptr_t)HPLX_LDS3(&Bs[0][0]);
     auto dma_stage = [&](int st, int buf) __attribute__((always_inline)) {
-        const char *asrc = a_tile + (size_t)st * kH2K * 2;
-        const char *bsrc = b_tile + (size_t)st * kH2K * 2;
+        const char *asrc = a_tile + (size_t)st * (size_t)sa * 2;
+        const char *bsrc = b_tile + (size_t)st * (size_t)sb * 2;
 #pragma unroll
         for (int q = 0; q < kH2AInst; ++q) {
             const uint32_t dst = lds_a + 2u * (uint32_t)(buf * kH2M * kH2K) + 1024u * (uint32_t)(kH2AInst * wave + q);
@@ -833,44 +844,46 @@ int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int
 }
 
 int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols,
-                       int w, const int *sexp, void *A16, void *B16, hipStream_t st)
+                       int w, const int *sexp, void *A16, int64_t sa, void *B16, int64_t sb, hipStream_t st)
 {
-    const int64_t gl = blocks_of(m, 64), gk = blocks_of(w, 64), gu = blocks_of((int64_t)w * ncols, 256);
+    if (w % 32 || sa % 512 || sb % 512) return HPL_ERR_INTERNAL;
+    const int64_t gl = blocks_of(m, 64), gk = blocks_of(w, 64);
+    const int64_t gu = blocks_of((int64_t)(w / 32) * blocks_of(ncols, 16) * 512, 256);
     if (gu > 0x7fffffffll || gl > 0x7fffffffll) return HPL_ERR_INTERNAL;
     if (fmt == 0) {
         hipLaunchKernelGGL(cvt_l_kernel<0>, dim3((unsigned)gl, (unsigned)gk), dim3(256), 0, st, L, ldl, m, w, sexp,
-                           (_Float16 *)A16);
+                           (_Float16 *)A16, sa);
         HPLX_TRY_LAUNCH();
         hipLaunchKernelGGL(cvt_u_kernel<0>, dim3((unsigned)gu), dim3(256), 0, st, U, ldu, w, ncols, sexp,
-                           (_Float16 *)B16);
+                           (_Float16 *)B16, sb);
     } else {
         hipLaunchKernelGGL(cvt_l_kernel<1>, dim3((unsigned)gl, (unsigned)gk), dim3(256), 0, st, L, ldl, m, w, sexp,
-                           (__bf16 *)A16);
+                           (__bf16 *)A16, sa);
         HPLX_TRY_LAUNCH();
         hipLaunchKernelGGL(cvt_u_kernel<1>, dim3((unsigned)gu), dim3(256), 0, st, U, ldu, w, ncols, sexp,
-                           (__bf16 *)B16);
+                           (__bf16 *)B16, sb);
     }
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
 
-int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, const void *B16, float *C,
-                        int64_t ldc, hipStream_t st)
+int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, int64_t sa, const void *B16,
+                        int64_t sb, float *C, int64_t ldc, hipStream_t st)
 {
     if (m <= 0 || n <= 0 || K <= 0) return HPL_OK;
-    if (K % kHBK) return HPL_ERR_INTERNAL;
+    if (K % kHBK || sa % 512 || sb % 512) return HPL_ERR_INTERNAL;
     // large updates on 256 x 128 tiles (at least two tiles per CU), the rest
-    // on 128 x 128
+    // on 128 x 128; an element gets the same bits from either
     const int64_t t2m = blocks_of(m, kH2M), t2n = blocks_of(n, kH2N);
-    if (t2m * t2n >= 512 && K % kH2K == 0 && K <= (1 << 20)) {
+    if (t2m * t2n >= 512 && K % kH2K == 0) {
         const int64_t g2 = t2m * t2n;
         if (g2 > 0x7fffffffll) return HPL_ERR_INTERNAL;
         if (fmt == 0)
             hipLaunchKernelGGL(hgemm256_update_kernel<0>, dim3((unsigned)g2), dim3(256), 0, st, m, n, K,
-                               (const _Float16 *)A16, (const _Float16 *)B16, C, ldc, t2m, t2n);
+                               (const _Float16 *)A16, sa, (const _Float16 *)B16, sb, C, ldc, t2m, t2n);
         else
             hipLaunchKernelGGL(hgemm256_update_kernel<1>, dim3((unsigned)g2), dim3(256), 0, st, m, n, K,
-                               (const __bf16 *)A16, (const __bf16 *)B16, C, ldc, t2m, t2n);
+                               (const __bf16 *)A16, sa, (const __bf16 *)B16, sb, C, ldc, t2m, t2n);
         HPLX_TRY_LAUNCH();
         return HPL_OK;
     }
@@ -879,10 +892,10 @@ int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A1
     if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
     if (fmt == 0)
         hipLaunchKernelGGL(hgemm_update_kernel<0>, dim3((unsigned)g), dim3(256), 0, st, m, n, K,
-                           (const _Float16 *)A16, (const _Float16 *)B16, C, ldc, tiles_m);
+                           (const _Float16 *)A16, sa, (const _Float16 *)B16, sb, C, ldc, tiles_m);
     else
         hipLaunchKernelGGL(hgemm_update_kernel<1>, dim3((unsigned)g), dim3(256), 0, st, m, n, K,
-                           (const __bf16 *)A16, (const __bf16 *)B16, C, ldc, tiles_m);
+                           (const __bf16 *)A16, sa, (const __bf16 *)B16, sb, C, ldc, tiles_m);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }

@@ -74,11 +74,15 @@ def test_mxp_factor_zero_pivot_info(fmt):
         h.hpl_set_option(h.HPL_OPT_LOOKAHEAD, old)
 
 
-@pytest.mark.parametrize("n,nb", [(64, 64), (130, 64), (1000, 128), (3000, 512), (4160, 1024)])
+@pytest.mark.parametrize("n,nb", [(64, 64), (130, 64), (1000, 128), (3000, 512), (4160, 1024), (2500, 64),
+                                  (8192, 256)])
 @pytest.mark.parametrize("fmt", [0, 1])
 def test_mxp_factor_lookahead_bitwise(n, nb, fmt):
-    """The look-ahead schedule (next panel's columns first, its FACT on the panel
-    stream beside the rest of the update) gives the bits of the plain schedule."""
+    """The look-ahead schedule (the next pair's columns and rows first, its panel
+    work on the panel stream beside the rest of the joint update) gives the bits
+    of the plain schedule.  At n = 8192 the plain schedule's joint updates run
+    on the 256 x 128 kernel alone, the look-ahead's narrow pieces on the
+    128 x 128 one: the two kernels must round alike."""
     h = hpl()
     A, _ = gpu_mxp_system(n, 9)
     old = h.hpl_get_option(h.HPL_OPT_LOOKAHEAD)
