@@ -237,7 +237,7 @@ def bench_mxp(args, torch, h):
     matrix; speed-up = t_fp64 / t_mxp."""
     n = 65536 if args.n == 163840 else args.n
     nb = args.nb            # FP64 path (its best panel width)
-    mnb = args.mxp_nb       # mixed-precision path (its best: the FP32 trailing matrix wants a wider panel)
+    mnb = args.mxp_nb       # mixed-precision path: FP32 panels of mnb columns, joint updates of 2048
     A = h.colmajor(n, n)
     h.hpl_mxp_generate(args.seed, A)
     b = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -749,7 +749,9 @@ def main():
                     help="hpl: seconds from process start after which no further step starts")
     ap.add_argument("--n", type=int, default=163840)
     ap.add_argument("--nb", type=int, default=512)
-    ap.add_argument("--mxp-nb", type=int, default=1024, help="panel width of the mixed-precision LU (--workload mxp)")
+    ap.add_argument("--mxp-nb", type=int, default=256,
+                    help="panel width of the mixed-precision LU (--workload mxp); panels are grouped 2048 columns "
+                         "at a time for the joint trailing update")
     ap.add_argument("--lookahead", type=int, default=1)
     ap.add_argument("--laswp-wgs", type=int, default=None,
                     help="hpl: workgroups of the trailing interchanges (HPL_OPT_LASWP_WGS; default: the library's)")

@@ -108,6 +108,7 @@ class Timer {
 // per-device state
 // ---------------------------------------------------------------------------
 constexpr int kRing = 4;        // panels in flight (plans and events are reused modulo kRing)
+constexpr int kMxpMaxGroup = 32; // panels per group of the mixed-precision factorization (at most)
 constexpr int kMaxChunks = 2;   // nb <= 1024 = 2 x kMaxSwaps
 constexpr int kMaxDevices = 64;
 
@@ -117,7 +118,7 @@ struct Device {
     hipStream_t sp = nullptr;  // panel stream (non-blocking)
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
     hipEvent_t ev_panel[kRing] = {}, ev_la[kRing] = {}, ev_iter[kRing] = {};
-    hipEvent_t ev_mxp[5] = {};          // mixed precision look-ahead: main -> panel stream (4), back (1)
+    hipEvent_t ev_mxp[2 * kMxpMaxGroup + 1] = {};  // mixed precision look-ahead: main -> panel stream, back
     void *ws = nullptr;
     LeafSync sync{};
     unsigned long long bar_epoch = 0;
@@ -672,33 +673,39 @@ static int mxp_panel(float *A, int64_t lda, int64_t n, int64_t c, int64_t w, uns
     return mxp_panel(A, lda, n, c + w1, w2, info, done, st);
 }
 
-// The mixed-precision factorization takes the panels in pairs P, Q (columns
-// [c, c+nb) and [c+nb, c+2nb)).  Per panel: FACT (FP32), U12 = L11^{-1} A12
-// (FP32), the scaling and conversion of -L21 and U12 to FP16/BF16.  Between
-// the two panels of a pair, P's update reaches only Q's columns and Q's rows;
-// the rest of the trailing matrix takes the update of both panels at once,
-// A22 += [-L21(P) -L21(Q)] [U12(P); U12(Q)] with k = 2 nb: the FP32 trailing
-// matrix is read and written once per two panels instead of once per panel
-// (the same products; only the FP32 sum of the two updates is rounded once
-// more before it meets A22).  The operand copies of P and Q sit side by side
-// in k in one buffer, indexed from the first row (column) below (right of) P.
+// The mixed-precision factorization takes the panels in groups of G (G nb =
+// kMxpJoint columns: G = 2 at nb = 1024).  Per panel: FACT (FP32), U12 =
+// L11^{-1} A12 (FP32), the scaling and conversion of -L21 and U12 to
+// FP16/BF16.  Inside a group, panel i's columns and rows take the updates of
+// panels 0 .. i-1 of the group (k = i nb) just before its FACT and its U12;
+// the rest of the trailing matrix takes the update of the whole group at once,
+// A22 += [-L21(0) .. -L21(G-1)] [U12(0); ..; U12(G-1)] with k = G nb: the FP32
+// trailing matrix is read and written once per G panels instead of once per
+// panel (the same products; only their FP32 sum over the group is rounded
+// once more before it meets A22).  The operand copies of a group sit side by
+// side in k in one buffer (panel i in k slots [i nb, (i+1) nb)), indexed from
+// the first row (column) below (right of) the group's panel 0.
 //
-// With look-ahead (Sec. III) the pair's joint update does, in order, the next
-// pair's P columns, its P rows, its Q columns, its Q rows, then the rest; the
-// panel stream factors the next P as soon as its columns are done, and so on
-// (FACT, U12 and copies of P into the second buffer, P's update of Q's
-// columns, FACT of Q, P's update of Q's rows, U12 and copies of Q), each step
-// as soon as its region is done, all beside the bulk of the joint update; the
-// next pair starts when both streams are done.  Every element takes the same
-// operations in the same order either way (the two update kernels round
-// alike), so the factors are bitwise equal.
+// With look-ahead (Sec. III) the group's joint update does, in order, the
+// columns then the rows of each panel of the next group, then the rest; the
+// panel stream takes each panel of the next group (its update by the group's
+// earlier panels, FACT, U12 and copies into the second buffer) as soon as the
+// joint update has reached its columns and rows, all beside the bulk of the
+// joint update; the next group starts when both streams are done.  Every
+// element takes the same operations in the same order either way (the two
+// update kernels round alike), so the factors are bitwise equal.
+constexpr int64_t kMxpJoint = 2048;  // k of the joint update of a group (G nb)
 static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, int64_t nb, int fmt, float *LU,
                            int64_t ldlu, int64_t *info, hipStream_t st)
 {
     const bool la = opt_lookahead.load() != 0 && opt_serialize.load() == 0 && n > nb;
-    // a buffer holds 2 nb slabs of k for rows (columns) 0 .. n-1 below P
+    int64_t G = kMxpJoint / nb;
+    if (G < 1) G = 1;
+    if (G > kMxpMaxGroup) G = kMxpMaxGroup;
+    const int64_t gw = G * nb;  // columns per group, k of the joint update
+    // a buffer holds gw k for rows (columns) 0 .. n-1 below the group's panel 0
     const int64_t ss = (n + 15) / 16 * 512;  // slab stride, elements
-    const size_t half_bytes = (sizeof(uint16_t) * (size_t)ss * (size_t)(2 * nb / 32) + 255) / 256 * 256;
+    const size_t half_bytes = (sizeof(uint16_t) * (size_t)ss * (size_t)(gw / 32) + 255) / 256 * 256;
     const int nbuf = la ? 2 : 1;
     const size_t sc_off = 2 * (size_t)nbuf * half_bytes;
     HPLX_PROPAGATE(ensure_mxp_ws(d, sc_off + 256));
@@ -722,10 +729,10 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         return tm.end(id, s, (double)(n - c) * (double)w * (double)w, 4.0 * (double)(n - c) * (double)w * 2.0);
     };
     // U12 of the panel at c (width nb) and the low-precision copies of -L21 and
-    // U12 into buffer q, rows (columns) from index off and k from kh nb, on s
-    auto prep = [&](int64_t c, int q, int64_t idx, int kh, hipStream_t s) -> int {
+    // U12 into buffer q, rows (columns) from index idx and k from slot i, on s
+    auto prep = [&](int64_t c, int q, int64_t idx, int64_t i, hipStream_t s) -> int {
         const int64_t c1 = c + nb, m = n - c1;
-        const size_t o = (size_t)kh * (size_t)(nb / 32) * (size_t)ss + (size_t)(idx / 16) * 512;
+        const size_t o = (size_t)i * (size_t)(nb / 32) * (size_t)ss + (size_t)(idx / 16) * 512;
         const int id = tm.begin(ST_MXP_FACT, s);
         HPLX_PROPAGATE(mxp_trsm(LU + off(c, c, ldlu), ldlu, nb, LU + off(c, c1, ldlu), ldlu, m, s));
         HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)nb, mx,
@@ -735,7 +742,7 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         return tm.end(id, s, (double)nb * (double)nb * (double)m, 4.0 * (double)nb * (double)m * 2.0);
     };
     // A22 rows [b0 + i0, b0 + i0 + ni) x columns [b0 + j0, b0 + j0 + nc) += the
-    // product of k = K of buffer q (b0 = the first row below the pair's P), on s
+    // product of k = K of buffer q (b0 = the first row below the group's panel 0), on s
     auto update = [&](int64_t b0, int q, int64_t i0, int64_t ni, int64_t j0, int64_t nc, int64_t K,
                       hipStream_t s) -> int {
         if (ni <= 0 || nc <= 0) return HPL_OK;
@@ -746,58 +753,62 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         return tm.end(id, s, 2.0 * (double)ni * (double)nc * (double)K,
                       8.0 * (double)ni * (double)nc + 2.0 * (double)K * (double)(ni + nc));
     };
-    // the panel work of the pair at c into buffer q, on stream s; with
-    // look-ahead each step first waits for its region of the previous joint
-    // update (events recorded on the main stream by the caller)
-    auto pair_panels = [&](int64_t c, int q, hipStream_t s, hipEvent_t *ev) -> int {
-        const int64_t b0 = c + nb, m1 = n - b0;
-        const int64_t wq = m1 < nb ? m1 : nb;
-        if (ev) HPLX_TRY(hipStreamWaitEvent(s, ev[1], 0));
-        HPLX_PROPAGATE(prep(c, q, 0, 0, s));
-        if (ev) HPLX_TRY(hipStreamWaitEvent(s, ev[2], 0));
-        HPLX_PROPAGATE(update(b0, q, 0, m1, 0, wq, nb, s));  // P's update of Q's columns
-        HPLX_PROPAGATE(fact(b0, wq, s));
-        if (m1 == wq) return HPL_OK;                         // Q is the last panel
-        if (ev) HPLX_TRY(hipStreamWaitEvent(s, ev[3], 0));
-        HPLX_PROPAGATE(update(b0, q, 0, wq, wq, m1 - wq, nb, s));  // P's update of Q's rows
-        return prep(b0, q, nb, 1, s);
+    // the panel work of the group at c into buffer q, on stream s, its panel 0
+    // factored; with look-ahead, panel i first waits for the joint update of
+    // the previous group to reach its columns (ev[2i]) and its rows (ev[2i+1])
+    auto group_panels = [&](int64_t c, int q, hipStream_t s, hipEvent_t *ev) -> int {
+        const int64_t b0 = c + nb;
+        for (int64_t i = 0; i < G; ++i) {
+            const int64_t ci = c + i * nb;  // panel i
+            if (ci >= n) break;
+            const int64_t wi = (n - ci) < nb ? (n - ci) : nb;
+            if (i > 0) {
+                if (ev) HPLX_TRY(hipStreamWaitEvent(s, ev[2 * i], 0));
+                HPLX_PROPAGATE(update(b0, q, ci - b0, n - ci, ci - b0, wi, i * nb, s));  // its columns
+                HPLX_PROPAGATE(fact(ci, wi, s));
+            }
+            if (ci + wi >= n) break;  // the last panel of the matrix
+            if (ev) HPLX_TRY(hipStreamWaitEvent(s, ev[2 * i + 1], 0));
+            if (i > 0) HPLX_PROPAGATE(update(b0, q, ci - b0, wi, ci + wi - b0, n - ci - wi, i * nb, s));  // its rows
+            HPLX_PROPAGATE(prep(ci, q, ci + wi - b0, i, s));
+        }
+        return HPL_OK;
     };
     HPLX_PROPAGATE(launch_fill_u64(dinfo, 1, ULLONG_MAX, st));
     HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)leaf_done, 1, 0ull, st));
     HPLX_PROPAGATE(launch_cvt_f64_f32(A, lda, LU, ldlu, n, n, st));
     HPLX_PROPAGATE(fact(0, nb < n ? nb : n, st));
     int cur = 0;
-    if (nb < n) HPLX_PROPAGATE(pair_panels(0, cur, st, nullptr));
-    for (int64_t c = 0; c + 2 * nb < n; c += 2 * nb) {
-        // the pair at c is factored and its copies are in buffer cur; the joint
-        // update covers rows and columns [c2, n), c2 = c + 2 nb, the next P
-        const int64_t b0 = c + nb, c2 = c + 2 * nb, m2 = n - c2;
-        const int64_t wp = m2 < nb ? m2 : nb;
-        const int64_t K = 2 * nb;
+    if (nb < n) HPLX_PROPAGATE(group_panels(0, cur, st, nullptr));
+    for (int64_t c = 0; c + gw < n; c += gw) {
+        // the group at c is factored and its copies are in buffer cur; the
+        // joint update covers rows and columns [c2, n), c2 = c + G nb, the
+        // next group, whose panel 0 is at index i2 = c2 - b0
+        const int64_t b0 = c + nb, c2 = c + gw, i2 = c2 - b0, m2 = n - c2;
+        const int64_t w0 = m2 < nb ? m2 : nb;
         if (!la) {
-            HPLX_PROPAGATE(update(b0, cur, nb, m2, nb, m2, K, st));
-            HPLX_PROPAGATE(fact(c2, wp, st));
-            if (m2 > wp) HPLX_PROPAGATE(pair_panels(c2, cur ^ 1, st, nullptr));
+            HPLX_PROPAGATE(update(b0, cur, i2, m2, i2, m2, gw, st));
+            HPLX_PROPAGATE(fact(c2, w0, st));
+            if (m2 > w0) HPLX_PROPAGATE(group_panels(c2, cur ^ 1, st, nullptr));
         } else {
             hipEvent_t *ev = d->ev_mxp;
-            const int64_t wq = (m2 - wp) < nb ? (m2 - wp) : nb;  // next Q (0: none)
-            HPLX_PROPAGATE(update(b0, cur, nb, m2, nb, wp, K, st));  // next P's columns
-            HPLX_TRY(hipEventRecord(ev[0], st));
-            HPLX_TRY(hipStreamWaitEvent(sp, ev[0], 0));
-            HPLX_PROPAGATE(fact(c2, wp, sp));
-            if (wq > 0) {
-                HPLX_PROPAGATE(update(b0, cur, nb, wp, nb + wp, m2 - wp, K, st));  // next P's rows
-                HPLX_TRY(hipEventRecord(ev[1], st));
-                HPLX_PROPAGATE(update(b0, cur, nb + wp, m2 - wp, nb + wp, wq, K, st));  // next Q's columns
-                HPLX_TRY(hipEventRecord(ev[2], st));
-                HPLX_PROPAGATE(update(b0, cur, nb + wp, wq, nb + wp + wq, m2 - wp - wq, K, st));  // next Q's rows
-                HPLX_TRY(hipEventRecord(ev[3], st));
-                HPLX_PROPAGATE(pair_panels(c2, cur ^ 1, sp, ev));
-                // the rest
-                HPLX_PROPAGATE(update(b0, cur, nb + wp + wq, m2 - wp - wq, nb + wp + wq, m2 - wp - wq, K, st));
+            int64_t done = i2;  // rows and columns [b0 + done, n) still to update: the rest
+            for (int64_t i = 0; i < G && done < n - b0; ++i) {
+                const int64_t wi = (n - b0 - done) < nb ? (n - b0 - done) : nb;
+                HPLX_PROPAGATE(update(b0, cur, done, n - b0 - done, done, wi, gw, st));  // panel i's columns
+                HPLX_TRY(hipEventRecord(ev[2 * i], st));
+                if (i == 0) {
+                    HPLX_TRY(hipStreamWaitEvent(sp, ev[0], 0));
+                    HPLX_PROPAGATE(fact(c2, w0, sp));
+                }
+                HPLX_PROPAGATE(update(b0, cur, done, wi, done + wi, n - b0 - done - wi, gw, st));  // its rows
+                HPLX_TRY(hipEventRecord(ev[2 * i + 1], st));
+                done += wi;
             }
-            HPLX_TRY(hipEventRecord(ev[4], sp));
-            HPLX_TRY(hipStreamWaitEvent(st, ev[4], 0));
+            if (m2 > w0) HPLX_PROPAGATE(group_panels(c2, cur ^ 1, sp, ev));
+            HPLX_PROPAGATE(update(b0, cur, done, n - b0 - done, done, n - b0 - done, gw, st));  // the rest
+            HPLX_TRY(hipEventRecord(ev[2 * kMxpMaxGroup], sp));
+            HPLX_TRY(hipStreamWaitEvent(st, ev[2 * kMxpMaxGroup], 0));
         }
         cur ^= 1;
     }
