@@ -92,10 +92,9 @@ struct BatchShared {
     };
     double T[kPBmax][kPBmax + 1];          // diagonal block (L11, or a block of U / L for the solves)
     double Ti[kPBmax][kPBmax + 1];         // L11^{-1}, identity past the panel width
-    double prow[2][kBW][kPBmax];           // per-wave candidate rows
-    double drow[2][kPBmax];                // the diagonal row
-    double pv[2][kBW];                     // per-wave candidate |a|
-    int pr[2][kBW];                        // per-wave candidate row (-1: none)
+    double Ur[kPBmax][kPBmax];             // the panel's pivot rows, step j: slot q = column k0+j+q
+    double pv[kBW];                        // per-wave candidate |a|
+    int pr[kBW];                           // per-wave candidate (logical) row
     double Ys[kBatchMaxRhs][kSB];          // solved block of the solves
     int perm[kBatchMaxN];                  // row permutation: row i of P A is row perm[i] of A
     int slot_row[2 * kPBmax];              // interchange composition: destination rows ...
@@ -142,9 +141,14 @@ __device__ __forceinline__ gf64 *col_ptr(gf64 *a, gf64 *b, int n, int c)
 
 // FACT of the panel [k0, k0+w) (rows k0..n-1 in registers), its interchanges
 // recorded in ip, the permutation and the slot lists; L11 left in sh.T.
-// The column loop is not unrolled (the unrolled body overflows the
-// instruction cache): the register row rotates by one column per step, so the
-// current column is always v[0] and every register index is a constant.
+// Rows do not move between threads: thread t holds row k0+t as loaded and the
+// logical row lr that row has become (an interchange swaps two lr values).
+// Step j's column is always v[0]: the rank-1 update writes slot q's result
+// into slot q-1 and the column's multiplier into the last slot, so the loop
+// is not unrolled and every register index is a constant.  Only the winning
+// row is published (into sh.Ur[j], its finished slots zeroed): a zero u
+// leaves a row's finished slots -- its earlier multipliers -- unchanged, so
+// the update needs no per-slot masks.
 template <int PB, int OCC>
 __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, int k0)
 {
@@ -166,89 +170,53 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
             v[q] = a[(size_t)rr + (size_t)cq * (size_t)n];
         }
     }
+    int lr = r;
     __syncthreads();
     for (int j = 0; j < w; ++j) {
-        const int par = j & 1;
-        // wave argmax of |v[0]| over rows >= k0+j; ties: the lowest row (lane)
-        const bool cand = own && t >= j;
-        const double cv = cand ? fabs(v[0]) : -1.0;
+        const int kj = k0 + j;
+        // wave argmax of |v[0]| over logical rows >= k0+j (a NaN ranks below
+        // every number); ties: the lowest logical row
+        const double av = fabs(v[0]);
+        const double cv = (own && lr >= kj) ? (av == av ? av : -0.5) : -1.0;
         const double vm = wave_max(cv);
-        const unsigned long long hit = __ballot(cand && cv == vm);
-        const int wl = hit ? (int)__builtin_ctzll(hit) : -1;
+        const unsigned rm = wave_min_u32(cv == vm ? (unsigned)lr : 0xffffffffu);
         if (lane == 0) {
-            sh.pv[par][wave] = vm;
-            sh.pr[par][wave] = wl >= 0 ? k0 + 64 * wave + wl : -1;
-        }
-        if (lane == wl) {
-#pragma unroll
-            for (int q = 0; q < kPB; ++q) sh.prow[par][wave][q] = v[q];
-        }
-        if (r == k0 + j) {
-#pragma unroll
-            for (int q = 0; q < kPB; ++q) sh.drow[par][q] = v[q];
+            sh.pv[wave] = vm;
+            sh.pr[wave] = (int)rm;
         }
         __syncthreads();
-        double gv = -1.0;
-        int gp = 0x7fffffff, gw = 0;
-        {
-            double qv[kBW];
-            int qr[kBW];
+        // the winner over the waves (a wave without candidates reports -1)
+        const double x = lane < kBW ? sh.pv[lane] : -2.0;
+        const unsigned y = lane < kBW ? (unsigned)sh.pr[lane] : 0xffffffffu;
+        const double gv = wave_max(x);
+        const int gp = (int)wave_min_u32(x == gv ? y : 0xffffffffu);
+        // its thread publishes the row: slots of the panel's remaining
+        // columns, zeros past them
+        if (own && lr == gp) {
 #pragma unroll
-            for (int q = 0; q < kBW; ++q) {
-                qv[q] = sh.pv[par][q];
-                qr[q] = sh.pr[par][q];
-            }
-#pragma unroll
-            for (int q = 0; q < kBW; ++q)
-                if (qr[q] >= 0 && (qv[q] > gv || (qv[q] == gv && qr[q] < gp))) {
-                    gv = qv[q];
-                    gp = qr[q];
-                    gw = q;
-                }
-        }
-        // no valid candidate (a NaN column): keep the diagonal row, so
-        // every row index stays inside the system
-        if (gp == 0x7fffffff) gp = k0 + j;
-        // the pivot row, in registers (broadcast reads, all issued at once)
-        double u[kPB];
-        {
-            const double *up = (gp == k0 + j) ? sh.drow[par] : sh.prow[par][gw];
-#pragma unroll
-            for (int q = 0; q < kPB; ++q) u[q] = up[q];
-        }
-        if (gp != k0 + j) {
-            if (r == k0 + j) {
-#pragma unroll
-                for (int q = 0; q < kPB; ++q) v[q] = u[q];
-            } else if (((gp - k0) >> 6) == wave) {  // the pivot row's wave (uniform branch)
-                if (r == gp) {
-#pragma unroll
-                    for (int q = 0; q < kPB; ++q) v[q] = sh.drow[par][q];
-                }
-            }
+            for (int q = 0; q < kPB; ++q) sh.Ur[j][q] = q < w - j ? v[q] : 0.0;
         }
         if (t == 0) sh.pivs[j] = gp;  // composed after the loop (off the per-column path)
+        __syncthreads();
+        double u[kPB];
+#pragma unroll
+        for (int q = 0; q < kPB; ++q) u[q] = sh.Ur[j][q];
+        // the interchange of logical rows k0+j and gp
+        if (lr == kj)
+            lr = gp;
+        else if (lr == gp)
+            lr = kj;
         const double piv = u[0];
-        if (piv == 0.0) {
-            if (t == 0 && sh.info == 0) sh.info = k0 + j + 1;  // column left unscaled
-        } else {
-            const bool below = own && r > k0 + j;
-            const double l = below ? v[0] / piv : 0.0;
-            if (below) v[0] = l;
-            // the panel's remaining columns sit at 1 .. w-1-j (selects, no branches)
+        const bool sing = piv == 0.0;  // column left unscaled, no update
+        if (sing && t == 0 && sh.info == 0) sh.info = kj + 1;
+        const double l = sing ? v[0] : v[0] / piv;
+        const double lu = (own && lr > kj && !sing) ? l : 0.0;
 #pragma unroll
-            for (int q = 1; q < kPB; ++q) {
-                const double x = __fma_rn(-l, u[q], v[q]);
-                v[q] = (below && q < w - j) ? x : v[q];
-            }
-        }
-        // rotate: the next column moves to v[0], this one to the end
-        const double c0 = v[0];
-#pragma unroll
-        for (int q = 0; q < kPB - 1; ++q) v[q] = v[q + 1];
-        v[kPB - 1] = c0;
+        for (int q = 1; q < kPB; ++q) v[q - 1] = __fma_rn(-lu, u[q], v[q]);
+        v[kPB - 1] = l;
     }
-    // w rotations so far: complete the turn, column q back at v[q]
+    // w steps so far: rotate the rest of the turn, so that slot q holds the
+    // multiplier of column k0+q
     for (int j = w; j < kPB; ++j) {
         const double c0 = v[0];
 #pragma unroll
@@ -304,15 +272,28 @@ __device__ __attribute__((noinline)) void bat_panel(gf64 *a, gi32 *ip, int n, in
         if (j < w) sh.perm[d0] = p0;
         if (isx) sh.perm[dx] = px;
     }
-    // write the factored panel back; L11 to LDS
+    // write the factored panel back: each row's multipliers to its logical
+    // row (a row of U11 holds those left of its diagonal), the rows of U from
+    // sh.Ur; L11 and U11 to sh.T
     if (own) {
+        const int nl = lr < k0 + w ? lr - k0 : w;
 #pragma unroll
         for (int q = 0; q < kPB; ++q)
-            if (q < w) a[(size_t)r + (size_t)(k0 + q) * (size_t)n] = v[q];
+            if (q < nl) a[(size_t)lr + (size_t)(k0 + q) * (size_t)n] = v[q];
+        if (lr < k0 + w) {
+#pragma unroll
+            for (int q = 0; q < kPB; ++q)
+                if (q < nl) sh.T[lr - k0][q] = v[q];
+        }
     }
     if (t < w) {
 #pragma unroll
-        for (int q = 0; q < kPB; ++q) sh.T[t][q] = v[q];
+        for (int q = 0; q < kPB; ++q)
+            if (q >= t && q < w) {
+                const double x = sh.Ur[t][q - t];
+                sh.T[t][q] = x;
+                a[(size_t)(k0 + t) + (size_t)(k0 + q) * (size_t)n] = x;
+            }
     }
     __syncthreads();
 }
