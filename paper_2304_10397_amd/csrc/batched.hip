@@ -302,8 +302,29 @@ template <int PB, int OCC>
 __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int n, int ncol, int k0, int w)
 {
     constexpr int kPB = PB, kMaxSlots = 2 * PB;
+    constexpr int kGq = kGc * kMaxSlots / kBT;  // gathered values per thread and chunk
     static_assert(kBT % kMaxSlots == 0 && kGc % (kBT / kMaxSlots) == 0, "interchange pass shape");
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nslots = sh.nslots;
+    const int nother = ncol - w;
+    const int slot = t & (kMaxSlots - 1), cq = t / kMaxSlots;  // kBT / kMaxSlots columns per pass
+    const int src = sh.slot_src[slot < nslots ? slot : nslots - 1];
+    const int dst = sh.slot_row[slot < nslots ? slot : nslots - 1];
+    // the gather of a chunk of kGc columns (lane = slot, so the panel rows of
+    // a column are read coalesced); issued one chunk ahead, so that its loads
+    // are in flight while the previous chunk is multiplied and scattered
+    double gq[kGq];
+    auto gather = [&](int e0) __attribute__((always_inline)) {
+        const int ce = (nother - e0) < kGc ? (nother - e0) : kGc;
+#pragma unroll
+        for (int q = 0; q < kGq; ++q) {
+            const int cl = cq + q * (kBT / kMaxSlots);
+            const int e = e0 + (cl < ce ? cl : ce - 1);
+            const int c = e < k0 ? e : e + w;
+            gq[q] = col_ptr(a, b, n, c)[src];
+        }
+    };
+    if (nother > 0) gather(0);
     // ---- 1. L11^{-1} (the triangular inverse; unit lower, identity past the
     //      panel width) into sh.Ti: lane j of wave 0 solves L11 y = e_j row by
     //      row, y_i = -sum_{k<i} l_ik y_k, with y_k = 0 above the diagonal
@@ -320,32 +341,19 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
         for (int i = 0; i < kPB; ++i) sh.Ti[i][lane] = y[i];
     }
     // ---- 2. interchanges on every other column; U12 = L11^{-1} A12 on the right.
-    //      Chunks of kGc columns through LDS: gather (lane = slot, so the
-    //      panel rows of a column are read coalesced), the right columns' top
+    //      Chunks of kGc columns through LDS: gathered, the right columns' top
     //      rows multiplied by L11^{-1} on the matrix cores (one 16 x 16 block
-    //      per wave), scatter.
+    //      per wave), scattered.
     {
-        const int nslots = sh.nslots;
-        const int nother = ncol - w;
-        const int slot = t & (kMaxSlots - 1), cq = t / kMaxSlots;  // kBT / kMaxSlots columns per pass
-        const int src = sh.slot_src[slot < nslots ? slot : nslots - 1];
-        const int dst = sh.slot_row[slot < nslots ? slot : nslots - 1];
         for (int e0 = 0; e0 < nother; e0 += kGc) {
             const int ce = (nother - e0) < kGc ? (nother - e0) : kGc;
-            double gq[kGc * kMaxSlots / kBT];
 #pragma unroll
-            for (int q = 0; q < kGc * kMaxSlots / kBT; ++q) {
-                const int cl = cq + q * (kBT / kMaxSlots);
-                const int e = e0 + (cl < ce ? cl : ce - 1);
-                const int c = e < k0 ? e : e + w;
-                gq[q] = col_ptr(a, b, n, c)[src];
-            }
-#pragma unroll
-            for (int q = 0; q < kGc * kMaxSlots / kBT; ++q) {
+            for (int q = 0; q < kGq; ++q) {
                 const int cl = cq + q * (kBT / kMaxSlots);
                 gstage<PB>(cl, slot) = gq[q];
             }
             __syncthreads();
+            if (e0 + kGc < nother) gather(e0 + kGc);
             if (e0 + ce > k0) {  // the chunk has right columns (uniform)
                 // block (rb, cb) of Y = L11^{-1} G_top: rows 16 rb.., columns 16 cb..;
                 // lane l supplies Ti(16 rb + l%16, 4 s + l/16) and G(4 s + l/16, 16 cb + l%16)
@@ -372,7 +380,7 @@ __device__ __attribute__((noinline)) void bat_interchange(gf64 *a, gf64 *b, int 
             __syncthreads();
             if (slot < nslots) {
 #pragma unroll
-                for (int q = 0; q < kGc * kMaxSlots / kBT; ++q) {
+                for (int q = 0; q < kGq; ++q) {
                     const int cl = cq + q * (kBT / kMaxSlots);
                     if (cl < ce) {
                         const int e = e0 + cl;
