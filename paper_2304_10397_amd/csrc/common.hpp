@@ -286,6 +286,8 @@ int launch_grad_a(const double *G, int64_t ldg, const double *X, int64_t ldx, in
 int launch_mxp_diag(double *A, int64_t n, int64_t lda, hipStream_t st);
 int launch_cvt_f64_f32(const double *A, int64_t lda, float *B, int64_t ldb, int64_t rows, int64_t cols,
                        hipStream_t st);
+// widest FP32 panel leaf and triangular-solve leaf (one launch each)
+constexpr int kPanel32LeafMax = 64, kTrsm32LeafMax = 64;
 int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsigned long long *info,
                         unsigned *done, hipStream_t st);
 int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st);

@@ -648,7 +648,7 @@ static int ensure_mxp_ws(Device *d, size_t bytes)
 static int mxp_trsm(const float *L, int64_t ldl, int64_t nbk, float *B, int64_t ldb, int64_t ncols, hipStream_t st)
 {
     if (nbk <= 0 || ncols <= 0) return HPL_OK;
-    if (nbk <= 32) return launch_trsm32_leaf(L, ldl, B, ldb, (int)nbk, ncols, st);
+    if (nbk <= kTrsm32LeafMax) return launch_trsm32_leaf(L, ldl, B, ldb, (int)nbk, ncols, st);
     // the panel's own solves (few columns): one launch instead of a recursion
     // of leaves and GEMMs
     if (trsm32_small_ok(nbk, ncols)) return launch_trsm32_small(L, ldl, B, ldb, nbk, ncols, st);
@@ -662,7 +662,7 @@ static int mxp_trsm(const float *L, int64_t ldl, int64_t nbk, float *B, int64_t 
 static int mxp_panel(float *A, int64_t lda, int64_t n, int64_t c, int64_t w, unsigned long long *info, unsigned *done,
                      hipStream_t st)
 {
-    if (w <= 32) return launch_panel32_leaf(A, lda, c, n, (int)w, info, done, st);
+    if (w <= kPanel32LeafMax) return launch_panel32_leaf(A, lda, c, n, (int)w, info, done, st);
     int64_t w1 = ((w / 2 + 31) / 32) * 32;
     if (w1 >= w) w1 = w - 1;
     const int64_t w2 = w - w1;

@@ -65,24 +65,24 @@ __global__ __launch_bounds__(256) void cvt_f64_f32_kernel(const double *__restri
 }
 
 // ---------------------------------------------------------------------------
-// FP32 panel leaf (w <= 32 columns, rows [c, n)), no pivoting.  Every row takes
-// the same right-looking steps: at step k a row i > k divides its entry k by
-// u_kk and subtracts that multiple of the pivot row from its entries q > k (a
-// zero u_kk leaves the column as is; info reports it).  Each thread holds one
-// row in registers: in every workgroup, threads 0..31 hold the rows of the
-// w x w diagonal block (recomputed by each workgroup) and threads 32..255 the
-// rows below it, 224 per workgroup.  At step k thread k publishes its row (the
+// FP32 panel leaf (w <= LW = 32 or 64 columns, rows [c, n)), no pivoting.
+// Every row takes the same right-looking steps: at step k a row i > k divides
+// its entry k by u_kk and subtracts that multiple of the pivot row from its
+// entries q > k (a zero u_kk leaves the column as is; info reports it).  Each
+// thread holds one row in registers: in every workgroup, threads 0..LW-1 hold
+// the rows of the w x w diagonal block (recomputed by each workgroup) and
+// threads LW..255 the rows below it, 256 - LW per workgroup.  At step k thread k publishes its row (the
 // final row k of U) to a double-buffered LDS row, so one barrier per step
 // suffices.  Every workgroup reads the diagonal block as input, so it is
 // written back only by the last workgroup to finish (counted on *done, which
 // wraps to zero at the end of each launch).
 // ---------------------------------------------------------------------------
-constexpr int kLw = 32, kLeafRows = 256 - kLw;
-
+template <int LW>
 __global__ __launch_bounds__(256) void panel32_leaf_kernel(float *__restrict__ A, int64_t lda, int64_t c,
                                                            int64_t n, int w, unsigned long long *__restrict__ info,
                                                            unsigned *__restrict__ done)
 {
+    constexpr int kLw = LW, kLeafRows = 256 - LW;
     __shared__ float P[2][kLw];
     __shared__ int last;
     const int t = threadIdx.x;
@@ -130,21 +130,22 @@ __global__ __launch_bounds__(256) void panel32_leaf_kernel(float *__restrict__ A
 }
 
 // ---------------------------------------------------------------------------
-// FP32 triangular-solve leaf: B (nbk x ncols, nbk <= 32) <- L^{-1} B with L
-// unit lower.  A workgroup of 128 threads takes 128 columns: the 32 x 128 block
+// FP32 triangular-solve leaf: B (nbk x ncols, nbk <= TL = 32 or 64) <- L^{-1} B
+// with L unit lower.  A workgroup of 128 threads takes 128 columns: the TL x 128 block
 // moves between B and LDS with coalesced accesses (16-byte vectors when every
 // column starts 16-byte aligned, else 32 lanes per column), then each thread
 // solves its column in registers, right-looking: at step k every row i > k
 // subtracts l_ik x_k, so each element takes its subtractions in k order.  L is
 // staged transposed so that step k reads one contiguous column of L.
 // ---------------------------------------------------------------------------
-constexpr int kTl = 32, kTlCols = 128, kTlPad = 4;
+constexpr int kTlCols = 128, kTlPad = 4;
 
-template <bool VEC>
+template <int TL, bool VEC>
 __global__ __launch_bounds__(kTlCols) void trsm32_leaf_kernel(const float *__restrict__ L, int64_t ldl,
                                                               float *__restrict__ B, int64_t ldb, int nbk,
                                                               int64_t ncols)
 {
+    constexpr int kTl = TL;
     typedef float f4 __attribute__((ext_vector_type(4)));
     __shared__ __attribute__((aligned(16))) float Lt[kTl][kTl + kTlPad];            // Lt[k][i] = l_ik
     __shared__ __attribute__((aligned(16))) float Xs[kTlCols][kTl + kTlPad];        // Xs[c][i] = b_i of column c
@@ -157,12 +158,13 @@ __global__ __launch_bounds__(kTlCols) void trsm32_leaf_kernel(const float *__res
         const int e = t + kTlCols * q, r = e % kTl, cc = e / kTl;
         sv[q] = load_or(r < nbk && cc < nbk, L + off(r, cc, ldl), L, 0.0f);
     }
+    constexpr int kUc = kTl / 4;  // 16-byte units per column
     if (VEC) {
-        // unit u: column u / 8, rows 4 (u % 8) .. + 3 (nbk == 32)
+        // unit u: column u / kUc, rows 4 (u % kUc) .. + 3 (nbk == TL)
         f4 vv[kTl / 4];
 #pragma unroll
         for (int q = 0; q < kTl / 4; ++q) {
-            const int u = t + kTlCols * q, c = u >> 3, r4 = (u & 7) * 4;
+            const int u = t + kTlCols * q, c = u / kUc, r4 = (u % kUc) * 4;
             const int64_t jj = j0 + c;
             const f4 v = *(const f4 *)(B + (size_t)(jj < ncols ? jj : ncols - 1) * (size_t)ldb + r4);
             vv[q] = jj < ncols ? v : (f4){0.0f, 0.0f, 0.0f, 0.0f};
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(kTlCols) void trsm32_leaf_kernel(const float *__res
 #pragma unroll
         for (int q = 0; q < kTl / 4; ++q) {
             const int u = t + kTlCols * q;
-            *(f4 *)&Xs[u >> 3][(u & 7) * 4] = vv[q];
+            *(f4 *)&Xs[u / kUc][(u % kUc) * 4] = vv[q];
         }
     } else {
         float xv[kTl];
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(kTlCols) void trsm32_leaf_kernel(const float *__res
     if (VEC) {
 #pragma unroll
         for (int q = 0; q < kTl / 4; ++q) {
-            const int u = t + kTlCols * q, c = u >> 3, r4 = (u & 7) * 4;
+            const int u = t + kTlCols * q, c = u / kUc, r4 = (u % kUc) * 4;
             const int64_t jj = j0 + c;
             if (jj < ncols) *(f4 *)(B + (size_t)jj * (size_t)ldb + r4) = *(const f4 *)&Xs[c][r4];
         }
@@ -789,11 +791,15 @@ int launch_cvt_f64_f32(const double *A, int64_t lda, float *B, int64_t ldb, int6
 int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsigned long long *info,
                         unsigned *done, hipStream_t st)
 {
-    if (w <= 0 || w > kLw) return HPL_ERR_INTERNAL;
+    if (w <= 0 || w > kPanel32LeafMax) return HPL_ERR_INTERNAL;
     const int64_t below = n - c - w;
-    const int64_t g = below > 0 ? blocks_of(below, kLeafRows) : 1;
+    const int lw = w <= 32 ? 32 : 64;
+    const int64_t g = below > 0 ? blocks_of(below, 256 - lw) : 1;
     if (g > 0xffffffffll) return HPL_ERR_INTERNAL;
-    hipLaunchKernelGGL(panel32_leaf_kernel, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info, done);
+    if (lw == 32)
+        hipLaunchKernelGGL(panel32_leaf_kernel<32>, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info, done);
+    else
+        hipLaunchKernelGGL(panel32_leaf_kernel<64>, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info, done);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
@@ -801,16 +807,26 @@ int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsi
 int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st)
 {
     if (ncols <= 0 || nbk <= 0) return HPL_OK;
-    if (nbk > kTl) return HPL_ERR_INTERNAL;
+    if (nbk > kTrsm32LeafMax) return HPL_ERR_INTERNAL;
     const int64_t g = blocks_of(ncols, kTlCols);
     if (g > 0x7fffffffll) return HPL_ERR_INTERNAL;
-    // 16-byte vectors need every column start 16-byte aligned and all 32 rows present
-    const bool vec = nbk == kTl && ((uintptr_t)B % 16) == 0 && (ldb % 4) == 0;
-    if (vec)
-        hipLaunchKernelGGL(trsm32_leaf_kernel<true>, dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B, ldb, nbk, ncols);
-    else
-        hipLaunchKernelGGL(trsm32_leaf_kernel<false>, dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B, ldb, nbk,
-                           ncols);
+    // 16-byte vectors need every column start 16-byte aligned and all rows present
+    const bool al = ((uintptr_t)B % 16) == 0 && (ldb % 4) == 0;
+    if (nbk <= 32) {
+        if (nbk == 32 && al)
+            hipLaunchKernelGGL((trsm32_leaf_kernel<32, true>), dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B, ldb,
+                               nbk, ncols);
+        else
+            hipLaunchKernelGGL((trsm32_leaf_kernel<32, false>), dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B,
+                               ldb, nbk, ncols);
+    } else {
+        if (nbk == 64 && al)
+            hipLaunchKernelGGL((trsm32_leaf_kernel<64, true>), dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B, ldb,
+                               nbk, ncols);
+        else
+            hipLaunchKernelGGL((trsm32_leaf_kernel<64, false>), dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B,
+                               ldb, nbk, ncols);
+    }
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
