@@ -293,14 +293,17 @@ int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsi
 int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st);
 int launch_sgemm32(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B, int64_t ldb,
                    float *C, int64_t ldc, hipStream_t st);
-int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols, int w,
-                     unsigned *mx, int *sexp, hipStream_t st);
-// -L21 and U12 scaled and rounded into the blocked low-precision layout (1 KB
-// blocks of 16 rows x 32 k, ordered by k slab then 16-row group; sa, sb = slab
-// strides in elements, multiples of 512; A16 and B16 point at the block of
-// the first row and k).
+// max |L21| and max |U12| of a panel into mx[0], mx[1] (accumulated: the pair
+// must start at zero).
+int launch_mxp_maxabs(const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols, int w,
+                      unsigned *mx, hipStream_t st);
+// -L21 and U12 scaled (the exponent from mx) and rounded into the blocked
+// low-precision layout (1 KB blocks of 16 rows x 32 k, ordered by k slab then
+// 16-row group; sa, sb = slab strides in elements, multiples of 512; A16 and
+// B16 point at the block of the first row and k); reset[0..1] cleared.
 int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols,
-                       int w, const int *sexp, void *A16, int64_t sa, void *B16, int64_t sb, hipStream_t st);
+                       int w, const unsigned *mx, unsigned *reset, void *A16, int64_t sa, void *B16, int64_t sb,
+                       hipStream_t st);
 int launch_hgemm_update(int fmt, int64_t m, int64_t n, int64_t K, const void *A16, int64_t sa, const void *B16,
                         int64_t sb, float *C, int64_t ldc, hipStream_t st);
 // r = b - A x with kResSplit column chunks; part holds 2 kResSplit n doubles of partial sums.

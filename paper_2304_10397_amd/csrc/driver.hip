@@ -716,8 +716,10 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         A16[q] = (uint16_t *)(ws + 2 * (size_t)qq * half_bytes);
         B16[q] = (uint16_t *)(ws + (2 * (size_t)qq + 1) * half_bytes);
     }
+    // two pairs of maxima (|L21|, |U12|), used by alternate panels: a panel's
+    // conversion clears the other pair for the next panel
     unsigned *mx = (unsigned *)(ws + sc_off);
-    int *sexp = (int *)(ws + sc_off + 16);
+    int prep_count = 0;
     unsigned long long *dinfo = (unsigned long long *)(ws + sc_off + 32);
     unsigned *leaf_done = (unsigned *)(ws + sc_off + 64);  // panel leaf's workgroup count (returns to zero)
     hipStream_t sp = la ? d->sp : st;
@@ -735,10 +737,11 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         const size_t o = (size_t)i * (size_t)(nb / 32) * (size_t)ss + (size_t)(idx / 16) * 512;
         const int id = tm.begin(ST_MXP_FACT, s);
         HPLX_PROPAGATE(mxp_trsm(LU + off(c, c, ldlu), ldlu, nb, LU + off(c, c1, ldlu), ldlu, m, s));
-        HPLX_PROPAGATE(launch_mxp_scale(LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)nb, mx,
-                                        sexp, s));
+        unsigned *pm = mx + 2 * (prep_count & 1), *other = mx + 2 * ((prep_count + 1) & 1);
+        ++prep_count;
+        HPLX_PROPAGATE(launch_mxp_maxabs(LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)nb, pm, s));
         HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)nb,
-                                          sexp, A16[q] + o, ss, B16[q] + o, ss, s));
+                                          pm, other, A16[q] + o, ss, B16[q] + o, ss, s));
         return tm.end(id, s, (double)nb * (double)nb * (double)m, 4.0 * (double)nb * (double)m * 2.0);
     };
     // A22 rows [b0 + i0, b0 + i0 + ni) x columns [b0 + j0, b0 + j0 + nc) += the
@@ -776,6 +779,7 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
     };
     HPLX_PROPAGATE(launch_fill_u64(dinfo, 1, ULLONG_MAX, st));
     HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)leaf_done, 1, 0ull, st));
+    HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)mx, 2, 0ull, st));
     HPLX_PROPAGATE(launch_cvt_f64_f32(A, lda, LU, ldlu, n, n, st));
     HPLX_PROPAGATE(fact(0, nb < n ? nb : n, st));
     int cur = 0;

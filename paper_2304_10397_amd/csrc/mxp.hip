@@ -297,38 +297,30 @@ __global__ __launch_bounds__(256) void sgemm32_kernel(int64_t m, int64_t n, int6
 }
 
 // ---------------------------------------------------------------------------
-// scaling: max |x| of a column-major block into *mx (non-negative floats order
-// as their bit patterns), then the exponent s = round((e_U - e_L) / 2) of the
-// maxima's binary exponents, written to *sexp.
+// scaling: max |x| of L21 (m x w at ldl) into mx[0] and of U12 (w x n at ldu)
+// into mx[1] (non-negative floats order as their bit patterns), in one launch:
+// blocks [0, gl) walk L21, the rest U12, each grid-stride over its part.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void maxabs32_kernel(const float *__restrict__ M, int64_t ld, int64_t rows,
-                                                       int64_t cols, unsigned *__restrict__ mx)
+__global__ __launch_bounds__(256) void maxabs_lu_kernel(const float *__restrict__ L, int64_t ldl, int64_t m, int64_t w,
+                                                        const float *__restrict__ U, int64_t ldu, int64_t n,
+                                                        unsigned *__restrict__ mx, int gl)
 {
     __shared__ float sh[4];
+    const bool lpart = (int)blockIdx.x < gl;
+    const float *M = lpart ? L : U;
+    const int64_t ld = lpart ? ldl : ldu, rows = lpart ? m : w, cols = lpart ? w : n;
+    const int64_t b0 = lpart ? blockIdx.x : blockIdx.x - gl, nb = lpart ? gl : gridDim.x - gl;
     float v = 0.0f;
-    const int64_t total = rows * cols, stride = (int64_t)gridDim.x * 256;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += stride) {
+    const int64_t total = rows * cols, stride = nb * 256;
+    for (int64_t e = b0 * 256 + threadIdx.x; e < total; e += stride) {
         const int64_t j = e / rows, i = e - j * rows;  // consecutive threads walk down a column
         v = fmaxf(v, fabsf(M[off(i, j, ld)]));
     }
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) atomicMax(mx, __float_as_uint(fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]))));
-}
-
-__global__ void scale_exp_kernel(const unsigned *__restrict__ mx, int *__restrict__ sexp)
-{
-    const float lmax = __uint_as_float(mx[0]), umax = __uint_as_float(mx[1]);
-    int s = 0;
-    if (lmax > 0.0f && umax > 0.0f) {
-        int el, eu;
-        frexpf(lmax, &el);
-        frexpf(umax, &eu);
-        const int d = eu - el;
-        s = d >= 0 ? (d + 1) / 2 : -((-d + 1) / 2);
-    }
-    *sexp = s;
+    if (threadIdx.x == 0)
+        atomicMax(mx + (lpart ? 0 : 1), __float_as_uint(fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]))));
 }
 
 template <int FMT> struct Half;
@@ -349,44 +341,65 @@ __device__ __forceinline__ size_t blk_index(int64_t i, int64_t k, int64_t ss)
     return (size_t)(k >> 5) * (size_t)ss + (size_t)(i >> 4) * 512 + (size_t)((i & 15) * 32 + (k & 31));
 }
 
-// L21 (m x w at ld) -> A16 (blocked, slab stride ss): -(2^s l) rounded.
-// A 64 x 64 tile goes through LDS: read down the columns, written along rows.
-template <int FMT>
-__global__ __launch_bounds__(256) void cvt_l_kernel(const float *__restrict__ L, int64_t ld, int64_t m, int w,
-                                                    const int *__restrict__ sexp, typename Half<FMT>::T *__restrict__ O,
-                                                    int64_t ss)
+// The scaling exponent of a panel from the maxima of |L21| and |U12| (bit
+// patterns of non-negative floats in mx[0], mx[1]): s = round((e_U - e_L) / 2)
+// of their binary exponents, ties away from zero; 0 if either is zero.
+__device__ __forceinline__ int mxp_scale_exp(const unsigned *mx)
 {
-    __shared__ float tile[64][65];
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const int k0 = blockIdx.y * 64;
-    const int s = *sexp;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int r = e % 64, q = e / 64;
-        tile[r][q] = (i0 + r < m && k0 + q < w) ? L[off(i0 + r, k0 + q, ld)] : 0.0f;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int q = e % 64, r = e / 64;
-        if (i0 + r < m && k0 + q < w)
-            O[blk_index(i0 + r, k0 + q, ss)] = (typename Half<FMT>::T)(-ldexpf(tile[r][q], s));
-    }
+    const float lmax = __uint_as_float(mx[0]), umax = __uint_as_float(mx[1]);
+    if (!(lmax > 0.0f && umax > 0.0f)) return 0;
+    int el, eu;
+    frexpf(lmax, &el);
+    frexpf(umax, &eu);
+    const int d = eu - el;
+    return d >= 0 ? (d + 1) / 2 : -((-d + 1) / 2);
 }
 
-// U12 (w x n at ld) -> B16 (blocked, slab stride ss; row j of B16 is column j
-// of U12): 2^-s u rounded.  Each 512 consecutive threads fill one block: reads
-// of 32 consecutive k of a column, the block written whole.
+// One launch for both copies of a panel, the scaling exponent computed from
+// the maxima by every workgroup:
+//  * blocks [0, gl gk): L21 (m x w at ldl) -> A16 (blocked, slab stride sa),
+//    -(2^s l) rounded; a 64 x 64 tile goes through LDS: read down the
+//    columns, written along rows;
+//  * the rest: U12 (w x n at ldu) -> B16 (blocked, slab stride sb; row j of
+//    B16 is column j of U12), 2^-s u rounded; each 512 consecutive threads
+//    fill one block: reads of 32 consecutive k of a column, the block written
+//    whole.
+// Block 0 also clears the other pair of maxima (reset), which the next panel's
+// maxima accumulate into.
 template <int FMT>
-__global__ __launch_bounds__(256) void cvt_u_kernel(const float *__restrict__ U, int64_t ld, int w, int64_t n,
-                                                    const int *__restrict__ sexp, typename Half<FMT>::T *__restrict__ O,
-                                                    int64_t ss)
+__global__ __launch_bounds__(256) void cvt_lu_kernel(const float *__restrict__ L, int64_t ldl, int64_t m, int w,
+                                                     const float *__restrict__ U, int64_t ldu, int64_t n,
+                                                     const unsigned *__restrict__ mx, unsigned *__restrict__ reset,
+                                                     typename Half<FMT>::T *__restrict__ A16, int64_t sa,
+                                                     typename Half<FMT>::T *__restrict__ B16, int64_t sb, int64_t gl,
+                                                     int64_t gk)
 {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    typedef typename Half<FMT>::T H;
+    __shared__ float tile[64][65];
+    const int s = mxp_scale_exp(mx);
+    if (blockIdx.x == 0 && threadIdx.x < 2) reset[threadIdx.x] = 0u;
+    const int64_t b = blockIdx.x;
+    if (b < gl * gk) {
+        const int64_t i0 = (b % gl) * 64;
+        const int k0 = (int)(b / gl) * 64;
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int r = e % 64, q = e / 64;
+            tile[r][q] = (i0 + r < m && k0 + q < w) ? L[off(i0 + r, k0 + q, ldl)] : 0.0f;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int q = e % 64, r = e / 64;
+            if (i0 + r < m && k0 + q < w) A16[blk_index(i0 + r, k0 + q, sa)] = (H)(-ldexpf(tile[r][q], s));
+        }
+        return;
+    }
+    const int64_t e = (b - gl * gk) * 256 + threadIdx.x;
     const int64_t nbj = (n + 15) / 16;  // 16-column groups
     const int64_t blk = e >> 9, kb = blk / nbj, jb = blk - kb * nbj;
     const int within = (int)(e & 511);
     const int64_t j = jb * 16 + (within >> 5), k = kb * 32 + (within & 31);
     if (kb * 32 >= w || j >= n || k >= w) return;
-    O[(size_t)kb * (size_t)ss + (size_t)jb * 512 + within] = (typename Half<FMT>::T)ldexpf(U[off(k, j, ld)], -*sexp);
+    B16[(size_t)kb * (size_t)sb + (size_t)jb * 512 + within] = (H)ldexpf(U[off(k, j, ldu)], -s);
 }
 
 // ---------------------------------------------------------------------------
@@ -843,42 +856,33 @@ int launch_sgemm32(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
     return HPL_OK;
 }
 
-int launch_mxp_scale(const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols, int w,
-                     unsigned *mx, int *sexp, hipStream_t st)
+int launch_mxp_maxabs(const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols, int w,
+                      unsigned *mx, hipStream_t st)
 {
-    HPLX_PROPAGATE(launch_fill_u64((unsigned long long *)mx, 1, 0ull, st));
-    const int64_t gl = blocks_of(m * w, 256 * 16), gu = blocks_of((int64_t)w * ncols, 256 * 16);
-    hipLaunchKernelGGL(maxabs32_kernel, dim3((unsigned)(gl < 2048 ? gl : 2048)), dim3(256), 0, st, L, ldl, m,
-                       (int64_t)w, mx);
-    HPLX_TRY_LAUNCH();
-    hipLaunchKernelGGL(maxabs32_kernel, dim3((unsigned)(gu < 2048 ? gu : 2048)), dim3(256), 0, st, U, ldu,
-                       (int64_t)w, ncols, mx + 1);
-    HPLX_TRY_LAUNCH();
-    hipLaunchKernelGGL(scale_exp_kernel, dim3(1), dim3(1), 0, st, mx, sexp);
+    int64_t gl = blocks_of(m * w, 256 * 16), gu = blocks_of((int64_t)w * ncols, 256 * 16);
+    gl = gl < 1 ? 1 : (gl > 2048 ? 2048 : gl);
+    gu = gu < 1 ? 1 : (gu > 2048 ? 2048 : gu);
+    hipLaunchKernelGGL(maxabs_lu_kernel, dim3((unsigned)(gl + gu)), dim3(256), 0, st, L, ldl, m, (int64_t)w, U, ldu,
+                       ncols, mx, (int)gl);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
 
 int launch_mxp_convert(int fmt, const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols,
-                       int w, const int *sexp, void *A16, int64_t sa, void *B16, int64_t sb, hipStream_t st)
+                       int w, const unsigned *mx, unsigned *reset, void *A16, int64_t sa, void *B16, int64_t sb,
+                       hipStream_t st)
 {
     if (w % 32 || sa % 512 || sb % 512) return HPL_ERR_INTERNAL;
     const int64_t gl = blocks_of(m, 64), gk = blocks_of(w, 64);
     const int64_t gu = blocks_of((int64_t)(w / 32) * blocks_of(ncols, 16) * 512, 256);
-    if (gu > 0x7fffffffll || gl > 0x7fffffffll) return HPL_ERR_INTERNAL;
-    if (fmt == 0) {
-        hipLaunchKernelGGL(cvt_l_kernel<0>, dim3((unsigned)gl, (unsigned)gk), dim3(256), 0, st, L, ldl, m, w, sexp,
-                           (_Float16 *)A16, sa);
-        HPLX_TRY_LAUNCH();
-        hipLaunchKernelGGL(cvt_u_kernel<0>, dim3((unsigned)gu), dim3(256), 0, st, U, ldu, w, ncols, sexp,
-                           (_Float16 *)B16, sb);
-    } else {
-        hipLaunchKernelGGL(cvt_l_kernel<1>, dim3((unsigned)gl, (unsigned)gk), dim3(256), 0, st, L, ldl, m, w, sexp,
-                           (__bf16 *)A16, sa);
-        HPLX_TRY_LAUNCH();
-        hipLaunchKernelGGL(cvt_u_kernel<1>, dim3((unsigned)gu), dim3(256), 0, st, U, ldu, w, ncols, sexp,
-                           (__bf16 *)B16, sb);
-    }
+    const int64_t g = gl * gk + gu;
+    if (g < 1 || g > 0x7fffffffll) return HPL_ERR_INTERNAL;
+    if (fmt == 0)
+        hipLaunchKernelGGL(cvt_lu_kernel<0>, dim3((unsigned)g), dim3(256), 0, st, L, ldl, m, w, U, ldu, ncols, mx,
+                           reset, (_Float16 *)A16, sa, (_Float16 *)B16, sb, gl, gk);
+    else
+        hipLaunchKernelGGL(cvt_lu_kernel<1>, dim3((unsigned)g), dim3(256), 0, st, L, ldl, m, w, U, ldu, ncols, mx,
+                           reset, (__bf16 *)A16, sa, (__bf16 *)B16, sb, gl, gk);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
