@@ -151,6 +151,21 @@ def test_mxp_refinement_reaches_fp64(n, nb, fmt):
     assert err <= 1e-10
 
 
+def test_mxp_solve_sizes_up_and_down():
+    """The refinement keeps its vectors and counters in a workspace that later
+    calls reuse: a call on a smaller system after a larger one, and a larger
+    one again, must each reach the residual test."""
+    h = hpl()
+    for n, fmt in ((1500, 0), (300, 1), (700, 0), (1500, 1)):
+        A, b = gpu_mxp_system(n, 21)
+        LU, info = h.hpl_mxp_factor(A, nb=128, fmt=fmt)
+        assert info == 0
+        x, out = h.hpl_mxp_solve(A, LU, b, max_iter=50)
+        assert out[1] < 16.0, (n, fmt, out)
+        res = oracle.residual(oracle.mxp_gen(21, n), x.cpu().numpy(), oracle.gen(21, 1, n, 1)[:, 0].copy())
+        assert res[0] < 16.0
+
+
 def test_mxp_zero_refinements_allowed():
     h = hpl()
     A, b = gpu_mxp_system(300, 3)
