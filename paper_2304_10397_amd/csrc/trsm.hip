@@ -205,6 +205,9 @@ __global__ __launch_bounds__(256) void trsm_small_kernel(const T *__restrict__ L
         const int buf = ch & 1;
         if (ch + 1 < nchunk) fetch(ch + 1);
         const int kend = (nbk - ch * kSmChunk) < kSmChunk ? (nbk - ch * kSmChunk) : kSmChunk;
+        // the step's L entries are read unconditionally and the update is a
+        // select, so that the LDS reads of the next steps can be issued ahead
+#pragma unroll 4
         for (int kk = 0; kk < kend; ++kk) {
             const int k = ch * kSmChunk + kk;
             const int sk = k >> 6, lk = k & 63;
@@ -216,7 +219,8 @@ __global__ __launch_bounds__(256) void trsm_small_kernel(const T *__restrict__ L
 #pragma unroll
             for (int s = 0; s < kSmRPL; ++s) {
                 const int r = lane + 64 * s;
-                if (r > k) x[s] = __fma_rn(-Lc[buf][kk][r], xk, x[s]);
+                const T y = __fma_rn(-Lc[buf][kk][r], xk, x[s]);
+                x[s] = r > k ? y : x[s];
             }
         }
         if (ch + 1 < nchunk) stash(buf ^ 1);
