@@ -106,11 +106,12 @@ __global__ __launch_bounds__(256) void panel32_leaf_kernel(float *__restrict__ A
             const float ukk = P[k & 1][k];
             if (t == 0 && ukk == 0.0f && first_zero == 0) first_zero = (unsigned)k + 1;
             // rows below k: the diagonal block's rows t > k and every row below it
+            // slots past w hold copies of column 0 and published values that
+            // are never stored: they are updated without a test per slot
             if ((!diag || t > k) && ukk != 0.0f) {
                 x[k] = x[k] / ukk;
 #pragma unroll
-                for (int q = k + 1; q < kLw; ++q)
-                    if (q < w) x[q] = x[q] - x[k] * P[k & 1][q];
+                for (int q = k + 1; q < kLw; ++q) x[q] = x[q] - x[k] * P[k & 1][q];
             }
         }
     }
