@@ -195,7 +195,7 @@ int launch_trsm_llnu(const double *L, int64_t ldl, double *B, int64_t ldb, int64
 // mixed-precision factorization: nbk <= 512, ncols <= 4096.
 bool trsm32_small_ok(int64_t nbk, int64_t ncols);
 int launch_trsm32_small(const float *L, int64_t ldl, float *B, int64_t ldb, int64_t nbk, int64_t ncols,
-                        hipStream_t st);
+                        hipStream_t st, unsigned *mx = nullptr);
 
 // laswp.hip
 // Interchanges k = 0..cnt-1: row r0+k <-> ipiv[k] (global rows, ipiv[k] >= r0+k),
@@ -288,15 +288,14 @@ int launch_cvt_f64_f32(const double *A, int64_t lda, float *B, int64_t ldb, int6
                        hipStream_t st);
 // widest FP32 panel leaf and triangular-solve leaf (one launch each)
 constexpr int kPanel32LeafMax = 64, kTrsm32LeafMax = 64;
+// With mx, the FP32 leaves fold the largest |value| they store into *mx (the
+// panel leaf: rows from l21_row0 on, i.e. L21; the solve leaves: all of it).
 int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsigned long long *info,
-                        unsigned *done, hipStream_t st);
-int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st);
+                        unsigned *done, hipStream_t st, unsigned *mx = nullptr, int64_t l21_row0 = 0);
+int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st,
+                       unsigned *mx = nullptr);
 int launch_sgemm32(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B, int64_t ldb,
                    float *C, int64_t ldc, hipStream_t st);
-// max |L21| and max |U12| of a panel into mx[0], mx[1] (accumulated: the pair
-// must start at zero).
-int launch_mxp_maxabs(const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols, int w,
-                      unsigned *mx, hipStream_t st);
 // -L21 and U12 scaled (the exponent from mx) and rounded into the blocked
 // low-precision layout (1 KB blocks of 16 rows x 32 k, ordered by k slab then
 // 16-row group; sa, sb = slab strides in elements, multiples of 512; A16 and

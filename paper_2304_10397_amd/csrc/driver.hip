@@ -644,33 +644,38 @@ static int ensure_mxp_ws(Device *d, size_t bytes)
     return HPL_OK;
 }
 
-// B (nbk x ncols) <- L^{-1} B, L unit lower (FP32): 32-row leaves joined by GEMMs.
-static int mxp_trsm(const float *L, int64_t ldl, int64_t nbk, float *B, int64_t ldb, int64_t ncols, hipStream_t st)
+// B (nbk x ncols) <- L^{-1} B, L unit lower (FP32): 64-row leaves joined by
+// GEMMs.  With mx, the largest |value| of the solution is folded into *mx (by
+// the leaves, which store final values).
+static int mxp_trsm(const float *L, int64_t ldl, int64_t nbk, float *B, int64_t ldb, int64_t ncols, hipStream_t st,
+                    unsigned *mx = nullptr)
 {
     if (nbk <= 0 || ncols <= 0) return HPL_OK;
-    if (nbk <= kTrsm32LeafMax) return launch_trsm32_leaf(L, ldl, B, ldb, (int)nbk, ncols, st);
+    if (nbk <= kTrsm32LeafMax) return launch_trsm32_leaf(L, ldl, B, ldb, (int)nbk, ncols, st, mx);
     // the panel's own solves (few columns): one launch instead of a recursion
     // of leaves and GEMMs
-    if (trsm32_small_ok(nbk, ncols)) return launch_trsm32_small(L, ldl, B, ldb, nbk, ncols, st);
+    if (trsm32_small_ok(nbk, ncols)) return launch_trsm32_small(L, ldl, B, ldb, nbk, ncols, st, mx);
     const int64_t h = ((nbk / 2 + 31) / 32) * 32;
-    HPLX_PROPAGATE(mxp_trsm(L, ldl, h, B, ldb, ncols, st));
+    HPLX_PROPAGATE(mxp_trsm(L, ldl, h, B, ldb, ncols, st, mx));
     HPLX_PROPAGATE(launch_sgemm32(nbk - h, ncols, h, L + h, ldl, B, ldb, B + h, ldb, st));
-    return mxp_trsm(L + off(h, h, ldl), ldl, nbk - h, B + h, ldb, ncols, st);
+    return mxp_trsm(L + off(h, h, ldl), ldl, nbk - h, B + h, ldb, ncols, st, mx);
 }
 
 // FACT of columns [c, c+w), rows [c, n), no pivoting, FP32: recursive halves.
+// With mx, the largest |l| of the rows from l21_row0 on is folded into *mx
+// (by the leaves, which store final values).
 static int mxp_panel(float *A, int64_t lda, int64_t n, int64_t c, int64_t w, unsigned long long *info, unsigned *done,
-                     hipStream_t st)
+                     hipStream_t st, unsigned *mx = nullptr, int64_t l21_row0 = 0)
 {
-    if (w <= kPanel32LeafMax) return launch_panel32_leaf(A, lda, c, n, (int)w, info, done, st);
+    if (w <= kPanel32LeafMax) return launch_panel32_leaf(A, lda, c, n, (int)w, info, done, st, mx, l21_row0);
     int64_t w1 = ((w / 2 + 31) / 32) * 32;
     if (w1 >= w) w1 = w - 1;
     const int64_t w2 = w - w1;
-    HPLX_PROPAGATE(mxp_panel(A, lda, n, c, w1, info, done, st));
+    HPLX_PROPAGATE(mxp_panel(A, lda, n, c, w1, info, done, st, mx, l21_row0));
     HPLX_PROPAGATE(mxp_trsm(A + off(c, c, lda), lda, w1, A + off(c, c + w1, lda), lda, w2, st));
     HPLX_PROPAGATE(launch_sgemm32(n - c - w1, w2, w1, A + off(c + w1, c, lda), lda, A + off(c, c + w1, lda), lda,
                                   A + off(c + w1, c + w1, lda), lda, st));
-    return mxp_panel(A, lda, n, c + w1, w2, info, done, st);
+    return mxp_panel(A, lda, n, c + w1, w2, info, done, st, mx, l21_row0);
 }
 
 // The mixed-precision factorization takes the panels in groups of G (G nb =
@@ -724,10 +729,11 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
     unsigned *leaf_done = (unsigned *)(ws + sc_off + 64);  // panel leaf's workgroup count (returns to zero)
     hipStream_t sp = la ? d->sp : st;
     Timer tm(d, opt_timing.load() != 0);
-    // FACT of the panel at c (width w), on stream s
+    // FACT of the panel at c (width w), on stream s; its leaves fold max |L21|
+    // into the pair of maxima its conversion will use
     auto fact = [&](int64_t c, int64_t w, hipStream_t s) -> int {
         const int id = tm.begin(ST_MXP_FACT, s);
-        HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c, w, dinfo, leaf_done, s));
+        HPLX_PROPAGATE(mxp_panel(LU, ldlu, n, c, w, dinfo, leaf_done, s, mx + 2 * (prep_count & 1), c + w));
         return tm.end(id, s, (double)(n - c) * (double)w * (double)w, 4.0 * (double)(n - c) * (double)w * 2.0);
     };
     // U12 of the panel at c (width nb) and the low-precision copies of -L21 and
@@ -736,10 +742,11 @@ static int mxp_factor_impl(Device *d, const double *A, int64_t n, int64_t lda, i
         const int64_t c1 = c + nb, m = n - c1;
         const size_t o = (size_t)i * (size_t)(nb / 32) * (size_t)ss + (size_t)(idx / 16) * 512;
         const int id = tm.begin(ST_MXP_FACT, s);
-        HPLX_PROPAGATE(mxp_trsm(LU + off(c, c, ldlu), ldlu, nb, LU + off(c, c1, ldlu), ldlu, m, s));
+        // max |U12| folded into pm[1] by the solve's leaves (max |L21| is in
+        // pm[0] from the panel's FACT)
         unsigned *pm = mx + 2 * (prep_count & 1), *other = mx + 2 * ((prep_count + 1) & 1);
         ++prep_count;
-        HPLX_PROPAGATE(launch_mxp_maxabs(LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)nb, pm, s));
+        HPLX_PROPAGATE(mxp_trsm(LU + off(c, c, ldlu), ldlu, nb, LU + off(c, c1, ldlu), ldlu, m, s, pm + 1));
         HPLX_PROPAGATE(launch_mxp_convert(fmt, LU + off(c1, c, ldlu), ldlu, m, LU + off(c, c1, ldlu), ldlu, m, (int)nb,
                                           pm, other, A16[q] + o, ss, B16[q] + o, ss, s));
         return tm.end(id, s, (double)nb * (double)nb * (double)m, 4.0 * (double)nb * (double)m * 2.0);

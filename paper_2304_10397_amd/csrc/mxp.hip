@@ -75,13 +75,32 @@ __global__ __launch_bounds__(256) void cvt_f64_f32_kernel(const double *__restri
 // final row k of U) to a double-buffered LDS row, so one barrier per step
 // suffices.  Every workgroup reads the diagonal block as input, so it is
 // written back only by the last workgroup to finish (counted on *done, which
-// wraps to zero at the end of each launch).
+// wraps to zero at the end of each launch).  With mx, the largest |l| of the
+// rows from l21_row0 on (the panel's L21) is folded into *mx (the bit pattern
+// of a non-negative float), one atomicMax per workgroup.
 // ---------------------------------------------------------------------------
+// largest v over the workgroup into *mx (non-negative floats order as their bit
+// patterns); red holds one float per wave
+__device__ __forceinline__ void block_max_to(float v, unsigned *mx, float *red)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    const int nw = (int)(blockDim.x >> 6);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = red[0];
+        for (int q = 1; q < nw; ++q) m = fmaxf(m, red[q]);
+        atomicMax(mx, __float_as_uint(m));
+    }
+}
+
 template <int LW>
 __global__ __launch_bounds__(256) void panel32_leaf_kernel(float *__restrict__ A, int64_t lda, int64_t c,
                                                            int64_t n, int w, unsigned long long *__restrict__ info,
-                                                           unsigned *__restrict__ done)
+                                                           unsigned *__restrict__ done, unsigned *__restrict__ mx,
+                                                           int64_t l21_row0)
 {
+    __shared__ float red[4];
     constexpr int kLw = LW, kLeafRows = 256 - LW;
     __shared__ float P[2][kLw];
     __shared__ int last;
@@ -128,11 +147,21 @@ __global__ __launch_bounds__(256) void panel32_leaf_kernel(float *__restrict__ A
         for (int j = 0; j < kLw; ++j)
             if (j < w) A[off(i, c + j, lda)] = x[j];
     }
+    if (mx) {  // uniform
+        float am = 0.0f;
+        if (live && !diag && i >= l21_row0) {
+#pragma unroll
+            for (int j = 0; j < kLw; ++j)
+                if (j < w) am = fmaxf(am, fabsf(x[j]));
+        }
+        block_max_to(am, mx, red);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // FP32 triangular-solve leaf: B (nbk x ncols, nbk <= TL = 32 or 64) <- L^{-1} B
-// with L unit lower.  A workgroup of 128 threads takes 128 columns: the TL x 128 block
+// with L unit lower; with mx, the largest |x| of the solution is folded into
+// *mx.  A workgroup of 128 threads takes 128 columns: the TL x 128 block
 // moves between B and LDS with coalesced accesses (16-byte vectors when every
 // column starts 16-byte aligned, else 32 lanes per column), then each thread
 // solves its column in registers, right-looking: at step k every row i > k
@@ -144,8 +173,9 @@ constexpr int kTlCols = 128, kTlPad = 4;
 template <int TL, bool VEC>
 __global__ __launch_bounds__(kTlCols) void trsm32_leaf_kernel(const float *__restrict__ L, int64_t ldl,
                                                               float *__restrict__ B, int64_t ldb, int nbk,
-                                                              int64_t ncols)
+                                                              int64_t ncols, unsigned *__restrict__ mx)
 {
+    __shared__ float red[kTlCols / 64];
     constexpr int kTl = TL;
     typedef float f4 __attribute__((ext_vector_type(4)));
     __shared__ __attribute__((aligned(16))) float Lt[kTl][kTl + kTlPad];            // Lt[k][i] = l_ik
@@ -211,6 +241,15 @@ __global__ __launch_bounds__(kTlCols) void trsm32_leaf_kernel(const float *__res
     }
 #pragma unroll
     for (int i4 = 0; i4 < kTl; i4 += 4) *(f4 *)&Xs[t][i4] = (f4){x[i4], x[i4 + 1], x[i4 + 2], x[i4 + 3]};
+    if (mx) {  // uniform
+        float am = 0.0f;
+        if (j0 + t < ncols) {
+#pragma unroll
+            for (int i = 0; i < kTl; ++i)
+                if (i < nbk) am = fmaxf(am, fabsf(x[i]));
+        }
+        block_max_to(am, mx, red);  // includes the barrier before the stores below
+    }
     __syncthreads();
     if (VEC) {
 #pragma unroll
@@ -295,33 +334,6 @@ __global__ __launch_bounds__(256) void sgemm32_kernel(int64_t m, int64_t n, int6
             const int64_t i = m0 + tx + 16 * u, j = n0 + ty + 16 * v;
             if (i < m && j < n) C[off(i, j, ldc)] = cv[u][v] - acc[u][v];
         }
-}
-
-// ---------------------------------------------------------------------------
-// scaling: max |x| of L21 (m x w at ldl) into mx[0] and of U12 (w x n at ldu)
-// into mx[1] (non-negative floats order as their bit patterns), in one launch:
-// blocks [0, gl) walk L21, the rest U12, each grid-stride over its part.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void maxabs_lu_kernel(const float *__restrict__ L, int64_t ldl, int64_t m, int64_t w,
-                                                        const float *__restrict__ U, int64_t ldu, int64_t n,
-                                                        unsigned *__restrict__ mx, int gl)
-{
-    __shared__ float sh[4];
-    const bool lpart = (int)blockIdx.x < gl;
-    const float *M = lpart ? L : U;
-    const int64_t ld = lpart ? ldl : ldu, rows = lpart ? m : w, cols = lpart ? w : n;
-    const int64_t b0 = lpart ? blockIdx.x : blockIdx.x - gl, nb = lpart ? gl : gridDim.x - gl;
-    float v = 0.0f;
-    const int64_t total = rows * cols, stride = nb * 256;
-    for (int64_t e = b0 * 256 + threadIdx.x; e < total; e += stride) {
-        const int64_t j = e / rows, i = e - j * rows;  // consecutive threads walk down a column
-        v = fmaxf(v, fabsf(M[off(i, j, ld)]));
-    }
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        atomicMax(mx + (lpart ? 0 : 1), __float_as_uint(fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]))));
 }
 
 template <int FMT> struct Half;
@@ -803,7 +815,7 @@ int launch_cvt_f64_f32(const double *A, int64_t lda, float *B, int64_t ldb, int6
 }
 
 int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsigned long long *info,
-                        unsigned *done, hipStream_t st)
+                        unsigned *done, hipStream_t st, unsigned *mx, int64_t l21_row0)
 {
     if (w <= 0 || w > kPanel32LeafMax) return HPL_ERR_INTERNAL;
     const int64_t below = n - c - w;
@@ -811,14 +823,17 @@ int launch_panel32_leaf(float *A, int64_t lda, int64_t c, int64_t n, int w, unsi
     const int64_t g = below > 0 ? blocks_of(below, 256 - lw) : 1;
     if (g > 0xffffffffll) return HPL_ERR_INTERNAL;
     if (lw == 32)
-        hipLaunchKernelGGL(panel32_leaf_kernel<32>, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info, done);
+        hipLaunchKernelGGL(panel32_leaf_kernel<32>, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info, done,
+                           mx, l21_row0);
     else
-        hipLaunchKernelGGL(panel32_leaf_kernel<64>, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info, done);
+        hipLaunchKernelGGL(panel32_leaf_kernel<64>, dim3((unsigned)g), dim3(256), 0, st, A, lda, c, n, w, info, done,
+                           mx, l21_row0);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
 
-int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st)
+int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int nbk, int64_t ncols, hipStream_t st,
+                       unsigned *mx)
 {
     if (ncols <= 0 || nbk <= 0) return HPL_OK;
     if (nbk > kTrsm32LeafMax) return HPL_ERR_INTERNAL;
@@ -829,17 +844,17 @@ int launch_trsm32_leaf(const float *L, int64_t ldl, float *B, int64_t ldb, int n
     if (nbk <= 32) {
         if (nbk == 32 && al)
             hipLaunchKernelGGL((trsm32_leaf_kernel<32, true>), dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B, ldb,
-                               nbk, ncols);
+                               nbk, ncols, mx);
         else
             hipLaunchKernelGGL((trsm32_leaf_kernel<32, false>), dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B,
-                               ldb, nbk, ncols);
+                               ldb, nbk, ncols, mx);
     } else {
         if (nbk == 64 && al)
             hipLaunchKernelGGL((trsm32_leaf_kernel<64, true>), dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B, ldb,
-                               nbk, ncols);
+                               nbk, ncols, mx);
         else
             hipLaunchKernelGGL((trsm32_leaf_kernel<64, false>), dim3((unsigned)g), dim3(kTlCols), 0, st, L, ldl, B,
-                               ldb, nbk, ncols);
+                               ldb, nbk, ncols, mx);
     }
     HPLX_TRY_LAUNCH();
     return HPL_OK;
@@ -853,18 +868,6 @@ int launch_sgemm32(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
     if (gy > 65535) return HPL_ERR_INTERNAL;
     hipLaunchKernelGGL(sgemm32_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, m, n, k, A, lda, B, ldb,
                        C, ldc);
-    HPLX_TRY_LAUNCH();
-    return HPL_OK;
-}
-
-int launch_mxp_maxabs(const float *L, int64_t ldl, int64_t m, const float *U, int64_t ldu, int64_t ncols, int w,
-                      unsigned *mx, hipStream_t st)
-{
-    int64_t gl = blocks_of(m * w, 256 * 16), gu = blocks_of((int64_t)w * ncols, 256 * 16);
-    gl = gl < 1 ? 1 : (gl > 2048 ? 2048 : gl);
-    gu = gu < 1 ? 1 : (gu > 2048 ? 2048 : gu);
-    hipLaunchKernelGGL(maxabs_lu_kernel, dim3((unsigned)(gl + gu)), dim3(256), 0, st, L, ldl, m, (int64_t)w, U, ldu,
-                       ncols, mx, (int)gl);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }

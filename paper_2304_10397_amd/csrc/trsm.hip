@@ -166,10 +166,13 @@ __device__ __forceinline__ float lane_value(float v, int l)
 constexpr int kSmRPL = 4;    // rows per lane of the FP64 form (nbk <= 256)
 constexpr int kSmRPL32 = 8;  // rows per lane of the FP32 form (nbk <= 512)
 constexpr int kSmChunk = 16; // columns of L per LDS stage
+// (FP32 only: with mx, the largest |x| of the solution is folded into *mx, the
+// bit pattern of a non-negative float.)
 template <typename T, int kSmRPL>
 __global__ __launch_bounds__(256) void trsm_small_kernel(const T *__restrict__ L, int64_t ldl, T *__restrict__ B,
-                                                         int64_t ldb, int nbk, int64_t ncols)
+                                                         int64_t ldb, int nbk, int64_t ncols, unsigned *__restrict__ mx)
 {
+    __shared__ float red[4];
     __shared__ T Lc[2][kSmChunk][64 * kSmRPL + 1];  // Lc[buf][kk][r] = L(r, chunk*16 + kk)
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t col = (int64_t)blockIdx.x * 4 + wave;
@@ -233,6 +236,20 @@ __global__ __launch_bounds__(256) void trsm_small_kernel(const T *__restrict__ L
             if (r < nbk) B[off(r, col, ldb)] = x[s];
         }
     }
+    if constexpr (sizeof(T) == 4) {
+        if (mx) {  // uniform
+            float am = 0.0f;
+            if (live) {
+#pragma unroll
+                for (int s = 0; s < kSmRPL; ++s)
+                    if (lane + 64 * s < nbk) am = fmaxf(am, fabsf((float)x[s]));
+            }
+            for (int o = 32; o > 0; o >>= 1) am = fmaxf(am, __shfl_xor(am, o, 64));
+            if (lane == 0) red[wave] = am;
+            __syncthreads();
+            if (t == 0) atomicMax(mx, __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))));
+        }
+    }
 }
 
 }  // namespace
@@ -244,7 +261,7 @@ int launch_trsm_llnu(const double *L, int64_t ldl, double *B, int64_t ldb, int64
     if (nbk <= 64 * kSmRPL && ncols <= 4096) {
         const int64_t g = (ncols + 3) / 4;
         hipLaunchKernelGGL((trsm_small_kernel<double, kSmRPL>), dim3((unsigned)g), dim3(256), 0, st, L, ldl, B, ldb,
-                           (int)nbk, ncols);
+                           (int)nbk, ncols, nullptr);
         HPLX_TRY_LAUNCH();
         return HPL_OK;
     }
@@ -263,13 +280,13 @@ bool trsm32_small_ok(int64_t nbk, int64_t ncols)
 }
 
 int launch_trsm32_small(const float *L, int64_t ldl, float *B, int64_t ldb, int64_t nbk, int64_t ncols,
-                        hipStream_t st)
+                        hipStream_t st, unsigned *mx)
 {
     if (nbk <= 0 || ncols <= 0) return HPL_OK;
     if (!trsm32_small_ok(nbk, ncols)) return HPL_ERR_INTERNAL;
     const int64_t g = (ncols + 3) / 4;
     hipLaunchKernelGGL((trsm_small_kernel<float, kSmRPL32>), dim3((unsigned)g), dim3(256), 0, st, L, ldl, B, ldb,
-                       (int)nbk, ncols);
+                       (int)nbk, ncols, mx);
     HPLX_TRY_LAUNCH();
     return HPL_OK;
 }
