@@ -44,8 +44,8 @@ PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X, FP64 vector (256 CUs x 128 flop/clk x 2
 # HBM bytes per trailing-GEMM launch measured with rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 2048 MiB copy: x2.000 and x1.000) at the default
 # workload, valid only for the GEMM source with this SHA-256 prefix.
-MEASURED_TRAFFIC = {"gemm_sha256_16": "87004d1e525164c4", "n": 163840, "nb": 512, "form": "augmented",
-                    "fetch_gb": 138.35, "write_gb": 35.74}
+MEASURED_TRAFFIC = {"gemm_sha256_16": "e73c0f582a69228e", "n": 163840, "nb": 512, "form": "augmented",
+                    "fetch_gb": 96.24, "write_gb": 35.74}
 
 
 def log(msg):
