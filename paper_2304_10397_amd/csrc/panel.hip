@@ -215,7 +215,8 @@ __global__ __launch_bounds__(kLeafThreads) void panel_leaf_kernel(double *__rest
 // tag, so each word validates itself and no ordering between words is needed.
 // Each step costs two short round trips: every workgroup reads the G
 // candidates' keys (one word per thread, polled side by side), picks the pivot
-// locally, then reads only the winner's row and the diagonal row.
+// locally, then reads only the winner's row and the diagonal row (both halves
+// of each value loaded together).
 // Slot of workgroup g: words 0..2 = tagged (row index, |a| low, |a| high),
 // words 3 + 2j, 4 + 2j = tagged halves of the candidate row's value in column
 // k + j.  The diagonal row is published by workgroup 0 in a separate area.
@@ -256,6 +257,27 @@ __device__ __forceinline__ bool get_tagged(const unsigned long long *p, uint32_t
         }
         __builtin_amdgcn_s_sleep(1);
     }
+}
+
+// The two words of one value: both loads are issued before either is tested,
+// so a pair that is already there costs one round trip rather than two; a word
+// that does not carry the tag yet is then polled on its own.  A word loaded
+// early with the current tag holds the current payload (tags are unique per
+// launch and step), so using it is as safe as polling it again.
+__device__ __forceinline__ bool get_tagged_pair(const unsigned long long *p, uint32_t tag, uint32_t &lo,
+                                                uint32_t &hi, int *abort_flag, unsigned long long t0)
+{
+    const unsigned long long v0 = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long v1 = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(v0 >> 32) == tag)
+        lo = (uint32_t)v0;
+    else if (!get_tagged(p, tag, lo, abort_flag, t0))
+        return false;
+    if ((uint32_t)(v1 >> 32) == tag)
+        hi = (uint32_t)v1;
+    else if (!get_tagged(p + 1, tag, hi, abort_flag, t0))
+        return false;
+    return true;
 }
 
 __device__ __forceinline__ double dbl_of(uint32_t lo, uint32_t hi)
@@ -442,8 +464,7 @@ __global__ __launch_bounds__(kRegThreads) void leaf_reg_kernel(double *__restric
                     top ? topw + (size_t)par * 2 * kRegW + 2 * j
                         : slots + ((size_t)par * kLeafMaxWGs + owner) * kLeafSlotWords + 3 + 2 * j;
                 uint32_t lo = 0, hi = 0;
-                if (!get_tagged(src, tag, lo, sync.abort_flag, t0) || !get_tagged(src + 1, tag, hi, sync.abort_flag, t0))
-                    s_abort = 1;
+                if (!get_tagged_pair(src, tag, lo, hi, sync.abort_flag, t0)) s_abort = 1;
                 const double x = dbl_of(lo, hi);
                 if (top) {
                     tr[j] = x;
